@@ -1,0 +1,310 @@
+"""ctypes wrapper of the FP64 CPU oracle (``oracle/darts_ref.c``).
+
+TEST INFRASTRUCTURE. Only the test-suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this module. It shares nothing with
+the GPU library: its own C source, its own structs, its own flag constants and
+its own normalisation helper. Scenes are given as the plain dictionaries that
+``paper_2402_03106_amd.workloads`` produces (values only, no arithmetic).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "darts_ref.c")
+LIB_PATH = os.path.join(HERE, "libdarts_ref.so")
+
+# Strategy bits (same numeric values as the GPU library; declared separately).
+RIS_DIST, EDA_DIR, ELL_TEXP, ELL_UNIFORM, DIRECT_REUSE, FORWARD = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+MODES = {
+    "darts": RIS_DIST | EDA_DIR | ELL_TEXP,
+    "uniform": ELL_UNIFORM,
+    "vanilla": DIRECT_REUSE,
+    "da_only": RIS_DIST | ELL_UNIFORM,
+    "eda_only": EDA_DIR | ELL_TEXP,
+    "texp_only": ELL_TEXP,
+    "forward": FORWARD,
+}
+MUT = {"none": 0, "printed_jacobian": 1, "ris_no_mean": 2, "eda_pdf_unscaled": 3,
+       "no_emitter_trans": 4, "hg_sample_flip": 5}
+STATS = ["paths", "vertices", "connections", "early_exit", "medium_exit", "ris_all_invalid",
+         "eda_branch", "truncated", "zero_paths", "ris_invalid_cands"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no -march=native, strict FP)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               SRC, "-lm", "-o", LIB_PATH + ".tmp"]
+        subprocess.run(cmd, check=True, cwd=HERE)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class _Medium(C.Structure):
+    _fields_ = [("sigma_s", C.c_double), ("sigma_a", C.c_double), ("g", C.c_double)]
+
+
+class _Emitter(C.Structure):
+    _fields_ = [("pos", C.c_double * 3), ("start", C.c_double), ("power", C.c_double)]
+
+
+class _Sensor(C.Structure):
+    _fields_ = [("kind", C.c_int), ("origin", C.c_double * 3), ("dir", C.c_double * 3),
+                ("du", C.c_double * 3), ("dv", C.c_double * 3), ("width", C.c_int), ("height", C.c_int)]
+
+
+class _Geometry(C.Structure):
+    _fields_ = [("kind", C.c_int), ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
+class _Bins(C.Structure):
+    _fields_ = [("l_lo", C.c_double), ("l_hi", C.c_double), ("n_bins", C.c_int)]
+
+
+class _Scene(C.Structure):
+    _fields_ = [("medium", _Medium), ("geom", _Geometry), ("emitters", C.POINTER(_Emitter)),
+                ("n_emitters", C.c_int), ("sensor", _Sensor), ("bins", _Bins)]
+
+
+class _Dims(C.Structure):
+    _fields_ = [("n_cs", C.c_int), ("n_s", C.c_int), ("n_cos", C.c_int), ("s_max", C.c_double)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("n_paths", C.c_uint64), ("path_offset", C.c_uint64), ("seed", C.c_uint64),
+                ("max_bounces", C.c_int), ("n_ris", C.c_int), ("alpha", C.c_double),
+                ("flags", C.c_uint), ("mutation", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        d, pd, u32p = C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_uint32)
+        L.ref_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.ref_u01.restype = d
+        L.ref_u01.argtypes = [C.c_uint32]
+        for name, nargs in [("ref_hg_pdf", 2), ("ref_hg_sample_mu", 2), ("ref_gamma", 2),
+                            ("ref_ell_t", 3)]:
+            f = getattr(L, name)
+            f.restype = d
+            f.argtypes = [d] * nargs
+        L.ref_texp_sample.restype = d
+        L.ref_texp_sample.argtypes = [d, d, d]
+        L.ref_texp_pdf.restype = d
+        L.ref_texp_pdf.argtypes = [d, d, d]
+        L.ref_ell_pdf_t.restype = d
+        L.ref_ell_pdf_t.argtypes = [d, d, d, d, d, C.c_int]
+        L.ref_onb.argtypes = [pd, pd, pd]
+        L.ref_da_D.restype = d
+        L.ref_da_D.argtypes = [C.POINTER(_Medium)]
+        L.ref_da_phi.restype = d
+        L.ref_da_phi.argtypes = [C.POINTER(_Medium), d, d]
+        L.ref_da_log_phi.restype = d
+        L.ref_da_log_phi.argtypes = [C.POINTER(_Medium), d, d]
+        L.ref_box_exit.restype = d
+        L.ref_box_exit.argtypes = [C.POINTER(_Geometry), pd, pd]
+        L.ref_box_entry.restype = C.c_int
+        L.ref_box_entry.argtypes = [C.POINTER(_Geometry), pd, pd, pd, pd]
+        L.ref_sobol_u.restype = d
+        L.ref_sobol_u.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+        L.ref_ris_step.restype = C.c_int
+        L.ref_ris_step.argtypes = [C.POINTER(_Medium), C.c_int, pd, pd, pd, d, d, C.c_uint32,
+                                   C.c_uint32, d, pd, pd, C.c_int]
+        L.ref_eda_row_raw.argtypes = [C.POINTER(_Medium), d, d, C.c_int, pd]
+        L.ref_build_da_tables.restype = C.c_int
+        L.ref_build_da_tables.argtypes = [C.POINTER(_Medium), C.POINTER(_Dims), pd,
+                                          C.POINTER(C.c_float), C.c_int]
+        L.ref_sample_direction.argtypes = [C.POINTER(_Medium), C.POINTER(_Dims), C.POINTER(C.c_float),
+                                           d, C.c_int, pd, pd, pd, d, pd, pd, pd,
+                                           C.POINTER(C.c_int), C.c_int]
+        L.ref_render_transient.restype = C.c_int
+        L.ref_render_transient.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
+                                           C.POINTER(C.c_float), pd, pd, C.POINTER(C.c_uint64), C.c_int]
+        L.ref_render_paths.restype = C.c_int
+        L.ref_render_paths.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
+                                       C.POINTER(C.c_float), pd, C.POINTER(C.c_int64), C.c_int]
+        L.ref_render_gradient.restype = C.c_int
+        L.ref_render_gradient.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
+                                          C.POINTER(C.c_float), pd, pd, C.c_int]
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------------------------
+# marshalling
+# --------------------------------------------------------------------------
+def _v3(x):
+    return (C.c_double * 3)(*[float(v) for v in x])
+
+
+def medium(m: dict) -> _Medium:
+    return _Medium(float(m["sigma_s"]), float(m["sigma_a"]), float(m["g"]))
+
+
+def geometry(g: dict) -> _Geometry:
+    return _Geometry(int(g["kind"]), _v3(g.get("lo", (0, 0, 0))), _v3(g.get("hi", (0, 0, 0))))
+
+
+def dims(d: dict) -> _Dims:
+    return _Dims(int(d["n_cs"]), int(d["n_s"]), int(d["n_cos"]), float(d["s_max"]))
+
+
+class _SceneHolder:
+    """Keeps the emitter array alive while the C struct points at it."""
+
+    def __init__(self, sc: dict):
+        ems = sc["emitters"]
+        self.em = (_Emitter * len(ems))(*[_Emitter(_v3(e["pos"]), float(e.get("start", 0.0)),
+                                                   float(e.get("power", 1.0))) for e in ems])
+        s = sc["sensor"]
+        sensor = _Sensor(int(s["kind"]), _v3(s["origin"]), _v3(s.get("dir", (0, 0, -1))),
+                         _v3(s.get("du", (0, 0, 0))), _v3(s.get("dv", (0, 0, 0))),
+                         int(s.get("width", 1)), int(s.get("height", 1)))
+        b = sc["bins"]
+        self.c = _Scene(medium(sc["medium"]), geometry(sc["geometry"]),
+                        C.cast(self.em, C.POINTER(_Emitter)), len(ems), sensor,
+                        _Bins(float(b["l_lo"]), float(b["l_hi"]), int(b["n_bins"])))
+
+
+def params(p: dict, mode: str | None = None, mutation: str = "none") -> _Params:
+    flags = MODES[mode] if mode is not None else int(p["flags"])
+    return _Params(int(p["n_paths"]), int(p.get("path_offset", 0)), int(p["seed"]),
+                   int(p["max_bounces"]), int(p.get("n_ris", 8)), float(p.get("alpha", 0.5)),
+                   flags, MUT[mutation])
+
+
+def n_cells(sc: dict) -> int:
+    s = sc["sensor"]
+    return int(s.get("width", 1)) * int(s.get("height", 1)) * int(sc["bins"]["n_bins"])
+
+
+def image_shape(sc: dict):
+    s = sc["sensor"]
+    return (int(sc["bins"]["n_bins"]), int(s.get("height", 1)), int(s.get("width", 1)))
+
+
+# --------------------------------------------------------------------------
+# API
+# --------------------------------------------------------------------------
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().ref_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def build_table(med: dict, d: dict, n_threads: int = 0):
+    """Returns (pmf float64 [n_cs,n_s,n_cos], cdf float32 [n_cs,n_s,n_cos+1])."""
+    dd = dims(d)
+    pmf = np.zeros((dd.n_cs, dd.n_s, dd.n_cos), np.float64)
+    cdf = np.zeros((dd.n_cs, dd.n_s, dd.n_cos + 1), np.float32)
+    rc = lib().ref_build_da_tables(C.byref(medium(med)), C.byref(dd),
+                                   pmf.ctypes.data_as(C.POINTER(C.c_double)),
+                                   cdf.ctypes.data_as(C.POINTER(C.c_float)), int(n_threads))
+    if rc:
+        raise ValueError(f"ref_build_da_tables failed: {rc}")
+    return pmf, cdf
+
+
+def _table_args(d, cdf):
+    if cdf is None:
+        return None, None
+    cdf = np.ascontiguousarray(cdf, np.float32)
+    return C.byref(dims(d)), cdf.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def render(sc: dict, p: dict, mode: str, table=None, dims_: dict | None = None,
+           n_threads: int = 0, mutation: str = "none"):
+    """Raw sums (image, m2) with shape [n_bins, H, W] and a stats dict."""
+    holder = _SceneHolder(sc)
+    pr = params(p, mode, mutation)
+    shape = image_shape(sc)
+    img = np.zeros(shape, np.float64)
+    m2 = np.zeros(shape, np.float64)
+    st = np.zeros(16, np.uint64)
+    cdf = None if table is None else np.ascontiguousarray(table, np.float32)
+    dptr = C.byref(dims(dims_)) if (cdf is not None) else None
+    cptr = cdf.ctypes.data_as(C.POINTER(C.c_float)) if cdf is not None else None
+    rc = lib().ref_render_transient(C.byref(holder.c), C.byref(pr), dptr, cptr,
+                                    img.ctypes.data_as(C.POINTER(C.c_double)),
+                                    m2.ctypes.data_as(C.POINTER(C.c_double)),
+                                    st.ctypes.data_as(C.POINTER(C.c_uint64)), int(n_threads))
+    if rc:
+        raise ValueError(f"ref_render_transient failed: {rc}")
+    return img, m2, {k: int(st[i]) for i, k in enumerate(STATS)}
+
+
+def render_paths(sc: dict, p: dict, mode: str, table=None, dims_: dict | None = None,
+                 n_threads: int = 0, mutation: str = "none"):
+    holder = _SceneHolder(sc)
+    pr = params(p, mode, mutation)
+    n = int(p["n_paths"])
+    val = np.zeros(n, np.float64)
+    cell = np.zeros(n, np.int64)
+    cdf = None if table is None else np.ascontiguousarray(table, np.float32)
+    dptr = C.byref(dims(dims_)) if (cdf is not None) else None
+    cptr = cdf.ctypes.data_as(C.POINTER(C.c_float)) if cdf is not None else None
+    rc = lib().ref_render_paths(C.byref(holder.c), C.byref(pr), dptr, cptr,
+                                val.ctypes.data_as(C.POINTER(C.c_double)),
+                                cell.ctypes.data_as(C.POINTER(C.c_int64)), int(n_threads))
+    if rc:
+        raise ValueError(f"ref_render_paths failed: {rc}")
+    return val, cell
+
+
+def render_gradient(sc: dict, p: dict, mode: str, grad_image, table=None, dims_=None, n_threads=0):
+    holder = _SceneHolder(sc)
+    pr = params(p, mode)
+    gi = np.ascontiguousarray(grad_image, np.float64)
+    out = np.zeros(3, np.float64)
+    cdf = None if table is None else np.ascontiguousarray(table, np.float32)
+    dptr = C.byref(dims(dims_)) if (cdf is not None) else None
+    cptr = cdf.ctypes.data_as(C.POINTER(C.c_float)) if cdf is not None else None
+    rc = lib().ref_render_gradient(C.byref(holder.c), C.byref(pr), dptr, cptr,
+                                   gi.ctypes.data_as(C.POINTER(C.c_double)),
+                                   out.ctypes.data_as(C.POINTER(C.c_double)), int(n_threads))
+    if rc:
+        raise ValueError(f"ref_render_gradient failed: {rc}")
+    return out
+
+
+def paths_per_cell(sc: dict, p: dict, mode: str) -> np.ndarray:
+    """Number of paths whose estimate lands in each cell: the stratified map
+    sends path id i to cell i mod n_cells (DARTS family); the vanilla mode
+    reuses a path for all bins of its pixel; the forward walk feeds every
+    cell of the single detector."""
+    shape = image_shape(sc)
+    nc = n_cells(sc)
+    n, off = int(p["n_paths"]), int(p.get("path_offset", 0))
+    ids = np.arange(nc, dtype=np.int64)
+    # count of i in [off, off+n) with i mod nc == c
+    first = (ids - off) % nc
+    cnt = np.where(first < n, (n - 1 - first) // nc + 1, 0).astype(np.float64)
+    if mode == "forward":
+        return np.full(shape, float(n))
+    if mode == "vanilla":
+        npix = shape[1] * shape[2]
+        per_pix = cnt.reshape(shape).sum(axis=0).reshape(1, shape[1], shape[2])
+        return np.broadcast_to(per_pix, shape).astype(np.float64)
+    return cnt.reshape(shape)
+
+
+def estimate(sc: dict, p: dict, mode: str, img, m2):
+    """Per-cell mean and standard error from the raw sums."""
+    n = paths_per_cell(sc, p, mode)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean = np.where(n > 0, img / n, 0.0)
+        var = np.where(n > 1, (m2 / n - mean ** 2) / np.maximum(n - 1, 1), 0.0)
+    return mean, np.sqrt(np.maximum(var, 0.0))

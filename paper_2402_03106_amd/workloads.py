@@ -1,0 +1,110 @@
+"""Seeded synthetic workloads (scene descriptions only, no method arithmetic).
+
+The paper's test scenes are triangle meshes that are not available; these
+homogeneous media stand in for them (the box medium of ``box_hg`` has a
+camera-to-emitter depth of about 3.35 transport mean free paths, inside the
+3.2-4.3 range of the paper's scene table, Section VI).  Every value here is
+plain data: both the GPU library's binding and the CPU oracle consume the same
+dictionaries, so this module is the only thing the two sides share.
+"""
+from __future__ import annotations
+
+import copy
+
+# Strategy names understood by both sides.
+MODES = ("darts", "uniform", "vanilla", "da_only", "eda_only")
+
+
+def infinite_point() -> dict:
+    """Infinite homogeneous medium, isotropic unit-energy pulse at the origin
+    (start 0), point fluence detector at distance 1; sigma_s = 1,
+    sigma_a = 0.01, isotropic phase; 64 path-length bins over [0, 10);
+    2^16 paths, at most 50 bounces; 64x64x32 direction table, S_max = 10."""
+    return {
+        "name": "infinite_point",
+        "scene": {
+            "medium": {"sigma_s": 1.0, "sigma_a": 0.01, "g": 0.0},
+            "geometry": {"kind": 0, "lo": (0.0, 0.0, 0.0), "hi": (0.0, 0.0, 0.0)},
+            "emitters": [{"pos": (0.0, 0.0, 0.0), "start": 0.0, "power": 1.0}],
+            "sensor": {"kind": 0, "origin": (1.0, 0.0, 0.0), "dir": (0.0, 0.0, 1.0),
+                       "du": (0.0, 0.0, 0.0), "dv": (0.0, 0.0, 0.0), "width": 1, "height": 1},
+            "bins": {"l_lo": 0.0, "l_hi": 10.0, "n_bins": 64},
+        },
+        "params": {"n_paths": 1 << 16, "path_offset": 0, "seed": 0xC1, "max_bounces": 50,
+                   "n_ris": 8, "alpha": 0.5},
+        "dims": {"n_cs": 64, "n_s": 64, "n_cos": 32, "s_max": 10.0},
+    }
+
+
+def box_hg() -> dict:
+    """Box medium [-1,1]^3 with index-matched boundary, sigma_t = 5, albedo
+    0.95 (sigma_s = 4.75, sigma_a = 0.25), Henyey-Greenstein g = 0.7; one
+    pulsed point emitter at (0, 0, 1.5) with start 0; 64x64 orthographic
+    radiance sensor on the plane z = +1 over [-1,1]^2 looking along -z; 256
+    bins over path length [0, 40); 2^20 paths; 64x64x32 FP32 direction table
+    with S_max = 40; at most 256 bounces."""
+    return {
+        "name": "box_hg",
+        "scene": {
+            "medium": {"sigma_s": 4.75, "sigma_a": 0.25, "g": 0.7},
+            "geometry": {"kind": 1, "lo": (-1.0, -1.0, -1.0), "hi": (1.0, 1.0, 1.0)},
+            "emitters": [{"pos": (0.0, 0.0, 1.5), "start": 0.0, "power": 1.0}],
+            "sensor": {"kind": 1, "origin": (-1.0, -1.0, 1.0), "dir": (0.0, 0.0, -1.0),
+                       "du": (2.0, 0.0, 0.0), "dv": (0.0, 2.0, 0.0), "width": 64, "height": 64},
+            "bins": {"l_lo": 0.0, "l_hi": 40.0, "n_bins": 256},
+        },
+        "params": {"n_paths": 1 << 20, "path_offset": 0, "seed": 0xC2, "max_bounces": 256,
+                   "n_ris": 8, "alpha": 0.5},
+        "dims": {"n_cs": 64, "n_s": 64, "n_cos": 32, "s_max": 40.0},
+    }
+
+
+def box_hg_small() -> dict:
+    """The box medium of ``box_hg`` with an 8x8 sensor and 32 bins over
+    [0, 10): a size the oracle finishes in seconds, for CPU pins."""
+    w = box_hg()
+    w["name"] = "box_hg_small"
+    w["scene"]["sensor"]["width"] = 8
+    w["scene"]["sensor"]["height"] = 8
+    w["scene"]["bins"] = {"l_lo": 0.0, "l_hi": 10.0, "n_bins": 32}
+    w["params"]["n_paths"] = 1 << 16
+    w["dims"] = {"n_cs": 32, "n_s": 32, "n_cos": 32, "s_max": 10.0}
+    return w
+
+
+def box_point() -> dict:
+    """Box medium [-1,1]^3 (sigma_s = 2, sigma_a = 0.1, g = 0.5) lit by a
+    pulse at (0, 0, 1.5) and seen by a point fluence detector at (1.5, 0, 0),
+    both outside the medium so that every estimator has bounded weights; 32
+    bins over [0, 16).  Used to check independent estimators against each
+    other at all scattering orders."""
+    return {
+        "name": "box_point",
+        "scene": {
+            "medium": {"sigma_s": 2.0, "sigma_a": 0.1, "g": 0.5},
+            "geometry": {"kind": 1, "lo": (-1.0, -1.0, -1.0), "hi": (1.0, 1.0, 1.0)},
+            "emitters": [{"pos": (0.0, 0.0, 1.5), "start": 0.0, "power": 1.0}],
+            "sensor": {"kind": 0, "origin": (1.5, 0.0, 0.0), "dir": (0.0, 0.0, 1.0),
+                       "du": (0.0, 0.0, 0.0), "dv": (0.0, 0.0, 0.0), "width": 1, "height": 1},
+            "bins": {"l_lo": 0.0, "l_hi": 16.0, "n_bins": 32},
+        },
+        "params": {"n_paths": 1 << 18, "path_offset": 0, "seed": 0xB0, "max_bounces": 128,
+                   "n_ris": 8, "alpha": 0.5},
+        "dims": {"n_cs": 32, "n_s": 32, "n_cos": 32, "s_max": 16.0},
+    }
+
+
+def with_(w: dict, **changes) -> dict:
+    """Copy of a workload with params/scene entries replaced, e.g.
+    ``with_(w, n_paths=4096, medium={"sigma_s": 2.0, ...})``."""
+    w = copy.deepcopy(w)
+    for k, v in changes.items():
+        if k in w["params"]:
+            w["params"][k] = v
+        elif k in w["scene"]:
+            w["scene"][k] = v
+        elif k in w["dims"]:
+            w["dims"][k] = v
+        else:
+            raise KeyError(k)
+    return w

@@ -1,0 +1,584 @@
+"""Pins of the FP64 oracle against things other than itself: published
+known-answer vectors, closed forms, invariants, special cases, brute force,
+and independent estimators of the same quantity.  Each pin is chosen so that
+a plausible mistake (a dropped term, a wrong sign, an inverted Jacobian)
+fails at least one of them; ``test_planted_mistakes_are_caught`` shows that
+for the mistakes the oracle can plant in itself."""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_2402_03106_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+PI = math.pi
+
+
+def _vec(x):
+    return (C.c_double * 3)(*x)
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10: published known-answer vectors (Random123, SC'11)
+# --------------------------------------------------------------------------
+def read_kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                v = [int(t, 16) for t in line.split()]
+                rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers(oracle):
+    for ctr, key, out in read_kat():
+        assert oracle.philox(ctr, key) == out
+
+
+def test_u01_map(oracle):
+    L = oracle.lib()
+    assert L.ref_u01(0) == 0.0
+    assert L.ref_u01(0x80000000) == 0.5
+    assert L.ref_u01(0xFFFFFFFF) == 1.0 - 2.0 ** -24
+    assert L.ref_u01(0x000000FF) == 0.0  # low 8 bits dropped
+
+
+# --------------------------------------------------------------------------
+# Henyey-Greenstein: normalisation, mean cosine, inverse CDF
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [-0.9, -0.3, 0.0, 0.01, 0.5, 0.7, 0.95])
+def test_hg_pdf_moments(oracle, g):
+    L = oracle.lib()
+    norm = integrate.quad(lambda mu: 2 * PI * L.ref_hg_pdf(mu, g), -1, 1, epsabs=1e-13, limit=200)[0]
+    mean = integrate.quad(lambda mu: 2 * PI * mu * L.ref_hg_pdf(mu, g), -1, 1, epsabs=1e-13, limit=200)[0]
+    assert abs(norm - 1.0) < 1e-9
+    assert abs(mean - g) < 1e-9
+
+
+@pytest.mark.parametrize("g", [-0.9, -0.3, 0.0, 0.01, 0.5, 0.7, 0.95])
+def test_hg_sampler_inverts_cdf(oracle, g):
+    """F(mu(xi)) = xi with F integrated numerically from the pdf (an
+    independent route to the CDF)."""
+    L = oracle.lib()
+    for xi in np.linspace(0.0, 0.999, 23):
+        mu = L.ref_hg_sample_mu(xi, g)
+        F = integrate.quad(lambda m: 2 * PI * L.ref_hg_pdf(m, g), -1, mu, epsabs=1e-13, limit=200)[0]
+        assert abs(F - xi) < 1e-8, (g, xi, mu, F)
+
+
+def test_onb_orthonormal(oracle):
+    L = oracle.lib()
+    rng = np.random.default_rng(1)
+    ns = [np.array([0, 0, 1.0]), np.array([0, 0, -1.0]), np.array([1.0, 0, 0])]
+    ns += [v / np.linalg.norm(v) for v in rng.normal(size=(50, 3))]
+    for n in ns:
+        b1, b2 = _vec([0, 0, 0]), _vec([0, 0, 0])
+        L.ref_onb(_vec(n), b1, b2)
+        b1, b2 = np.array(b1[:]), np.array(b2[:])
+        M = np.stack([b1, b2, n])
+        assert np.allclose(M @ M.T, np.eye(3), atol=1e-14)
+        assert np.allclose(np.cross(b1, b2), n, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Transient diffusion approximation (Eq. 9)
+# --------------------------------------------------------------------------
+MEDIA = [dict(sigma_s=1.0, sigma_a=0.01, g=0.0), dict(sigma_s=4.75, sigma_a=0.25, g=0.7),
+         dict(sigma_s=2.0, sigma_a=0.1, g=-0.3)]
+
+
+@pytest.mark.parametrize("med", MEDIA)
+def test_da_D(oracle, med):
+    D = oracle.lib().ref_da_D(C.byref(oracle.medium(med)))
+    assert abs(D - 1.0 / (3 * (med["sigma_a"] + med["sigma_s"] * (1 - med["g"])))) < 1e-15
+
+
+@pytest.mark.parametrize("med", MEDIA)
+def test_da_phi_space_integral(oracle, med):
+    """A delta pulse in an absorbing medium keeps energy exp(-sigma_a s)."""
+    L, m = oracle.lib(), C.byref(oracle.medium(med))
+    for s in [0.05, 0.5, 3.0, 17.0]:
+        tot = integrate.quad(lambda r: 4 * PI * r * r * L.ref_da_phi(m, r, s), 0, np.inf, epsabs=0,
+                             epsrel=1e-11, limit=400)[0]
+        assert abs(tot - math.exp(-med["sigma_a"] * s)) < 1e-8
+
+
+@pytest.mark.parametrize("med", MEDIA)
+def test_da_phi_time_integral_is_steady_state(oracle, med):
+    """Time integral = steady-state diffusion Green's function
+    exp(-r sqrt(sigma_a/D)) / (4 pi D r)."""
+    L, m = oracle.lib(), C.byref(oracle.medium(med))
+    D = 1.0 / (3 * (med["sigma_a"] + med["sigma_s"] * (1 - med["g"])))
+    for r in [0.3, 1.0, 2.5]:
+        tot = integrate.quad(lambda s: L.ref_da_phi(m, r, s), 0, np.inf, epsabs=0, epsrel=1e-11,
+                             limit=400)[0]
+        assert abs(tot / (math.exp(-r * math.sqrt(med["sigma_a"] / D)) / (4 * PI * D * r)) - 1) < 1e-8
+
+
+def test_da_phi_causal_and_log(oracle):
+    L, m = oracle.lib(), C.byref(oracle.medium(MEDIA[1]))
+    assert L.ref_da_phi(m, 0.5, 0.0) == 0.0 and L.ref_da_phi(m, 0.5, -1.0) == 0.0
+    assert L.ref_da_log_phi(m, 0.5, -1.0) == -np.inf
+    for r, s in [(0.1, 0.2), (1.0, 3.0), (3.0, 4.0)]:
+        assert abs(math.log(L.ref_da_phi(m, r, s)) - L.ref_da_log_phi(m, r, s)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Truncated exponential (Eq. 13-14)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("sigma,width", [(1.0, 2.0), (5.0, 0.3), (5.0, np.inf), (0.01, 10.0), (20.0, 5.0)])
+def test_texp_inverse_cdf(oracle, sigma, width):
+    L = oracle.lib()
+    F = (lambda x: -math.expm1(-sigma * x) / -math.expm1(-sigma * width)) if np.isfinite(width) \
+        else (lambda x: -math.expm1(-sigma * x))
+    for u in np.linspace(0, 1 - 2 ** -24, 31):
+        x = L.ref_texp_sample(u, sigma, width)
+        assert 0.0 <= x < width
+        assert abs(F(x) - u) < 1e-12
+    if np.isfinite(width):
+        tot = integrate.quad(lambda x: L.ref_texp_pdf(x, sigma, width), 0, width, epsabs=0, epsrel=1e-12)[0]
+        assert abs(tot - 1) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# Elliptical connection (Eq. 18, 21, 22)
+# --------------------------------------------------------------------------
+def test_ellipse_identity(oracle):
+    """The control vertex x + w t lies on the ellipsoid of length sum S."""
+    L = oracle.lib()
+    rng = np.random.default_rng(2)
+    for _ in range(500):
+        x, xe = rng.normal(size=3), rng.normal(size=3)
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        Cd = np.linalg.norm(xe - x)
+        mu = np.dot(w, xe - x) / Cd
+        S = Cd * (1 + rng.uniform(1e-3, 3))
+        t = L.ref_ell_t(S, Cd, mu)
+        assert t > 0
+        assert abs(t + np.linalg.norm(x + w * t - xe) - S) < 1e-12 * S
+
+
+@pytest.mark.parametrize("printed", [0, 1])
+def test_ellipse_density_integrates_to_one(oracle, printed):
+    """p(t) over [t(S_lo), t(S_hi)] must integrate to 1 (true for the
+    corrected Jacobian, false for the printed one)."""
+    L = oracle.lib()
+    worst = 0.0
+    for Cd, mu, S_lo, S_hi, sig in [(1.0, 0.3, 1.2, 4.0, 2.0), (2.0, 0.95, 2.0, 2.5, 5.0),
+                                    (0.5, -0.7, 0.6, 9.0, 1.0)]:
+        width = S_hi - S_lo
+
+        def p_t(t):
+            # invert t(S): S solves t = (S^2 - C^2)/(2S - 2 C mu)
+            a, b, c = 1.0, -2 * t, 2 * t * Cd * mu - Cd * Cd
+            S = (-b + math.sqrt(b * b - 4 * a * c)) / 2
+            pS = L.ref_texp_pdf(S - S_lo, sig, width)
+            return L.ref_ell_pdf_t(pS, S, Cd, mu, t, printed)
+
+        t0, t1 = L.ref_ell_t(S_lo, Cd, mu), L.ref_ell_t(S_hi, Cd, mu)
+        tot = integrate.quad(p_t, t0, t1, epsabs=0, epsrel=1e-11, limit=200)[0]
+        worst = max(worst, abs(tot - 1))
+    if printed:
+        assert worst > 0.05
+    else:
+        assert worst < 1e-8
+
+
+def test_ellipse_density_matches_histogram(oracle):
+    """Brute force: push stratified S samples through t(S) and compare the
+    histogram of t with the bin integrals of p(t)."""
+    L = oracle.lib()
+    Cd, mu, S_lo, S_hi, sig = 1.0, 0.3, 1.2, 4.0, 2.0
+    width = S_hi - S_lo
+    n = 200000
+    u = (np.arange(n) + 0.5) / n
+    S = S_lo + np.array([L.ref_texp_sample(v, sig, width) for v in u])
+    t = (S * S - Cd * Cd) / (2 * S - 2 * Cd * mu)
+    edges = np.linspace(t.min(), t.max(), 41)
+    hist = np.histogram(t, edges)[0] / n
+
+    def p_t(tt):
+        S_ = tt + math.sqrt(tt * tt - 2 * tt * Cd * mu + Cd * Cd)
+        return L.ref_ell_pdf_t(L.ref_texp_pdf(S_ - S_lo, sig, width), S_, Cd, mu, tt, 0)
+
+    pred = np.array([integrate.quad(p_t, a, b)[0] for a, b in zip(edges[:-1], edges[1:])])
+    assert np.max(np.abs(hist - pred)) < 2e-4
+
+
+def test_gamma(oracle):
+    L = oracle.lib()
+    assert L.ref_gamma(0.0, 0.5) == 0.0
+    assert abs(L.ref_gamma(0.5, 0.5) - 0.5) < 1e-15
+    assert abs(L.ref_gamma(0.9, 0.5) - 0.9 / 1.4) < 1e-15
+
+
+def test_box_entry_exit(oracle):
+    L = oracle.lib()
+    g = oracle.geometry({"kind": 1, "lo": (-1, -1, -1), "hi": (1, 1, 1)})
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        x = rng.uniform(-0.99, 0.99, 3)
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        d = L.ref_box_exit(C.byref(g), _vec(x), _vec(w))
+        p = x + w * d
+        assert np.max(np.abs(p)) == pytest.approx(1.0, abs=1e-12)
+        assert np.all(np.abs(x + w * d * 0.999) < 1.0)
+        o = x - 3 * w
+        ti, to = C.c_double(), C.c_double()
+        assert L.ref_box_entry(C.byref(g), _vec(o), _vec(w), C.byref(ti), C.byref(to))
+        assert abs(to.value - (3 + d)) < 1e-12
+    inf = oracle.geometry({"kind": 0})
+    assert L.ref_box_exit(C.byref(inf), _vec([0, 0, 0]), _vec([0, 0, 1])) == np.inf
+
+
+# --------------------------------------------------------------------------
+# RIS distance sampling (Section IV-C, Eq. 10-15)
+# --------------------------------------------------------------------------
+def test_sobol_rows_stratify(oracle):
+    L = oracle.lib()
+    for row in range(32):
+        vals = [L.ref_sobol_u(row, c, 0) for c in range(8)]
+        assert sorted(int(v * 8) for v in vals) == list(range(8))
+        # radical inverse of 8*row + c
+        for c, v in enumerate(vals):
+            i, inv, f = 8 * row + c, 0.0, 0.5
+            while i:
+                inv += f * (i & 1)
+                i >>= 1
+                f *= 0.5
+            assert v == inv
+
+
+def _ris_expectation(oracle, med, x, w, xe, R_hi, d_m, h, mutation=0, M=4181):
+    """Expectation of p_m * factor * h(d) over the 32 rows and a Fibonacci
+    lattice in (eps, u_sel)."""
+    L = oracle.lib()
+    m = C.byref(oracle.medium(med))
+    st = med["sigma_s"] + med["sigma_a"]
+    pc = 1.0 if np.isinf(d_m) else -math.expm1(-st * d_m)
+    d, fac = C.c_double(), C.c_double()
+    acc = 0.0
+    xv, wv, ev = _vec(x), _vec(w), _vec(xe)
+    F1 = 2584  # consecutive Fibonacci numbers (2584, 4181)
+    for row in range(32):
+        for i in range(M):
+            eps = int((i + 0.5) / M * 2 ** 32)
+            u_sel = ((i * F1) % M + 0.5) / M
+            if L.ref_ris_step(m, 8, xv, wv, ev, R_hi, d_m, row, eps, u_sel,
+                              C.byref(d), C.byref(fac), mutation):
+                acc += pc * fac.value * h(d.value)
+    return acc / (32 * M)
+
+
+RIS_CASES = {
+    # walking away from the emitter (C = 1): valid while 1 + d < R_hi - d
+    "away": dict(x=[0, 0, 0.5], w=[0, 0, -1.0], d_m=1.5, dmax=lambda R: min(1.5, (R - 1.0) / 2)),
+    # walking towards it (C = 2): always inside the ellipsoid; the fluence
+    # grows eightfold along the ray, so the resampling weights matter
+    "toward": dict(x=[0, 0, -0.5], w=[0, 0, 1.0], d_m=1.5, dmax=lambda R: min(1.5, R)),
+}
+
+
+@pytest.mark.parametrize("case,R_hi", [("away", 3.0), ("away", 1.6), ("toward", 2.3), ("toward", 5.0)])
+@pytest.mark.parametrize("hname", ["one", "d", "cos"])
+def test_ris_step_unbiased(oracle, case, R_hi, hname):
+    """E[p_m * weight * h(d)] = int_0^{d_m} sigma_s exp(-sigma_t d) h(d) 1{valid} dd
+    (valid: residual left and inside the residual-time ellipsoid)."""
+    h = {"one": lambda d: 1.0, "d": lambda d: d, "cos": lambda d: math.cos(3 * d)}[hname]
+    med = MEDIA[1]
+    st = med["sigma_s"] + med["sigma_a"]
+    c = RIS_CASES[case]
+    exact = integrate.quad(lambda d: med["sigma_s"] * math.exp(-st * d) * h(d), 0, c["dmax"](R_hi),
+                           epsabs=0, epsrel=1e-12)[0]
+    est = _ris_expectation(oracle, med, c["x"], c["w"], [0, 0, 1.5], R_hi, c["d_m"], h)
+    assert abs(est - exact) < 2e-3 * abs(exact) + 1e-6, (est, exact)
+
+
+def test_ris_step_all_invalid(oracle):
+    L = oracle.lib()
+    d, fac = C.c_double(), C.c_double()
+    # residual smaller than the distance to the emitter: no candidate valid
+    ok = L.ref_ris_step(C.byref(oracle.medium(MEDIA[1])), 8, _vec([0, 0, 0.5]), _vec([0, 0, -1]),
+                        _vec([0, 0, 1.5]), 0.9, 1.5, 3, 12345, 0.5, C.byref(d), C.byref(fac), 0)
+    assert ok == 0
+
+
+# --------------------------------------------------------------------------
+# EDA table (Section V-A, Eq. 16-18)
+# --------------------------------------------------------------------------
+def test_eda_row_uniform_when_emitter_at_focus(oracle):
+    """C -> 0: the ellipse is a sphere and the integrand does not depend on
+    cos(theta), so every bin carries the same mass."""
+    L = oracle.lib()
+    for med in MEDIA:
+        out = np.zeros(32)
+        L.ref_eda_row_raw(C.byref(oracle.medium(med)), 0.0, 3.0, 32, out.ctypes.data_as(C.POINTER(C.c_double)))
+        assert np.max(np.abs(out / out.mean() - 1)) < 1e-12
+
+
+def _row_adaptive(med, Cd, S, n):
+    st = med["sigma_s"] + med["sigma_a"]
+    D = 1.0 / (3 * (med["sigma_a"] + med["sigma_s"] * (1 - med["g"])))
+
+    def f(t, u):
+        s = S - t
+        r2 = max(t * t + Cd * Cd - 2 * t * Cd * u, 0.0)
+        return med["sigma_s"] * math.exp(-st * t) * (4 * PI * D * s) ** -1.5 * math.exp(-r2 / (4 * D * s) - med["sigma_a"] * s)
+
+    out = []
+    for k in range(n):
+        lo, hi = -1 + 2 * k / n, -1 + 2 * (k + 1) / n
+        out.append(integrate.dblquad(f, lo, hi, lambda u: 0.0, lambda u: (S * S - Cd * Cd) / (2 * S - 2 * Cd * u),
+                                     epsabs=0, epsrel=1e-10)[0])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("kappa,S", [(0.1, 1.0), (0.5, 2.0), (0.3, 10.0), (0.9, 5.0)])
+def test_eda_row_matches_adaptive_quadrature(oracle, kappa, S):
+    """The fixed Gauss-Legendre rule reproduces Eq. (17) integrated by an
+    independent adaptive quadrature (accuracy of the rule: ~1e-3 worst case
+    on strongly peaked rows, far better on smooth ones)."""
+    med = MEDIA[1]
+    L = oracle.lib()
+    raw = np.zeros(32)
+    L.ref_eda_row_raw(C.byref(oracle.medium(med)), kappa * S, S, 32, raw.ctypes.data_as(C.POINTER(C.c_double)))
+    ex = _row_adaptive(med, kappa * S, S, 32)
+    assert abs(raw.sum() / ex.sum() - 1) < 5e-4
+    pe, pr = ex / ex.sum(), raw / raw.sum()
+    assert np.max(np.abs(pr - pe) / pe) < 2e-3
+
+
+def test_table_layout(oracle):
+    w = W.box_hg_small()
+    pmf, cdf = oracle.build_table(w["scene"]["medium"], w["dims"])
+    assert np.allclose(pmf.sum(-1), 1.0, atol=1e-12)
+    assert np.all(cdf[..., 0] == 0.0) and np.all(cdf[..., -1] == 1.0)
+    assert np.all(np.diff(cdf, axis=-1) >= 0)
+    assert np.allclose(np.diff(cdf.astype(np.float64), axis=-1), pmf, atol=2e-7)
+
+
+# --------------------------------------------------------------------------
+# Direction sampling with one-sample MIS (Section V-A, Eq. 19)
+# --------------------------------------------------------------------------
+def _direction_moments(oracle, med, dims, cdf, x, xe, wprev, S, mutation=0, n=60000, seed=5):
+    L = oracle.lib()
+    rng = np.random.default_rng(seed)
+    m, dd = C.byref(oracle.medium(med)), C.byref(oracle.dims(dims))
+    cp = np.ascontiguousarray(cdf, np.float32).ctypes.data_as(C.POINTER(C.c_float))
+    a = np.array(xe, float) - np.array(x, float)
+    a /= np.linalg.norm(a)
+    wo, wt, eb = _vec([0, 0, 0]), C.c_double(), C.c_int()
+    xv, ev, pv = _vec(x), _vec(xe), _vec(wprev)
+    acc = np.zeros(3)
+    U = rng.random((n, 4))
+    for i in range(n):
+        L.ref_sample_direction(m, dd, cp, 0.5, 1, xv, ev, pv, S, (C.c_double * 4)(*U[i]), wo, C.byref(wt), C.byref(eb), mutation)
+        mu = np.dot(np.array(wo[:]), a)
+        acc += wt.value * np.array([1.0, mu, mu * mu])
+    return acc / n
+
+
+def test_direction_mis_is_unbiased(oracle):
+    """E[weight h(w)] = int p_HG(w_prev.w) h(w) dw: for h = 1, a.w and (a.w)^2
+    the right side is 1, g (a.w_prev) and (1 + 2 g^2 P2(a.w_prev))/3."""
+    w = W.box_hg_small()
+    med = w["scene"]["medium"]
+    _, cdf = oracle.build_table(med, w["dims"])
+    x, xe = [0.2, -0.1, 0.3], [0.0, 0.0, 1.5]
+    wprev = np.array([0.3, 0.5, -0.8])
+    wprev /= np.linalg.norm(wprev)
+    a = np.array(xe) - np.array(x)
+    Cd = np.linalg.norm(a)
+    a /= Cd
+    c = float(np.dot(a, wprev))
+    g = med["g"]
+    exact = np.array([1.0, g * c, (1 + 2 * g * g * 0.5 * (3 * c * c - 1)) / 3])
+    est = _direction_moments(oracle, med, w["dims"], cdf, x, xe, list(wprev), S=Cd * 1.6)
+    assert np.max(np.abs(est - exact)) < 0.01, (est, exact)
+
+
+# --------------------------------------------------------------------------
+# Whole-path pins
+# --------------------------------------------------------------------------
+def _order1_exact(sc, R=1.0):
+    m = sc["medium"]
+    st = m["sigma_s"] + m["sigma_a"]
+    phi1 = lambda L: m["sigma_s"] * math.exp(-st * L) * math.log((L + R) / (L - R)) / (4 * PI * R * L)
+    b = sc["bins"]
+    edges = np.linspace(b["l_lo"], b["l_hi"], b["n_bins"] + 1)
+    return np.array([integrate.quad(phi1, max(lo, R), hi, limit=200)[0] if hi > R else 0.0
+                     for lo, hi in zip(edges[:-1], edges[1:])])
+
+
+def _order1_z(oracle, mode, mutation="none", n=1 << 19):
+    w = W.with_(W.infinite_point(), n_paths=n, max_bounces=1)
+    _, cdf = oracle.build_table(w["scene"]["medium"], w["dims"])
+    img, m2, _ = oracle.render(w["scene"], w["params"], mode, cdf, w["dims"], mutation=mutation)
+    mean, se = oracle.estimate(w["scene"], w["params"], mode, img, m2)
+    exact = _order1_exact(w["scene"])
+    return mean.ravel(), se.ravel(), exact
+
+
+def test_single_scattering_closed_form_is_checked_independently():
+    """The closed form itself: volume integral over the ellipsoid of
+    1/(r1^2 r2^2) equals (4 pi/(R L)) ln((L+R)/(L-R)) (prolate spheroidal
+    coordinates), checked by direct quadrature in spherical coordinates
+    about one focus."""
+    R = 1.0
+    for Lg in [1.05, 2.0, 7.3]:
+        # points at distance t from focus 1 along cos mu: r2 = L - t on the
+        # shell; int delta(r1 + r2 - L) dV = int dOmega t^2 / |d(r1+r2)/dt| / (t^2 r2^2)
+        def f(mu):
+            t = (Lg * Lg - R * R) / (2 * (Lg - R * mu))
+            r2 = Lg - t
+            dsdt = 1 + (t - R * mu) / r2
+            return 2 * PI / (dsdt * r2 * r2)
+        val = integrate.quad(f, -1, 1, epsabs=0, epsrel=1e-12)[0]
+        assert abs(val / (4 * PI / (R * Lg) * math.log((Lg + R) / (Lg - R))) - 1) < 1e-9
+
+
+@pytest.mark.parametrize("mode", ["darts", "uniform", "vanilla", "forward"])
+def test_single_scattering_transient(oracle, mode):
+    """Order-1 image of the infinite medium vs the analytic single-scattering
+    transient sigma_s e^{-sigma_t L} ln((L+R)/(L-R)) / (4 pi R L); bins below
+    L = R are exactly zero (causality)."""
+    mean, se, exact = _order1_z(oracle, mode)
+    assert np.all(mean[:6] == 0.0)
+    z = (mean[7:] - exact[7:]) / se[7:]
+    assert np.max(np.abs(z)) < 4.0, np.round(z, 1)
+    assert abs(mean[7:].sum() - exact[7:].sum()) < 4.0 * math.sqrt((se[7:] ** 2).sum())
+
+
+def test_causality_all_orders(oracle):
+    w = W.with_(W.infinite_point(), n_paths=1 << 16)
+    _, cdf = oracle.build_table(w["scene"]["medium"], w["dims"])
+    for mode in ["darts", "uniform", "vanilla", "forward"]:
+        img, _, _ = oracle.render(w["scene"], w["params"], mode, cdf, w["dims"])
+        assert np.all(img.ravel()[:6] == 0.0), mode
+
+
+def _box_point(oracle, mode, n, seed=0xB0, **kw):
+    w = W.with_(W.box_point(), n_paths=n, seed=seed, **kw)
+    _, cdf = oracle.build_table(w["scene"]["medium"], w["dims"])
+    img, m2, st = oracle.render(w["scene"], w["params"], mode, cdf, w["dims"])
+    mean, se = oracle.estimate(w["scene"], w["params"], mode, img, m2)
+    return mean.ravel(), se.ravel(), st
+
+
+@pytest.mark.parametrize("mode", ["darts", "uniform", "vanilla", "da_only", "eda_only"])
+def test_estimators_agree_all_orders(oracle, mode):
+    """Box medium, emitter and point detector outside it (bounded weights):
+    DARTS, the uniform-S baseline, vanilla path tracing and both ablation
+    arms against the forward analog walk, which shares no sampling step."""
+    mf, sf, _ = _box_point(oracle, "forward", 1 << 21)
+    m, s, _ = _box_point(oracle, mode, 1 << 21)
+    ok = (sf > 0) & (mf > 1e-4 * mf.max())      # bins the forward walk resolves
+    z = (m - mf)[ok] / np.sqrt(s ** 2 + sf ** 2)[ok]
+    assert np.max(np.abs(z)) < 4.0, np.round(z, 1)
+    assert abs(m[ok].sum() / mf[ok].sum() - 1) < 0.02
+
+
+def test_energy_conservation(oracle):
+    """Sum over 32 bins equals a single bin covering the same length range
+    (two different gate stratifications of the same integral)."""
+    m32, s32, _ = _box_point(oracle, "darts", 1 << 20)
+    w1 = dict(l_lo=0.0, l_hi=16.0, n_bins=1)
+    m1, s1, _ = _box_point(oracle, "darts", 1 << 17, bins=w1)
+    tot, se = m32.sum(), math.sqrt((s32 ** 2).sum())
+    assert abs(tot - m1[0]) < 4 * math.sqrt(se ** 2 + s1[0] ** 2)
+    mf, sf, _ = _box_point(oracle, "forward", 1 << 20, bins=w1)
+    assert abs(tot - mf[0]) < 4 * math.sqrt(se ** 2 + sf[0] ** 2)
+
+
+def test_darts_vs_uniform_infinite_medium(oracle):
+    """The config the paper's comparison is quoted on: plain uniform-S vs
+    DARTS RIS on the infinite medium agree (bins grouped by 8; the point
+    emitter inside the medium gives both estimators heavy-tailed weights)."""
+    w = W.with_(W.infinite_point(), n_paths=1 << 20)
+    _, cdf = oracle.build_table(w["scene"]["medium"], w["dims"])
+    out = {}
+    for mode in ["darts", "uniform"]:
+        img, m2, _ = oracle.render(w["scene"], w["params"], mode, cdf, w["dims"])
+        mean, se = oracle.estimate(w["scene"], w["params"], mode, img, m2)
+        out[mode] = (mean.ravel()[8:].reshape(7, 8).sum(1), np.sqrt((se.ravel()[8:] ** 2).reshape(7, 8).sum(1)))
+    (a, sa), (b, sb) = out["darts"], out["uniform"]
+    z = (a - b) / np.sqrt(sa ** 2 + sb ** 2)
+    assert np.max(np.abs(z)) < 4.0, z
+
+
+def test_late_time_diffusion_band(oracle):
+    """DA is an approximation of the transport equation (Section IV-B): the
+    multiple-scattering transient approaches it at late times.  Sanity band,
+    not parity: total fluence over [6, 10) within 15% of the DA fluence."""
+    w = W.with_(W.infinite_point(), n_paths=1 << 20)
+    sc = w["scene"]
+    m = sc["medium"]
+    D = 1.0 / (3 * (m["sigma_a"] + m["sigma_s"] * (1 - m["g"])))
+    phi = lambda s: (4 * PI * D * s) ** -1.5 * math.exp(-1.0 / (4 * D * s) - m["sigma_a"] * s)
+    da = integrate.quad(phi, 6.0, 10.0)[0]
+    _, cdf = oracle.build_table(m, w["dims"])
+    img, m2, _ = oracle.render(sc, w["params"], "darts", cdf, w["dims"])
+    mean, _ = oracle.estimate(sc, w["params"], "darts", img, m2)
+    ratio = mean.ravel()[38:].sum() / da
+    assert 0.95 < ratio < 1.15, ratio
+
+
+def test_box_sensor_modes_agree(oracle):
+    """Orthographic radiance sensor on the box medium (the GPU workload's
+    geometry at a small size): DARTS vs uniform-S vs vanilla, per bin summed
+    over pixels."""
+    w = W.box_hg_small()
+    _, cdf = oracle.build_table(w["scene"]["medium"], w["dims"])
+    res = {}
+    for mode in ["darts", "uniform", "vanilla"]:
+        p = dict(w["params"], n_paths=1 << 17 if mode != "vanilla" else 1 << 14)
+        img, m2, _ = oracle.render(w["scene"], p, mode, cdf, w["dims"])
+        mean, se = oracle.estimate(w["scene"], p, mode, img, m2)
+        res[mode] = (mean.sum((1, 2)), np.sqrt((se ** 2).sum((1, 2))))
+    a, sa = res["vanilla"]
+    ok = a > 1e-3 * a.max()
+    for mode in ["darts", "uniform"]:
+        b, sb = res[mode]
+        z = (b - a)[ok] / np.sqrt(sa ** 2 + sb ** 2)[ok]
+        assert np.max(np.abs(z)) < 4.0, (mode, np.round(z, 1))
+
+
+# --------------------------------------------------------------------------
+# Planted mistakes must be caught by the pins above
+# --------------------------------------------------------------------------
+def test_planted_mistakes_are_caught(oracle):
+    # inverted Jacobian of Eq. (22) and dropped emitter transmittance: the
+    # single-scattering transient pin fails
+    for mut in ["printed_jacobian", "no_emitter_trans"]:
+        mean, se, exact = _order1_z(oracle, "darts", mutation=mut, n=1 << 17)
+        z = (mean[7:] - exact[7:]) / np.maximum(se[7:], 1e-300)
+        assert np.max(np.abs(z)) > 6.0, mut
+    # RIS weight without mean/selected: the RIS expectation pin fails
+    med = MEDIA[1]
+    st = med["sigma_s"] + med["sigma_a"]
+    exact = integrate.quad(lambda d: med["sigma_s"] * math.exp(-st * d) * d, 0, 1.5)[0]
+    est = _ris_expectation(oracle, med, [0, 0, -0.5], [0, 0, 1.0], [0, 0, 1.5], 2.3, 1.5,
+                           lambda d: d, mutation=2, M=987)
+    assert abs(est - exact) > 0.02 * exact
+    # EDA pdf without its solid-angle scale, HG sample mirrored: the MIS pin fails
+    w = W.box_hg_small()
+    medb = w["scene"]["medium"]
+    _, cdf = oracle.build_table(medb, w["dims"])
+    x, xe = [0.2, -0.1, 0.3], [0.0, 0.0, 1.5]
+    wprev = np.array([0.3, 0.5, -0.8]) / np.linalg.norm([0.3, 0.5, -0.8])
+    a = np.array(xe) - np.array(x)
+    Cd = np.linalg.norm(a)
+    c = float(np.dot(a / Cd, wprev))
+    g = medb["g"]
+    exact = np.array([1.0, g * c, (1 + 2 * g * g * 0.5 * (3 * c * c - 1)) / 3])
+    for mut in [3, 5]:
+        est = _direction_moments(oracle, medb, w["dims"], cdf, x, xe, list(wprev), S=Cd * 1.6,
+                                 mutation=mut, n=20000)
+        assert np.max(np.abs(est - exact)) > 0.05, (mut, est, exact)
