@@ -1,0 +1,217 @@
+/*
+ * darts.h -- C ABI of libdarts, an MI355X (gfx950) implementation of the hot
+ * path of DARTS (He, Du, Jiang, Jin, "DARTS: Diffusion Approximated Residual
+ * Time Sampling for Time-of-flight Rendering in Homogeneous Scattering
+ * Media", 2024): per-path transient volumetric path tracing in a homogeneous
+ * medium with
+ *   - free-flight distances resampled (RIS) against the transient diffusion
+ *     fluence (Section IV, Eq. (9)-(15)),
+ *   - scattering directions drawn from an offline-tabulated elliptical-DA
+ *     density mixed with the phase function by one-sample MIS (Section V-A,
+ *     Eq. (16)-(19)),
+ *   - an elliptical control-vertex connection that closes the path inside a
+ *     target path-length interval (Section V-B, Eq. (20)-(22)),
+ *   - accumulation into path-length (time) bins on the sensor (Eq. (1), (4)).
+ *
+ * Units: speed of light and refractive index are 1; time and path length are
+ * the same quantity (Eq. (3)).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device pointers (hipMalloc'ed or torch CUDA
+ *     tensors) owned by the caller; the library never allocates, frees or
+ *     keeps device memory across calls and only writes the outputs named.
+ *   - Host structs are read during the call only.
+ *   - `stream` is a hipStream_t (NULL = default stream); all work is enqueued
+ *     on it and the call returns without synchronising.
+ *   - Return value: DARTS_OK (0) or a negative DARTS_ERR_* code; the message
+ *     of the last failure on the calling thread is darts_last_error().
+ *     Kernel faults are asynchronous and surface at the next synchronisation.
+ */
+#ifndef DARTS_H
+#define DARTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DARTS_OK                  0
+#define DARTS_ERR_INVALID_ARG    -1  /* bad sizes, parameters or null pointers  */
+#define DARTS_ERR_DEVICE         -2  /* a HIP runtime call failed               */
+#define DARTS_ERR_UNSUPPORTED    -3  /* valid request this build does not serve */
+#define DARTS_ERR_TABLE_MISMATCH -4  /* table built for another medium / dims   */
+
+#define DARTS_MAX_EMITTERS 8
+#define DARTS_MAX_COS_BINS 1024
+
+/* Homogeneous medium (Eq. (9)): sigma_s, sigma_a >= 0 in 1/length, with
+ * sigma_s + sigma_a > 0; Henyey-Greenstein asymmetry |g| < 1. */
+typedef struct { double sigma_s, sigma_a, g; } darts_medium;
+
+/* Isotropic pulsed point emitter (Section III, Eq. (1)): the pulse leaves at
+ * path-length offset `start`; radiant intensity power / (4 pi). */
+typedef struct { float pos[3]; float start; float power; } darts_emitter;
+
+/* Sensor.
+ *   kind 0: point fluence detector at `origin` (ray directions uniform on the
+ *           sphere, weight 4 pi); width = height = 1.
+ *   kind 1: orthographic radiance sensor; pixel (px, py) covers
+ *           origin + [px/width, (px+1)/width) du + [py/height, (py+1)/height) dv;
+ *           rays travel along `dir` (need not be normalised). */
+typedef struct {
+    int kind;
+    float origin[3], dir[3], du[3], dv[3];
+    int width, height;
+} darts_sensor;
+
+/* kind 0: infinite medium.  kind 1: the medium fills the axis-aligned box
+ * [lo, hi] with an index-matched boundary (vacuum outside, no refraction). */
+typedef struct { int kind; float lo[3], hi[3]; } darts_geometry;
+
+/* n_bins half-open bins of equal width over total path length [l_lo, l_hi),
+ * measured from the sensor and including the emitter's start offset. */
+typedef struct { float l_lo, l_hi; int n_bins; } darts_bins;
+
+typedef struct {
+    darts_medium medium;
+    darts_geometry geom;
+    const darts_emitter *emitters;   /* host array of n_emitters entries */
+    int n_emitters;                  /* 1 .. DARTS_MAX_EMITTERS          */
+    darts_sensor sensor;
+    darts_bins bins;
+} darts_scene;
+
+/* Elliptical-DA direction table (Section V-A): n_cs cells of C/S over [0,1),
+ * n_s cells of S over [0, s_max), n_cos uniform cos(theta) bins over [-1,1].
+ * The paper uses 256 cos bins; 32 is the default here (any table keeps the
+ * estimator unbiased, only its variance changes). */
+typedef struct { int n_cs, n_s, n_cos; float s_max; } darts_table_dims;
+
+/* A built table: `cdf_dev` holds float[n_cs][n_s][n_cos + 1]; row (i, j) is
+ * the cumulative distribution over cos-bins for C/S in cell i and S in cell
+ * j, cdf[..][0] = 0, cdf[..][n_cos] = 1.  `medium` and `dims` must be the
+ * values the table was built with; they are checked against the scene. */
+typedef struct { darts_medium medium; darts_table_dims dims; const float *cdf_dev; } darts_table;
+
+/* Sampling strategy bits (Section VI, ablation study):
+ *   DARTS     = RIS_DIST | EDA_DIR | ELL_TEXP
+ *   uniform   = ELL_UNIFORM            (temporally uniform connection, Section V-B)
+ *   vanilla   = DIRECT_REUSE           (shadow connection, path binned by length)
+ *   DA only   = RIS_DIST | ELL_UNIFORM,  EDA only = EDA_DIR | ELL_TEXP
+ * Exactly one of ELL_TEXP / ELL_UNIFORM unless DIRECT_REUSE is set. */
+#define DARTS_RIS_DIST      0x1u
+#define DARTS_EDA_DIR       0x2u
+#define DARTS_ELL_TEXP      0x4u
+#define DARTS_ELL_UNIFORM   0x8u
+#define DARTS_DIRECT_REUSE  0x10u
+
+typedef struct {
+    uint64_t n_paths;      /* paths in this call                                 */
+    uint64_t path_offset;  /* first path id; ids drive the RNG and the cell map  */
+    uint64_t seed;         /* Philox4x32-10 key                                  */
+    int max_bounces;       /* >= 1; maximum scattering order                     */
+    int n_ris;             /* RIS candidates; 8 (the paper's choice)             */
+    float alpha;           /* Eq. (19) preference parameter, >= 0 (paper: 0.5)   */
+    unsigned flags;        /* DARTS_* strategy bits                              */
+} darts_params;
+
+/* Statistics counters (uint64 each, accumulated with atomics). */
+enum {
+    DARTS_ST_PATHS = 0, DARTS_ST_VERTICES, DARTS_ST_CONNECTIONS, DARTS_ST_EARLY_EXIT,
+    DARTS_ST_MEDIUM_EXIT, DARTS_ST_RIS_ALL_INVALID, DARTS_ST_EDA_BRANCH,
+    DARTS_ST_TRUNCATED, DARTS_ST_ZERO_PATHS, DARTS_ST_COUNT = 16
+};
+
+/* Size in bytes of the cdf array of a table of these dimensions.
+ * Returns INVALID_ARG for non-positive dims, n_cos > DARTS_MAX_COS_BINS or
+ * s_max <= 0. */
+int darts_table_bytes(const darts_table_dims *dims, size_t *bytes);
+
+/* Build the elliptical-DA direction table of Section V-A (Eq. (16)-(18)).
+ * Entry (i, j, k) integrates sigma_s exp(-sigma_t t) Phi(x + w t, S - t) over
+ * t in [0, t_M(u)] (Eq. (18)) and u = cos(theta) in cos-bin k, with C/S and S
+ * at the cell centres ((i + 1/2)/n_cs, (j + 1/2) s_max/n_s) and Phi the
+ * transient diffusion fluence of Eq. (9).  Computed in FP64 on the device by
+ * a fixed Gauss-Legendre rule (4 nodes per cos-bin in u; 64 nodes in
+ * v = (1 - e^{-sigma_t t})/(1 - e^{-sigma_t t_M})); each row is normalised
+ * and its cumulative sum stored as float.  Rows whose integral underflows are
+ * uniform.  cdf_dev: device float[darts_table_bytes / 4], written in full. */
+int darts_build_da_tables(const darts_medium *medium, const darts_table_dims *dims,
+                          float *cdf_dev, void *stream);
+
+/* Render: accumulate raw path contributions into the time-resolved image.
+ *   Path id p = path_offset + i (i < n_paths) belongs to cell
+ *   c = p mod (n_bins * height * width); its pixel is c mod (height*width) and,
+ *   except in vanilla mode, its target interval is bin c / (height*width).
+ *   DARTS family: each path adds its estimate to its own cell; vanilla: each
+ *   path adds to every bin of its pixel its length reaches.
+ *   image_hi_dev, image_lo_dev: device float[n_bins][height][width],
+ *     accumulate-into; hi + lo is a compensated (two-float) sum.
+ *   image_m2_dev (nullable): accumulate-into sums of squared per-path (DARTS
+ *     family) or per-path-per-bin (vanilla) contributions.
+ *   stats_dev (nullable): accumulate-into uint64[DARTS_ST_COUNT].
+ *   table: required when flags contain DARTS_EDA_DIR, else may be NULL.
+ * The per-cell estimate is (hi + lo) / (number of paths mapped to the cell),
+ * or per pixel for vanilla. */
+int darts_render_transient(const darts_scene *scene, const darts_params *params,
+                           const darts_table *table,
+                           float *image_hi_dev, float *image_lo_dev, float *image_m2_dev,
+                           uint64_t *stats_dev, void *stream);
+
+/* Per-path estimates (DARTS family only), for parity checks and variance
+ * studies: path_value_dev[i] = total contribution of path path_offset + i
+ * (device float[n_paths], overwritten).  Same kernel as the render. */
+int darts_render_paths(const darts_scene *scene, const darts_params *params,
+                       const darts_table *table, float *path_value_dev, void *stream);
+
+/* Gradient of L = sum_c grad_image[c] * I[c] (I the raw per-cell sums the
+ * render call would add) with respect to (sigma_s, sigma_a, g), by replaying
+ * the same paths (same ids, same Philox counters; nothing is stored between
+ * the calls) and weighting each contribution with the derivative of the log
+ * of its path throughput (detached sampling).  grad_image_dev: device
+ * float[n_bins][height][width]; grad_out_dev: device double[3],
+ * accumulate-into.  DARTS family only. */
+int darts_render_transient_backward(const darts_scene *scene, const darts_params *params,
+                                    const darts_table *table, const float *grad_image_dev,
+                                    double *grad_out_dev, void *stream);
+
+/* Diagnostic: evaluate one device building block on n items (one thread per
+ * item) with the same device functions the render kernel uses.  in_dev:
+ * float[n][DARTS_PW_IN] (32-bit integers are passed by bit pattern), out_dev:
+ * float[n][DARTS_PW_OUT]; per-function layouts are listed with the ids.
+ * medium / table may be NULL for functions that do not use them. */
+#define DARTS_PW_IN  16
+#define DARTS_PW_OUT 8
+enum {
+    DARTS_PW_PHILOX = 0,  /* in: ctr[4], key[2] (bits)   out: x[4] (bits)              */
+    DARTS_PW_HG_PDF,      /* in: mu, g                   out: pdf                      */
+    DARTS_PW_HG_SAMPLE,   /* in: xi, g                   out: mu, sin(theta)           */
+    DARTS_PW_DA_LOGPHI,   /* in: r, s                    out: log Phi (medium)         */
+    DARTS_PW_TEXP,        /* in: u, sigma, width         out: x, pdf(x)                */
+    DARTS_PW_ELLIPSE,     /* in: S, C, mu, pS            out: t, r, p_t                */
+    DARTS_PW_SOBOL,       /* in: row, col, eps (bits)    out: u                        */
+    DARTS_PW_ONB,         /* in: n[3]                    out: b1[3], b2[3]             */
+    DARTS_PW_BOX_EXIT,    /* in: x[3], w[3], lo[3], hi[3] out: distance                */
+    DARTS_PW_RIS,         /* in: x[3], w[3], xe[3], R_hi, d_m, row (bits), eps (bits),
+                                 u_sel                   out: ok, d, factor (medium)   */
+    DARTS_PW_DIRECTION,   /* in: x[3], xe[3], w_prev[3], S, u[4], use_eda, alpha
+                                                         out: w[3], weight, eda_branch
+                                                         (medium, table)               */
+    DARTS_PW_COUNT
+};
+int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n,
+                          const darts_medium *medium, const darts_table *table, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *darts_last_error(void);
+
+/* ABI version of this header (incremented on incompatible change). */
+#define DARTS_ABI_VERSION 1
+int darts_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DARTS_H */

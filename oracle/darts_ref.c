@@ -810,6 +810,27 @@ int ref_render_paths(const ref_scene *sc, const ref_params *pr,
     return 0;
 }
 
+int ref_render_path_list(const ref_scene *sc, const ref_params *pr,
+                         const ref_table_dims *dims, const float *cdf,
+                         const uint64_t *ids, int64_t n, double *path_value, int n_threads)
+{
+    if (check_args(sc, pr)) return -1;
+    if (pr->flags & (REF_DIRECT_REUSE | REF_FORWARD)) return -1;
+    if ((pr->flags & REF_EDA_DIR) && (!cdf || !dims)) return -1;
+    int nt = nthreads_eff(n_threads);
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        ref_stats S;
+        memset(&S, 0, sizeof S);
+        int64_t cell;
+        path_value[i] = trace_darts(sc, pr, dims, cdf, ids[i], &cell, &S);
+    }
+    (void)nt;
+    return 0;
+}
+
 int ref_render_transient(const ref_scene *sc, const ref_params *pr,
                          const ref_table_dims *dims, const float *cdf,
                          double *image, double *m2, uint64_t *stats, int n_threads)

@@ -152,6 +152,11 @@ int ref_render_paths(const ref_scene *sc, const ref_params *pr,
                      const ref_table_dims *dims, const float *cdf,
                      double *path_value, int64_t *path_cell, int n_threads);
 
+/* Per-path contributions for an explicit list of path ids. */
+int ref_render_path_list(const ref_scene *sc, const ref_params *pr,
+                         const ref_table_dims *dims, const float *cdf,
+                         const uint64_t *ids, int64_t n, double *path_value, int n_threads);
+
 /* Detached-sampling gradient of L = sum_cells grad_image[cell] * I[cell]
  * with respect to (sigma_s, sigma_a, g): raw sums over paths (divide by the
  * same per-cell path counts as the image). grad_out[3]. */

@@ -134,6 +134,10 @@ def lib():
         L.ref_render_paths.restype = C.c_int
         L.ref_render_paths.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
                                        C.POINTER(C.c_float), pd, C.POINTER(C.c_int64), C.c_int]
+        L.ref_render_path_list.restype = C.c_int
+        L.ref_render_path_list.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
+                                           C.POINTER(C.c_float), C.POINTER(C.c_uint64), C.c_int64, pd,
+                                           C.c_int]
         L.ref_render_gradient.restype = C.c_int
         L.ref_render_gradient.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
                                           C.POINTER(C.c_float), pd, pd, C.c_int]
@@ -262,6 +266,24 @@ def render_paths(sc: dict, p: dict, mode: str, table=None, dims_: dict | None = 
     if rc:
         raise ValueError(f"ref_render_paths failed: {rc}")
     return val, cell
+
+
+def render_path_list(sc: dict, p: dict, mode: str, ids, table=None, dims_: dict | None = None,
+                     n_threads: int = 0):
+    """Per-path contributions of the given path ids (DARTS family)."""
+    holder = _SceneHolder(sc)
+    pr = params(p, mode)
+    ids = np.ascontiguousarray(ids, np.uint64)
+    val = np.zeros(len(ids), np.float64)
+    cdf = None if table is None else np.ascontiguousarray(table, np.float32)
+    dptr = C.byref(dims(dims_)) if (cdf is not None) else None
+    cptr = cdf.ctypes.data_as(C.POINTER(C.c_float)) if cdf is not None else None
+    rc = lib().ref_render_path_list(C.byref(holder.c), C.byref(pr), dptr, cptr,
+                                    ids.ctypes.data_as(C.POINTER(C.c_uint64)), len(ids),
+                                    val.ctypes.data_as(C.POINTER(C.c_double)), int(n_threads))
+    if rc:
+        raise ValueError(f"ref_render_path_list failed: {rc}")
+    return val
 
 
 def render_gradient(sc: dict, p: dict, mode: str, grad_image, table=None, dims_=None, n_threads=0):

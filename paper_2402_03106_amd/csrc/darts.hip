@@ -1,0 +1,885 @@
+// libdarts: gfx950 kernels and the C ABI declared in include/darts.h.
+//
+// Hot path (one launch per call):  every lane owns one image cell and a
+// contiguous chunk of that cell's paths (ids c + m * n_cells) and runs them
+// back to back in a path-regeneration loop; per-path sums stay in registers
+// and each lane flushes one compensated FP32 atomic pair at the end.  Lanes of
+// a wave own consecutive cells of the same time bin, so their paths have
+// similar lengths, and blocks are ordered latest bin first so the long paths
+// start first.
+#include "../../include/darts.h"
+#include "darts_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace darts;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok()
+{
+    g_last_error.clear();
+    return DARTS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel parameter block (passed by value in the kernarg segment).
+// ---------------------------------------------------------------------------
+struct KParams {
+    Medium med;
+    int box;                    // 0 infinite, 1 box
+    Box bx;
+    int n_em;
+    float em_pos[DARTS_MAX_EMITTERS][3];
+    float em_start[DARTS_MAX_EMITTERS];
+    float em_scale[DARTS_MAX_EMITTERS];  // power / (4 pi) * n_em
+    int sensor_kind;
+    float origin[3], dir[3], du[3], dv[3];
+    int width, height;
+    float beta0;
+    float l_lo, l_hi, delta;
+    int n_bins;
+    uint64_t path_offset, n_paths;
+    uint32_t key0, key1;
+    int max_bounces;
+    float alpha;
+    unsigned flags;
+    int64_t npix, ncells;
+    // work decomposition: launch covers ids [q0*ncells + r0, q1*ncells + r1)
+    uint64_t q0, r0, q1, r1;
+    uint64_t n_items;
+    uint64_t chunk;
+    Table tb;
+    float *hi, *lo, *m2;
+    unsigned long long *stats;
+    float *path_out;
+    const float *grad_image;
+    double *grad_out;
+};
+
+constexpr int kBlock = 256;
+constexpr uint32_t kCameraVertex = 0xFFFFFFFFu;
+
+enum { OUT_IMAGE = 0, OUT_PATHS = 1, OUT_GRAD = 2 };
+
+struct Stats {
+    uint32_t v[DARTS_ST_COUNT];
+};
+
+// Per-path state carried across vertices.
+struct PathState {
+    V3 x, w;          // vertex and walk direction
+    float beta;       // throughput / pdf
+    float Le;         // length travelled from the sensor
+    float G_lo, G_hi; // target interval for the total path length
+    float C;          // distance to the emitter
+    float dm;         // distance to the boundary along w (inf: infinite medium)
+    int k;            // vertex index
+    int em;           // emitter index
+    float acc;        // sum of this path's contributions
+    // derivative bookkeeping for the backward pass (detached sampling)
+    float L_med;      // in-medium length walked so far
+    float dlog_g;     // sum of d log f_HG / dg over walk vertices so far
+};
+
+__device__ __forceinline__ V3 em_pos(const KParams &P, int j)
+{
+    return V3{P.em_pos[j][0], P.em_pos[j][1], P.em_pos[j][2]};
+}
+
+__device__ __forceinline__ float dlog_hg_dg(float mu, float g)
+{
+    // d/dg log[(1 - g^2)(1 + g^2 - 2 g mu)^{-3/2}]
+    return -2.f * g / (1.f - g * g) + 3.f * (mu - g) / fmaf(-2.f * g, mu, fmaf(g, g, 1.f));
+}
+
+// Path set-up (Section III; Section V-A: the target interval is fixed per
+// path by the stratified cell map).  Returns false if the path cannot
+// contribute (camera ray misses the medium, or nothing reachable).
+__device__ bool setup_path(const KParams &P, uint64_t p, int64_t bin, int px, int py,
+                           PathState &s, Stats &st, bool vanilla)
+{
+    const U4 r = philox((uint32_t)p, (uint32_t)(p >> 32), kCameraVertex, 0u, P.key0, P.key1);
+    const float u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z);
+    V3 pos, w;
+    if (P.sensor_kind == 1) {
+        const float fu = ((float)px + u0) / (float)P.width, fv = ((float)py + u1) / (float)P.height;
+        pos = V3{P.origin[0] + fu * P.du[0] + fv * P.dv[0], P.origin[1] + fu * P.du[1] + fv * P.dv[1],
+                 P.origin[2] + fu * P.du[2] + fv * P.dv[2]};
+        w = V3{P.dir[0], P.dir[1], P.dir[2]};
+    } else {
+        pos = V3{P.origin[0], P.origin[1], P.origin[2]};
+        const float mu = 1.f - 2.f * u0;
+        const float sn = sqrtf(fmaxf((1.f - mu) * (1.f + mu), 0.f));
+        float sp, cp;
+        sincospif(2.f * u1, &sp, &cp);
+        w = V3{sn * cp, sn * sp, mu};
+    }
+    int j = (int)(u2 * (float)P.n_em);
+    j = min(j, P.n_em - 1);
+    s.em = j;
+    s.beta = P.beta0;
+    s.k = 0;
+    s.acc = 0.f;
+    s.L_med = 0.f;
+    s.dlog_g = 0.f;
+    if (vanilla) {
+        s.G_lo = P.l_lo - P.em_start[j];
+        s.G_hi = P.l_hi - P.em_start[j];
+    } else {
+        s.G_lo = fmaf((float)bin, P.delta, P.l_lo) - P.em_start[j];
+        s.G_hi = fmaf((float)(bin + 1), P.delta, P.l_lo) - P.em_start[j];
+    }
+    st.v[DARTS_ST_PATHS]++;
+    float t_in = 0.f, t_out = kInf;
+    if (P.box) {
+        if (!box_entry(P.bx, pos, w, t_in, t_out)) return false;
+    }
+    s.x = fma3(pos, w, t_in);
+    s.w = w;
+    s.Le = t_in;
+    s.dm = P.box ? t_out - t_in : kInf;
+    s.C = length(em_pos(P, j) - s.x);
+    st.v[DARTS_ST_VERTICES]++;
+    if (s.G_hi - s.Le <= s.C) { st.v[DARTS_ST_EARLY_EXIT]++; return false; }
+    return true;
+}
+
+// Generalised shadow connection through a control vertex on the current ray
+// (Section V-B, case I, with the boundary clipping S_M): samples the length
+// sum S in [max(R_lo, C), min(R_hi, S_exit)), places the control vertex at
+// the polar distance t(S) (Eq. (21)) and weights it with p(t) = p(S) (S - C
+// mu)/(S - t) (Eq. (22), Jacobian taken as the text defines it).
+// Returns the contribution; dlog (if not null) receives the derivative of
+// the log path throughput w.r.t. (sigma_s, sigma_a, g) of the connected path.
+__device__ float connect(const KParams &P, const PathState &s, float u4, float *dlog)
+{
+    const V3 xe = em_pos(P, s.em);
+    const V3 de = xe - s.x;
+    const float C = s.C;
+    if (!(C > 0.f)) return 0.f;
+    const float b = dot(s.w, de);
+    const float cm = fmaxf(C - b, 0.f);
+    const float R_lo = s.G_lo - s.Le, R_hi = s.G_hi - s.Le;
+    float S_exit = kInf;
+    if (P.box) S_exit = s.dm + length(fma3(s.x, s.w, s.dm) - xe);
+    const float S_lo = fmaxf(R_lo, C), S_hi = fminf(R_hi, S_exit);
+    if (!(S_lo < S_hi)) return 0.f;
+    const float W = S_hi - S_lo;
+    const Medium &m = P.med;
+    const bool texp = (P.flags & DARTS_ELL_TEXP) != 0;
+    float S, mass = 0.f;
+    if (texp) {
+        mass = texp_mass(m.sigma_t, W);
+        S = S_lo + texp_sample(u4, m.inv_sigma_t, mass, expf(-m.sigma_t * W));
+    } else {
+        S = fmaf(u4, W, S_lo);
+    }
+    float den, t, r;
+    ellipse(S, C, cm, den, t, r);
+    if (!(den > 0.f) || !(r > 0.f)) return 0.f;
+    const V3 xc = fma3(s.x, s.w, t);
+    const V3 wc = (xe - xc) * (1.f / r);
+    const float r_in = P.box ? fminf(r, box_exit(P.bx, xc, wc)) : r;
+    const float mu_c = dot(s.w, wc);
+    const float f = hg_pdf(mu_c, m.g);
+    const float scale = s.beta * P.em_scale[s.em] * f / (r * den);
+    float c;
+    if (texp) {
+        // e^{-sigma_t (t + r_in)} / p(S) = (mass / sigma_t) e^{-sigma_t (S_lo - (r - r_in))}
+        c = scale * m.albedo * mass * __expf(-m.sigma_t * (S_lo - (r - r_in)));
+    } else {
+        c = scale * m.sigma_s * W * __expf(-m.sigma_t * (t + r_in));
+    }
+    if (dlog) {
+        const float Lm = s.L_med + t + r_in;               // in-medium length
+        const float n = (float)(s.k + 1);                  // scattering vertices
+        dlog[0] = n / m.sigma_s - Lm;
+        dlog[1] = -Lm;
+        dlog[2] = s.dlog_g + dlog_hg_dg(mu_c, m.g);
+    }
+    return c;
+}
+
+// One vertex of the DARTS family: connection at vertex k, then free flight
+// (medium-event Bernoulli, Eq. (12); DA-RIS or exponential distance), the
+// early-exit test at the new vertex and direction sampling there.  Returns
+// false when the path has ended.
+template <int OUT>
+__device__ bool step_darts(const KParams &P, uint64_t p, PathState &s, Stats &st, float grad_w, double *gacc)
+{
+    const Medium &m = P.med;
+    const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
+    float dl[3];
+    const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD ? dl : nullptr);
+    if (c != 0.f) {
+        st.v[DARTS_ST_CONNECTIONS]++;
+        s.acc += c;
+        if (OUT == OUT_GRAD) {
+            const double cw = (double)c * (double)grad_w;
+            gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
+        }
+    }
+    if (s.k == P.max_bounces - 1) { st.v[DARTS_ST_TRUNCATED]++; return false; }
+    const float pc = P.box ? texp_mass(m.sigma_t, s.dm) : 1.f;
+    const float u5 = u01(r1.y);
+    if (!(u5 < pc)) { st.v[DARTS_ST_MEDIUM_EXIT]++; return false; }
+    const V3 xe = em_pos(P, s.em);
+    float d, factor;
+    if (P.flags & DARTS_RIS_DIST) {
+        const V3 de = xe - s.x;
+        const float epc = P.box ? expf(-m.sigma_t * s.dm) : 0.f;
+        if (!ris_distance(m, s.C * s.C, dot(s.w, de), s.G_hi - s.Le, pc, epc, r1.y & 31u, r1.z, u01(r1.w), d,
+                          factor)) {
+            st.v[DARTS_ST_RIS_ALL_INVALID]++;
+            return false;
+        }
+    } else {
+        d = texp_sample(u5, m.inv_sigma_t, 1.f, 0.f);   // plain exponential, given u5 < pc
+        factor = m.albedo;
+    }
+    s.x = fma3(s.x, s.w, d);
+    s.Le += d;
+    s.L_med += d;
+    s.beta *= factor;
+    s.k += 1;
+    const V3 de = xe - s.x;
+    s.C = length(de);
+    st.v[DARTS_ST_VERTICES]++;
+    const float R_hi = s.G_hi - s.Le;
+    if (R_hi <= s.C) { st.v[DARTS_ST_EARLY_EXIT]++; return false; }
+    const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 0u, P.key0, P.key1);
+    float weight;
+    bool eb;
+    const V3 wp = s.w;
+    s.w = sample_direction(m, P.tb, P.alpha, (P.flags & DARTS_EDA_DIR) != 0, de * (1.f / s.C), s.C, R_hi,
+                           wp, r0, weight, eb);
+    if (OUT == OUT_GRAD) s.dlog_g += dlog_hg_dg(dot(wp, s.w), m.g);
+    st.v[DARTS_ST_EDA_BRANCH] += eb ? 1u : 0u;
+    s.beta *= weight;
+    s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
+    return true;
+}
+
+__device__ __forceinline__ void add_compensated(float *hi, float *lo, int64_t i, float v, float v_lo)
+{
+    const float old = unsafeAtomicAdd(hi + i, v);
+    const float e = two_sum_err(old, v, old + v);
+    const float tot = e + v_lo;
+    if (tot != 0.f) unsafeAtomicAdd(lo + i, tot);
+}
+
+// Vanilla transient path tracing (the paper's baseline): exponential free
+// flight, phase sampling, a shadow connection at every medium vertex, each
+// connection binned by its total length.
+__device__ bool step_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathState &s, Stats &st)
+{
+    const Medium &m = P.med;
+    const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
+    const float pc = P.box ? texp_mass(m.sigma_t, s.dm) : 1.f;
+    const float u5 = u01(r1.y);
+    if (!(u5 < pc)) { st.v[DARTS_ST_MEDIUM_EXIT]++; return false; }
+    const float d = texp_sample(u5, m.inv_sigma_t, 1.f, 0.f);
+    s.x = fma3(s.x, s.w, d);
+    s.Le += d;
+    s.beta *= m.albedo;
+    s.k += 1;
+    const V3 xe = em_pos(P, s.em);
+    const V3 de = xe - s.x;
+    const float r = length(de);
+    s.C = r;
+    {
+        const V3 wc = de * (1.f / r);
+        const float r_in = P.box ? fminf(r, box_exit(P.bx, s.x, wc)) : r;
+        const float L = s.Le + r + P.em_start[s.em];
+        const int bin = (int)floorf((L - P.l_lo) / P.delta);
+        if (L >= P.l_lo && bin >= 0 && bin < P.n_bins) {
+            const float v = s.beta * P.em_scale[s.em] * hg_pdf(dot(s.w, wc), m.g) * __expf(-m.sigma_t * r_in) / (r * r);
+            const int64_t cell = (int64_t)bin * P.npix + pixel;
+            add_compensated(P.hi, P.lo, cell, v, 0.f);
+            if (P.m2) unsafeAtomicAdd(P.m2 + cell, v * v);
+            st.v[DARTS_ST_CONNECTIONS]++;
+            s.acc += v;
+        }
+    }
+    if (s.k == P.max_bounces) { st.v[DARTS_ST_TRUNCATED]++; return false; }
+    st.v[DARTS_ST_VERTICES]++;
+    if (s.G_hi - s.Le <= s.C) { st.v[DARTS_ST_EARLY_EXIT]++; return false; }
+    const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 0u, P.key0, P.key1);
+    float mu, sn;
+    hg_sample(u01(r0.y), m.g, mu, sn);
+    s.w = from_frame(s.w, mu, sn, u01(r0.z));
+    s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
+    return true;
+}
+
+template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS>
+__global__ __launch_bounds__(kBlock) void render_kernel(KParams P)
+{
+    const uint64_t w = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool have = w < P.n_items;
+    const int64_t cp = have ? (int64_t)(w % (uint64_t)P.ncells) : 0;
+    const int64_t c = P.ncells - 1 - cp;          // latest time bin first
+    const uint64_t j = have ? w / (uint64_t)P.ncells : 0;
+    const uint64_t m_lo = P.q0 + ((uint64_t)c < P.r0 ? 1 : 0);
+    const uint64_t m_hi = P.q1 + ((uint64_t)c < P.r1 ? 1 : 0);
+    uint64_t m = m_lo + j * P.chunk;
+    uint64_t m_end = have ? min(m + P.chunk, m_hi) : m;
+    const int64_t bin = c / P.npix;
+    const int64_t pixel = c - bin * P.npix;
+    const int px = (int)(pixel % P.width), py = (int)(pixel / P.width);
+    const float grad_w = (OUT == OUT_GRAD && have) ? P.grad_image[c] : 0.f;
+
+    Stats st;
+#pragma unroll
+    for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
+    PathState s;
+    bool alive = false;
+    uint64_t p = 0;
+    float lane_hi = 0.f, lane_lo = 0.f, lane_m2 = 0.f;
+    double gacc[3] = {0.0, 0.0, 0.0};
+
+    while (true) {
+        if (!alive) {
+            if (m >= m_end) break;
+            p = (uint64_t)c + m * (uint64_t)P.ncells;
+            ++m;
+            alive = setup_path(P, p, bin, px, py, s, st, MODE == 1);
+            if (!alive) {
+                st.v[DARTS_ST_ZERO_PATHS]++;
+                if (OUT == OUT_PATHS) P.path_out[p - P.path_offset] = 0.f;
+                continue;
+            }
+        }
+        if (MODE == 1) alive = step_vanilla(P, p, pixel, s, st);
+        else alive = step_darts<OUT>(P, p, s, st, grad_w, gacc);
+        if (!alive) {
+            if (s.acc == 0.f) st.v[DARTS_ST_ZERO_PATHS]++;
+            if (MODE == 0) {
+                if (OUT == OUT_PATHS) {
+                    P.path_out[p - P.path_offset] = s.acc;
+                } else if (OUT == OUT_IMAGE) {
+                    const float ns = lane_hi + s.acc;
+                    lane_lo += two_sum_err(lane_hi, s.acc, ns);
+                    lane_hi = ns;
+                    lane_m2 = fmaf(s.acc, s.acc, lane_m2);
+                }
+            }
+        }
+    }
+
+    if (MODE == 0 && OUT == OUT_IMAGE && have) {
+        if (lane_hi != 0.f || lane_lo != 0.f) add_compensated(P.hi, P.lo, c, lane_hi, lane_lo);
+        if (P.m2 && lane_m2 != 0.f) unsafeAtomicAdd(P.m2 + c, lane_m2);
+    }
+    if (OUT == OUT_GRAD) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double v = gacc[i];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if ((threadIdx.x & 63) == 0 && v != 0.0) unsafeAtomicAdd(P.grad_out + i, v);
+        }
+    }
+    if (STATS) {
+#pragma unroll
+        for (int i = 0; i < DARTS_ST_ZERO_PATHS + 1; ++i) {
+            uint32_t v = st.v[i];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if ((threadIdx.x & 63) == 0 && v) atomicAdd(P.stats + i, (unsigned long long)v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Elliptical-DA table (Section V-A, Eq. (16)-(18)), FP64.
+// One block (one wave) per (C/S, S) cell; lane k integrates cos-bin k with
+// the fixed Gauss-Legendre rule; lane 0 normalises the row and writes the
+// float cumulative sums.
+// ---------------------------------------------------------------------------
+constexpr int kGLU = 4, kGLV = 64;
+
+struct TParams {
+    double sigma_s, sigma_a, sigma_t, albedo, D;
+    int n_cs, n_s, n_cos;
+    double s_max;
+    double xu[kGLU], wu[kGLU], xv[kGLV], wv[kGLV];
+    float *cdf;
+};
+
+__device__ double da_phi64(const TParams &T, double r2, double s)
+{
+    if (!(s > 0.0)) return 0.0;
+    const double fds = 4.0 * M_PI * T.D * s;
+    return exp(-r2 / (4.0 * T.D * s) - T.sigma_a * s) / (fds * sqrt(fds));
+}
+
+__global__ __launch_bounds__(64) void table_kernel(TParams T)
+{
+    extern __shared__ double row[];
+    const int cell = blockIdx.x;
+    const int i = cell / T.n_s, j = cell % T.n_s;
+    const double kappa = (i + 0.5) / T.n_cs;
+    const double S = (j + 0.5) * T.s_max / T.n_s;
+    const double C = kappa * S;
+    const double h = 2.0 / T.n_cos;
+    for (int k = threadIdx.x; k < T.n_cos; k += blockDim.x) {
+        const double ulo = -1.0 + k * h;
+        double acc = 0.0;
+        for (int a = 0; a < kGLU; ++a) {
+            const double u = ulo + 0.5 * h * (T.xu[a] + 1.0);
+            const double tM = (S * S - C * C) / (2.0 * S - 2.0 * C * u);   // Eq. (18)
+            const double pM = -expm1(-T.sigma_t * tM);
+            double inner = 0.0;
+            for (int bq = 0; bq < kGLV; ++bq) {
+                const double v = 0.5 * (T.xv[bq] + 1.0);
+                const double t = -log1p(-v * pM) / T.sigma_t;
+                const double r2 = fmax(t * t + C * C - 2.0 * t * C * u, 0.0);
+                inner += 0.5 * T.wv[bq] * da_phi64(T, r2, S - t);
+            }
+            acc += 0.5 * h * T.wu[a] * T.albedo * pM * inner;
+        }
+        row[k] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < T.n_cos; ++k) tot += row[k];
+        const bool good = isfinite(tot) && tot > 0.0;
+        float *out = T.cdf + (size_t)cell * (T.n_cos + 1);
+        double run = 0.0;
+        out[0] = 0.f;
+        for (int k = 0; k < T.n_cos; ++k) {
+            run += good ? row[k] / tot : 1.0 / T.n_cos;
+            out[k + 1] = (float)run;
+        }
+        out[T.n_cos] = 1.f;
+    }
+}
+
+// Gauss-Legendre nodes on [-1, 1]: Newton's method on P_n from Tricomi's
+// asymptotic initial guess, P_n and P_n' by the three-term recurrence.
+void gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 1; i <= n; ++i) {
+        const double th = M_PI * (4.0 * i - 1.0) / (4.0 * n + 2.0);
+        double z = (1.0 - (n - 1.0) / (8.0 * n * n * n)) * std::cos(th);
+        double pn = 0.0, dpn = 1.0;
+        for (int it = 0; it < 64; ++it) {
+            double pm1 = 1.0, p = z;
+            for (int k = 1; k < n; ++k) {
+                const double pp1 = ((2.0 * k + 1.0) * z * p - k * pm1) / (k + 1.0);
+                pm1 = p;
+                p = pp1;
+            }
+            pn = p;
+            dpn = n * (pm1 - z * p) / (1.0 - z * z);
+            const double step = pn / dpn;
+            z -= step;
+            if (std::fabs(step) <= 1e-17) break;
+        }
+        double pm1 = 1.0, p = z;
+        for (int k = 1; k < n; ++k) {
+            const double pp1 = ((2.0 * k + 1.0) * z * p - k * pm1) / (k + 1.0);
+            pm1 = p;
+            p = pp1;
+        }
+        dpn = n * (pm1 - z * p) / (1.0 - z * z);
+        x[i - 1] = z;
+        w[i - 1] = 2.0 / ((1.0 - z * z) * dpn * dpn);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise diagnostics.
+// ---------------------------------------------------------------------------
+struct PWParams {
+    int fn;
+    int64_t n;
+    const float *in;
+    float *out;
+    Medium med;
+    Table tb;
+};
+
+__device__ __forceinline__ uint32_t bits(float f) { return __float_as_uint(f); }
+
+__global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= Q.n) return;
+    const float *a = Q.in + i * DARTS_PW_IN;
+    float *o = Q.out + i * DARTS_PW_OUT;
+    switch (Q.fn) {
+    case DARTS_PW_PHILOX: {
+        const U4 r = philox(bits(a[0]), bits(a[1]), bits(a[2]), bits(a[3]), bits(a[4]), bits(a[5]));
+        o[0] = __uint_as_float(r.x); o[1] = __uint_as_float(r.y);
+        o[2] = __uint_as_float(r.z); o[3] = __uint_as_float(r.w);
+        break;
+    }
+    case DARTS_PW_HG_PDF: o[0] = hg_pdf(a[0], a[1]); break;
+    case DARTS_PW_HG_SAMPLE: hg_sample(a[0], a[1], o[0], o[1]); break;
+    case DARTS_PW_DA_LOGPHI: o[0] = da_log_phi_rel(Q.med, a[0] * a[0], a[1]); break;
+    case DARTS_PW_TEXP: {
+        const float mass = texp_mass(a[1], a[2]);
+        const float x = texp_sample(a[0], 1.f / a[1], mass, expf(-a[1] * a[2]));
+        o[0] = x;
+        o[1] = a[1] * __expf(-a[1] * x) / mass;
+        break;
+    }
+    case DARTS_PW_ELLIPSE: {
+        float den, t, r;
+        const float S = a[0], C = a[1], mu = a[2];
+        ellipse(S, C, C * (1.f - mu), den, t, r);
+        o[0] = t; o[1] = r; o[2] = a[3] * den / r;
+        break;
+    }
+    case DARTS_PW_SOBOL: o[0] = sobol_u(bits(a[0]), bits(a[1]), bits(a[2])); break;
+    case DARTS_PW_ONB: {
+        V3 b1, b2;
+        onb(V3{a[0], a[1], a[2]}, b1, b2);
+        o[0] = b1.x; o[1] = b1.y; o[2] = b1.z; o[3] = b2.x; o[4] = b2.y; o[5] = b2.z;
+        break;
+    }
+    case DARTS_PW_BOX_EXIT: {
+        Box b{{a[6], a[7], a[8]}, {a[9], a[10], a[11]}};
+        o[0] = box_exit(b, V3{a[0], a[1], a[2]}, V3{a[3], a[4], a[5]});
+        break;
+    }
+    case DARTS_PW_RIS: {
+        const V3 x{a[0], a[1], a[2]}, w{a[3], a[4], a[5]}, xe{a[6], a[7], a[8]};
+        const float R_hi = a[9], d_m = a[10];
+        const V3 de = xe - x;
+        const float C = length(de);
+        const float pc = isinf(d_m) ? 1.f : texp_mass(Q.med.sigma_t, d_m);
+        const float epc = isinf(d_m) ? 0.f : expf(-Q.med.sigma_t * d_m);
+        float d = 0.f, f = 0.f;
+        const bool okk = ris_distance(Q.med, C * C, dot(w, de), R_hi, pc, epc, bits(a[11]) & 31u, bits(a[12]), a[13],
+                                      d, f);
+        o[0] = okk ? 1.f : 0.f; o[1] = d; o[2] = f;
+        break;
+    }
+    case DARTS_PW_DIRECTION: {
+        const V3 x{a[0], a[1], a[2]}, xe{a[3], a[4], a[5]}, wp{a[6], a[7], a[8]};
+        const float S = a[9];
+        const U4 r{bits(a[10]), bits(a[11]), bits(a[12]), bits(a[13])};
+        const V3 de = xe - x;
+        const float C = length(de);
+        float wt;
+        bool eb;
+        const V3 w = sample_direction(Q.med, Q.tb, a[15], a[14] != 0.f, de * (1.f / C), C, S, wp, r, wt, eb);
+        o[0] = w.x; o[1] = w.y; o[2] = w.z; o[3] = wt; o[4] = eb ? 1.f : 0.f;
+        break;
+    }
+    default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side validation and parameter set-up.
+// ---------------------------------------------------------------------------
+int check_medium(const darts_medium *m)
+{
+    if (!m) return fail(DARTS_ERR_INVALID_ARG, "medium is null");
+    if (!(m->sigma_s >= 0.0) || !(m->sigma_a >= 0.0) || !(m->sigma_s + m->sigma_a > 0.0) ||
+        !std::isfinite(m->sigma_s) || !std::isfinite(m->sigma_a))
+        return fail(DARTS_ERR_INVALID_ARG, "need sigma_s, sigma_a >= 0 and sigma_s + sigma_a > 0");
+    if (!(std::fabs(m->g) < 1.0)) return fail(DARTS_ERR_INVALID_ARG, "need |g| < 1");
+    return DARTS_OK;
+}
+
+int check_dims(const darts_table_dims *d)
+{
+    if (!d) return fail(DARTS_ERR_INVALID_ARG, "table dims are null");
+    if (d->n_cs <= 0 || d->n_s <= 0 || d->n_cos <= 0 || d->n_cos > DARTS_MAX_COS_BINS || !(d->s_max > 0.f) ||
+        !std::isfinite(d->s_max))
+        return fail(DARTS_ERR_INVALID_ARG, "table dims must be positive, n_cos <= %d, s_max > 0",
+                    DARTS_MAX_COS_BINS);
+    if ((int64_t)d->n_cs * d->n_s > (1 << 26)) return fail(DARTS_ERR_INVALID_ARG, "table too large");
+    return DARTS_OK;
+}
+
+Medium make_medium(const darts_medium &m)
+{
+    Medium o;
+    o.sigma_s = (float)m.sigma_s;
+    o.sigma_a = (float)m.sigma_a;
+    o.sigma_t = (float)(m.sigma_s + m.sigma_a);
+    o.inv_sigma_t = (float)(1.0 / (m.sigma_s + m.sigma_a));
+    o.albedo = (float)(m.sigma_s / (m.sigma_s + m.sigma_a));
+    o.g = (float)m.g;
+    const double D = 1.0 / (3.0 * (m.sigma_a + m.sigma_s * (1.0 - m.g)));
+    o.inv4D = (float)(1.0 / (4.0 * D));
+    return o;
+}
+
+bool same_medium(const darts_medium &a, const darts_medium &b)
+{
+    return a.sigma_s == b.sigma_s && a.sigma_a == b.sigma_a && a.g == b.g;
+}
+
+int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &tb)
+{
+    tb = Table{nullptr, 1, 1, 1, 0.f};
+    if (!needed) return DARTS_OK;
+    if (!t || !t->cdf_dev) return fail(DARTS_ERR_INVALID_ARG, "EDA direction sampling needs a built table");
+    if (int rc = check_dims(&t->dims)) return rc;
+    if (sc && !same_medium(t->medium, sc->medium))
+        return fail(DARTS_ERR_TABLE_MISMATCH, "table was built for another medium");
+    tb.cdf = t->cdf_dev;
+    tb.n_cs = t->dims.n_cs;
+    tb.n_s = t->dims.n_s;
+    tb.n_cos = t->dims.n_cos;
+    tb.ns_over_smax = (float)t->dims.n_s / t->dims.s_max;
+    return DARTS_OK;
+}
+
+int64_t g_target_lanes = 1 << 20;
+
+int make_params(const darts_scene *sc, const darts_params *pr, const darts_table *table, KParams &P,
+                bool per_path_only)
+{
+    if (!sc || !pr) return fail(DARTS_ERR_INVALID_ARG, "scene or params is null");
+    if (int rc = check_medium(&sc->medium)) return rc;
+    if (sc->n_emitters < 1 || sc->n_emitters > DARTS_MAX_EMITTERS || !sc->emitters)
+        return fail(DARTS_ERR_INVALID_ARG, "need 1..%d emitters", DARTS_MAX_EMITTERS);
+    if (sc->bins.n_bins <= 0 || !(sc->bins.l_hi > sc->bins.l_lo) || !std::isfinite(sc->bins.l_lo) ||
+        !std::isfinite(sc->bins.l_hi))
+        return fail(DARTS_ERR_INVALID_ARG, "bins need n_bins > 0 and l_hi > l_lo");
+    const darts_sensor &sn = sc->sensor;
+    if (sn.kind != 0 && sn.kind != 1) return fail(DARTS_ERR_INVALID_ARG, "sensor kind must be 0 or 1");
+    if (sn.width <= 0 || sn.height <= 0) return fail(DARTS_ERR_INVALID_ARG, "sensor size must be positive");
+    if (sn.kind == 0 && (sn.width != 1 || sn.height != 1))
+        return fail(DARTS_ERR_INVALID_ARG, "point detector has width = height = 1");
+    if (sc->geom.kind != 0 && sc->geom.kind != 1) return fail(DARTS_ERR_INVALID_ARG, "geometry kind must be 0 or 1");
+    if (sc->geom.kind == 1)
+        for (int a = 0; a < 3; ++a)
+            if (!(sc->geom.hi[a] > sc->geom.lo[a])) return fail(DARTS_ERR_INVALID_ARG, "box needs hi > lo");
+    if (pr->max_bounces < 1) return fail(DARTS_ERR_INVALID_ARG, "max_bounces must be >= 1");
+    if (pr->n_ris != 8) return fail(DARTS_ERR_UNSUPPORTED, "this build implements n_ris = 8 (the paper's choice)");
+    if (!(pr->alpha >= 0.f)) return fail(DARTS_ERR_INVALID_ARG, "alpha must be >= 0");
+    const unsigned f = pr->flags;
+    if (f & ~(DARTS_RIS_DIST | DARTS_EDA_DIR | DARTS_ELL_TEXP | DARTS_ELL_UNIFORM | DARTS_DIRECT_REUSE))
+        return fail(DARTS_ERR_INVALID_ARG, "unknown flag bits 0x%x", f);
+    const bool vanilla = (f & DARTS_DIRECT_REUSE) != 0;
+    if (vanilla && (f != DARTS_DIRECT_REUSE))
+        return fail(DARTS_ERR_INVALID_ARG, "DIRECT_REUSE (vanilla) excludes the other strategy bits");
+    if (!vanilla && (((f & DARTS_ELL_TEXP) != 0) == ((f & DARTS_ELL_UNIFORM) != 0)))
+        return fail(DARTS_ERR_INVALID_ARG, "exactly one of ELL_TEXP / ELL_UNIFORM");
+    if (per_path_only && vanilla) return fail(DARTS_ERR_UNSUPPORTED, "per-path output needs the DARTS family");
+    if (int rc = fill_table(table, sc, !vanilla && (f & DARTS_EDA_DIR), P.tb)) return rc;
+
+    std::memset(&P.em_pos, 0, sizeof P.em_pos);
+    P.med = make_medium(sc->medium);
+    P.box = sc->geom.kind;
+    for (int a = 0; a < 3; ++a) { P.bx.lo[a] = sc->geom.lo[a]; P.bx.hi[a] = sc->geom.hi[a]; }
+    P.n_em = sc->n_emitters;
+    for (int j = 0; j < P.n_em; ++j) {
+        const darts_emitter &e = sc->emitters[j];
+        if (!std::isfinite(e.start) || !(e.power >= 0.f)) return fail(DARTS_ERR_INVALID_ARG, "bad emitter %d", j);
+        for (int a = 0; a < 3; ++a) P.em_pos[j][a] = e.pos[a];
+        P.em_start[j] = e.start;
+        P.em_scale[j] = (float)(e.power / (4.0 * M_PI) * sc->n_emitters);
+    }
+    P.sensor_kind = sn.kind;
+    double dl = 0;
+    for (int a = 0; a < 3; ++a) dl += (double)sn.dir[a] * sn.dir[a];
+    if (sn.kind == 1 && !(dl > 0)) return fail(DARTS_ERR_INVALID_ARG, "sensor dir must be non-zero");
+    dl = std::sqrt(dl);
+    for (int a = 0; a < 3; ++a) {
+        P.origin[a] = sn.origin[a];
+        P.dir[a] = sn.kind == 1 ? (float)(sn.dir[a] / dl) : 0.f;
+        P.du[a] = sn.du[a];
+        P.dv[a] = sn.dv[a];
+    }
+    P.width = sn.width;
+    P.height = sn.height;
+    P.beta0 = sn.kind == 0 ? (float)(4.0 * M_PI) : 1.f;
+    P.l_lo = sc->bins.l_lo;
+    P.l_hi = sc->bins.l_hi;
+    P.n_bins = sc->bins.n_bins;
+    P.delta = (float)(((double)sc->bins.l_hi - sc->bins.l_lo) / sc->bins.n_bins);
+    P.path_offset = pr->path_offset;
+    P.n_paths = pr->n_paths;
+    P.key0 = (uint32_t)pr->seed;
+    P.key1 = (uint32_t)(pr->seed >> 32);
+    P.max_bounces = pr->max_bounces;
+    P.alpha = pr->alpha;
+    P.flags = f;
+    P.npix = (int64_t)sn.width * sn.height;
+    P.ncells = P.npix * sc->bins.n_bins;
+    if (P.ncells > ((int64_t)1 << 40)) return fail(DARTS_ERR_INVALID_ARG, "image too large");
+    const uint64_t nc = (uint64_t)P.ncells;
+    if (pr->path_offset > UINT64_MAX - pr->n_paths) return fail(DARTS_ERR_INVALID_ARG, "path id range overflows");
+    const uint64_t end = pr->path_offset + pr->n_paths;
+    P.q0 = pr->path_offset / nc;
+    P.r0 = pr->path_offset % nc;
+    P.q1 = end / nc;
+    P.r1 = end % nc;
+    // paths per cell: at most ceil(n / nc) + 1; split into chunks so that the
+    // launch has about g_target_lanes lanes
+    const uint64_t reps = pr->n_paths / nc + 2;
+    uint64_t n_chunks = (uint64_t)std::max<int64_t>(1, (g_target_lanes + P.ncells - 1) / P.ncells);
+    n_chunks = std::min(n_chunks, reps);
+    P.chunk = (reps + n_chunks - 1) / n_chunks;
+    n_chunks = (reps + P.chunk - 1) / P.chunk;
+    P.n_items = nc * n_chunks;
+    if (P.n_items / kBlock > 0x7FFFFFFFull) return fail(DARTS_ERR_INVALID_ARG, "launch too large");
+    P.hi = P.lo = P.m2 = nullptr;
+    P.stats = nullptr;
+    P.path_out = nullptr;
+    P.grad_image = nullptr;
+    P.grad_out = nullptr;
+    return DARTS_OK;
+}
+
+template <int MODE, int OUT>
+int launch_render(const KParams &P, bool stats, hipStream_t stream)
+{
+    const uint64_t blocks = (P.n_items + kBlock - 1) / kBlock;
+    if (blocks == 0 || P.n_paths == 0) return ok();
+    if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, stream, P);
+    else hipLaunchKernelGGL((render_kernel<MODE, OUT, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, stream, P);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "render launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *darts_last_error(void) { return g_last_error.c_str(); }
+
+int darts_abi_version(void) { return DARTS_ABI_VERSION; }
+
+int darts_table_bytes(const darts_table_dims *dims, size_t *bytes)
+{
+    if (int rc = check_dims(dims)) return rc;
+    if (!bytes) return fail(DARTS_ERR_INVALID_ARG, "bytes is null");
+    *bytes = (size_t)dims->n_cs * dims->n_s * (dims->n_cos + 1) * sizeof(float);
+    return ok();
+}
+
+int darts_build_da_tables(const darts_medium *medium, const darts_table_dims *dims, float *cdf_dev, void *stream)
+{
+    if (int rc = check_medium(medium)) return rc;
+    if (int rc = check_dims(dims)) return rc;
+    if (!cdf_dev) return fail(DARTS_ERR_INVALID_ARG, "cdf_dev is null");
+    TParams T;
+    T.sigma_s = medium->sigma_s;
+    T.sigma_a = medium->sigma_a;
+    T.sigma_t = medium->sigma_s + medium->sigma_a;
+    T.albedo = medium->sigma_s / T.sigma_t;
+    T.D = 1.0 / (3.0 * (medium->sigma_a + medium->sigma_s * (1.0 - medium->g)));
+    T.n_cs = dims->n_cs;
+    T.n_s = dims->n_s;
+    T.n_cos = dims->n_cos;
+    T.s_max = dims->s_max;
+    gauss_legendre(kGLU, T.xu, T.wu);
+    gauss_legendre(kGLV, T.xv, T.wv);
+    T.cdf = cdf_dev;
+    const uint32_t blocks = (uint32_t)(dims->n_cs * dims->n_s);
+    hipLaunchKernelGGL(table_kernel, dim3(blocks), dim3(64), sizeof(double) * dims->n_cos, (hipStream_t)stream, T);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "table launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+int darts_render_transient(const darts_scene *scene, const darts_params *params, const darts_table *table,
+                           float *image_hi_dev, float *image_lo_dev, float *image_m2_dev, uint64_t *stats_dev,
+                           void *stream)
+{
+    KParams P;
+    if (int rc = make_params(scene, params, table, P, false)) return rc;
+    if (!image_hi_dev || !image_lo_dev) return fail(DARTS_ERR_INVALID_ARG, "image_hi/lo are null");
+    P.hi = image_hi_dev;
+    P.lo = image_lo_dev;
+    P.m2 = image_m2_dev;
+    P.stats = (unsigned long long *)stats_dev;
+    const bool vanilla = (params->flags & DARTS_DIRECT_REUSE) != 0;
+    if (vanilla) return launch_render<1, OUT_IMAGE>(P, stats_dev != nullptr, (hipStream_t)stream);
+    return launch_render<0, OUT_IMAGE>(P, stats_dev != nullptr, (hipStream_t)stream);
+}
+
+int darts_render_paths(const darts_scene *scene, const darts_params *params, const darts_table *table,
+                       float *path_value_dev, void *stream)
+{
+    KParams P;
+    if (int rc = make_params(scene, params, table, P, true)) return rc;
+    if (!path_value_dev) return fail(DARTS_ERR_INVALID_ARG, "path_value_dev is null");
+    P.path_out = path_value_dev;
+    return launch_render<0, OUT_PATHS>(P, false, (hipStream_t)stream);
+}
+
+int darts_render_transient_backward(const darts_scene *scene, const darts_params *params, const darts_table *table,
+                                    const float *grad_image_dev, double *grad_out_dev, void *stream)
+{
+    KParams P;
+    if (int rc = make_params(scene, params, table, P, true)) return rc;
+    if (!grad_image_dev || !grad_out_dev) return fail(DARTS_ERR_INVALID_ARG, "grad buffers are null");
+    P.grad_image = grad_image_dev;
+    P.grad_out = grad_out_dev;
+    return launch_render<0, OUT_GRAD>(P, false, (hipStream_t)stream);
+}
+
+int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n, const darts_medium *medium,
+                          const darts_table *table, void *stream)
+{
+    if (fn < 0 || fn >= DARTS_PW_COUNT) return fail(DARTS_ERR_INVALID_ARG, "unknown pointwise function %d", fn);
+    if (n < 0 || (n > 0 && (!in_dev || !out_dev))) return fail(DARTS_ERR_INVALID_ARG, "bad buffers");
+    PWParams Q;
+    Q.fn = fn;
+    Q.n = n;
+    Q.in = in_dev;
+    Q.out = out_dev;
+    Q.med = Medium{};
+    const bool need_med = fn == DARTS_PW_DA_LOGPHI || fn == DARTS_PW_RIS || fn == DARTS_PW_DIRECTION;
+    if (need_med) {
+        if (int rc = check_medium(medium)) return rc;
+        Q.med = make_medium(*medium);
+    }
+    if (int rc = fill_table(table, nullptr, fn == DARTS_PW_DIRECTION, Q.tb)) return rc;
+    if (fn == DARTS_PW_DIRECTION && !same_medium(table->medium, *medium))
+        return fail(DARTS_ERR_TABLE_MISMATCH, "table was built for another medium");
+    if (n == 0) return ok();
+    const uint64_t blocks = ((uint64_t)n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(pointwise_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, (hipStream_t)stream, Q);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "pointwise launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+// Tuning knob (not part of the stable ABI): lanes a render launch aims for.
+int darts_set_target_lanes(int64_t lanes)
+{
+    if (lanes < 64) return fail(DARTS_ERR_INVALID_ARG, "target lanes must be >= 64");
+    g_target_lanes = lanes;
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,324 @@
+// Device building blocks of the DARTS path kernel (gfx950, wave64, FP32 path
+// arithmetic).  Every function here is also reachable one item per thread
+// through darts_debug_pointwise, so it can be checked on its own.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace darts {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInv4Pi = 0.0795774715459476679f;   // 1 / (4 pi)
+constexpr float kInf = __builtin_huge_valf();
+
+struct V3 { float x, y, z; };
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator*(V3 a, float s) { return V3{a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float length(V3 a) { return sqrtf(dot(a, a)); }
+__device__ __forceinline__ V3 fma3(V3 x, V3 w, float t) { return V3{fmaf(w.x, t, x.x), fmaf(w.y, t, x.y), fmaf(w.z, t, x.z)}; }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// with a Weyl-sequence key schedule.  Counter layout of this library:
+// (path id low, path id high, vertex index or 0xFFFFFFFF for camera set-up,
+// stream), key = seed.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// 24-bit uniform in [0,1): exact in float and double.
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
+
+// RIS candidate uniform: base-2 radical inverse of 8*row + col (row of the
+// 32x8 Sobol table, Section IV-C) plus a random offset, modulo 1 on 32-bit
+// fixed point.
+__device__ __forceinline__ float sobol_u(uint32_t row, uint32_t col, uint32_t eps)
+{
+    return u01(__builtin_bitreverse32(8u * row + col) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Henyey-Greenstein phase function.
+// ---------------------------------------------------------------------------
+// 1 + g^2 - 2 g mu is evaluated as a sum of non-negative terms,
+// (1 - g)^2 + 2 g (1 - mu) for g >= 0 and (1 + g)^2 + 2 |g| (1 + mu) for g < 0,
+// so the forward peak keeps full relative precision.
+__device__ __forceinline__ float hg_pdf(float mu, float g)
+{
+    const float den = g >= 0.f ? fmaf(2.f * g, 1.f - mu, (1.f - g) * (1.f - g))
+                               : fmaf(-2.f * g, 1.f + mu, (1.f + g) * (1.f + g));
+    return (1.f - g) * (1.f + g) * kInv4Pi * rsqrtf(den) / den;
+}
+
+// Inverse CDF of HG in mu, rewritten without cancellation: with
+// t = 1 - g + 2 g xi and q = (1 - g^2)/t,
+//   1 - mu = (1 - g)(1 - xi)(q + 1 - g)/t,   1 + mu = (1 + g) xi (q + 1 + g)/t,
+// both sums of positive terms for every |g| < 1 (g = 0 gives mu = 2 xi - 1).
+__device__ __forceinline__ void hg_sample(float xi, float g, float &mu, float &sin_t)
+{
+    const float t = fmaf(2.f * g, xi, 1.f - g);
+    const float it = 1.f / t;
+    const float q = (1.f - g) * (1.f + g) * it;
+    const float omu = (1.f - g) * (1.f - xi) * (q + 1.f - g) * it;
+    const float opu = (1.f + g) * xi * (q + 1.f + g) * it;
+    mu = fminf(fmaxf(0.5f * (opu - omu), -1.f), 1.f);
+    sin_t = sqrtf(fmaxf(omu * opu, 0.f));
+}
+
+// Orthonormal basis completing unit n (Duff et al., JCGT 2017, branchless).
+__device__ __forceinline__ void onb(V3 n, V3 &b1, V3 &b2)
+{
+    const float sign = copysignf(1.f, n.z);
+    const float a = -1.f / (sign + n.z);
+    const float b = n.x * n.y * a;
+    b1 = V3{1.f + sign * n.x * n.x * a, sign * b, -sign * n.x};
+    b2 = V3{b, sign + n.y * n.y * a, -n.y};
+}
+
+// Direction at cosine mu (sine s) to axis n, azimuth 2 pi u.
+__device__ __forceinline__ V3 from_frame(V3 n, float mu, float s, float u)
+{
+    V3 b1, b2;
+    onb(n, b1, b2);
+    float sp, cp;
+    sincospif(2.f * u, &sp, &cp);
+    const float a1 = s * cp, a2 = s * sp;
+    return V3{fmaf(a1, b1.x, fmaf(a2, b2.x, mu * n.x)),
+              fmaf(a1, b1.y, fmaf(a2, b2.y, mu * n.y)),
+              fmaf(a1, b1.z, fmaf(a2, b2.z, mu * n.z))};
+}
+
+// ---------------------------------------------------------------------------
+// Truncated exponential on [0, width) (Eq. (13)-(14)) with
+// mass = 1 - e^{-sigma width} and emass = e^{-sigma width}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float texp_mass(float sigma, float width)   // 1 - e^{-sigma width}
+{
+    return -expm1f(-sigma * width);
+}
+
+// x = -log(1 - mass u) / sigma without cancellation:  when mass u < 1/2 the
+// logarithm is log1p by Kahan's rescaling (log(v) y / (1 - v) with v the
+// rounded 1 - y, exact v - 1); otherwise 1 - mass u = (1 - u) + u emass is a
+// sum of non-negative terms with 1 - u exact (u >= 1/2).
+__device__ __forceinline__ float texp_sample(float u, float inv_sigma, float mass, float emass)
+{
+    const float y = mass * u;
+    const bool small = y < 0.5f;
+    const float v = small ? 1.f - y : fmaf(u, emass, 1.f - u);
+    const float L = logf(v);
+    const float nl = small ? (v == 1.f ? y : L * y / (v - 1.f)) : -L;
+    return nl * inv_sigma;
+}
+// ---------------------------------------------------------------------------
+// Index-matched box.
+// ---------------------------------------------------------------------------
+struct Box { float lo[3], hi[3]; };
+
+// Distance from x (inside) along unit w to the boundary.
+__device__ __forceinline__ float box_exit(const Box &b, V3 x, V3 w)
+{
+    float t = kInf;
+    const float xs[3] = {x.x, x.y, x.z}, ws[3] = {w.x, w.y, w.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (ws[a] > 0.f) t = fminf(t, (b.hi[a] - xs[a]) / ws[a]);
+        else if (ws[a] < 0.f) t = fminf(t, (b.lo[a] - xs[a]) / ws[a]);
+    }
+    return fmaxf(t, 0.f);
+}
+
+// Slab test for a ray from x along w; returns false on a miss.
+__device__ __forceinline__ bool box_entry(const Box &b, V3 x, V3 w, float &t_in, float &t_out)
+{
+    float tn = -kInf, tf = kInf;
+    const float xs[3] = {x.x, x.y, x.z}, ws[3] = {w.x, w.y, w.z};
+    bool hit = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (ws[a] == 0.f) {
+            hit = hit && !(xs[a] < b.lo[a] || xs[a] > b.hi[a]);
+        } else {
+            const float t1 = (b.lo[a] - xs[a]) / ws[a], t2 = (b.hi[a] - xs[a]) / ws[a];
+            tn = fmaxf(tn, fminf(t1, t2));
+            tf = fminf(tf, fmaxf(t1, t2));
+        }
+    }
+    t_in = fmaxf(tn, 0.f);
+    t_out = tf;
+    return hit && tf > t_in;
+}
+
+// ---------------------------------------------------------------------------
+// Medium constants (FP32) derived once on the host.
+// ---------------------------------------------------------------------------
+struct Medium {
+    float sigma_s, sigma_a, sigma_t, inv_sigma_t, albedo, g;
+    float inv4D;      // 1 / (4 D), D = 1 / (3 (sigma_a + sigma_s (1 - g)))  (Eq. (9))
+};
+
+// log of the DA fluence without its constant -1.5 log(4 pi D) (Eq. (9));
+// s > 0 is the residual time, r2 the squared distance to the emitter.
+__device__ __forceinline__ float da_log_phi_rel(const Medium &m, float r2, float s)
+{
+    const float is = 1.f / s;
+    return -1.5f * __logf(s) - r2 * m.inv4D * is - m.sigma_a * s;
+}
+
+// ---------------------------------------------------------------------------
+// Elliptical connection geometry (Eq. (18), (21), (22)).  For a length sum S,
+// focal distance C and cm = C (1 - mu) >= 0 (mu the cosine of the direction
+// to the focal axis):  den = S - C mu, t the polar distance, r = S - t the
+// distance from the control vertex to the emitter, written so that nothing
+// cancels when S ~ C or mu ~ 1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ellipse(float S, float C, float cm, float &den, float &t, float &r)
+{
+    const float sc = S - C;
+    den = sc + cm;
+    const float ih = 0.5f / den;
+    t = sc * (S + C) * ih;
+    r = fmaf(sc, sc, 2.f * S * cm) * ih;
+}
+
+// ---------------------------------------------------------------------------
+// DA distance sampling by RIS with 8 candidates (Section IV-C).  Candidates
+// follow the truncated exponential on [0, d_m) (pc = 1 - e^{-sigma_t d_m});
+// weights are the DA fluence at the upper residual time R_hi - d (zero
+// outside the residual-time ellipsoid); the selection and the normalisation
+// run in FP64.  On success returns the distance and the factor
+// albedo * mean(w) / w_selected that multiplies the path throughput.
+// b = dot(w, x_e - x), C2 = |x_e - x|^2, epc = 1 - pc = e^{-sigma_t d_m}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b, float R_hi, float pc,
+                                             float epc, uint32_t row, uint32_t eps, float u_sel,
+                                             float &d_out, float &factor)
+{
+    float dc[8], lp[8];
+    float lmax = -kInf;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float ui = sobol_u(row, (uint32_t)i, eps);
+        const float di = texp_sample(ui, m.inv_sigma_t, pc, epc);
+        const float si = R_hi - di;
+        const float r2 = fmaf(di, di - 2.f * b, C2);
+        const bool valid = (si > 0.f) && (r2 < si * si);
+        const float l = valid ? da_log_phi_rel(m, r2, si) : -kInf;
+        dc[i] = di;
+        lp[i] = l;
+        lmax = fmaxf(lmax, l);
+    }
+    if (!(lmax > -kInf)) return false;
+    float wv[8];
+    double wsum = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { wv[i] = __expf(lp[i] - lmax); wsum += (double)wv[i]; }
+    const double target = (double)u_sel * wsum;
+    double cum = 0.0;
+    float dsel = dc[7], wsel = wv[7];
+    bool found = false;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        cum += (double)wv[i];
+        const bool take = !found && (cum > target);
+        dsel = take ? dc[i] : dsel;
+        wsel = take ? wv[i] : wsel;
+        found = found || take;
+    }
+    if (!found) {  // only reachable through rounding: take the last positive weight
+#pragma unroll
+        for (int i = 0; i < 8; ++i) if (wv[i] > 0.f) { dsel = dc[i]; wsel = wv[i]; }
+    }
+    d_out = dsel;
+    factor = (float)((double)m.albedo * (wsum * 0.125) / (double)wsel);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// EDA direction sampling with one-sample MIS (Section V-A, Eq. (19)).
+// With probability gamma = kappa/(kappa + alpha) (kappa = C/S) cos(theta) to
+// the axis towards the emitter is drawn from the table row of (C/S, S) by
+// inverse transform (cos uniform inside the chosen bin, phi uniform);
+// otherwise from the phase function about the previous direction.  The
+// throughput is multiplied by phase / (gamma p_EDA + (1 - gamma) p_HG).
+// ---------------------------------------------------------------------------
+struct Table { const float *cdf; int n_cs, n_s, n_cos; float ns_over_smax; };
+
+__device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb, float alpha, bool use_eda,
+                                               V3 a /*unit, to emitter*/, float C, float S, V3 w_prev,
+                                               U4 r, float &weight, bool &eda_branch)
+{
+    const float u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
+    float gam = 0.f;
+    const float *row = nullptr;
+    if (use_eda && C > 0.f) {
+        const float kappa = C / S;
+        gam = kappa / (kappa + alpha);
+        const int i = min(max((int)(kappa * (float)tb.n_cs), 0), tb.n_cs - 1);
+        const int j = min(max((int)(S * tb.ns_over_smax), 0), tb.n_s - 1);
+        row = tb.cdf + ((size_t)i * tb.n_s + j) * (size_t)(tb.n_cos + 1);
+    }
+    eda_branch = u0 < gam;
+    V3 axis;
+    float mu, s, c_lo = 0.f, c_hi = 0.f;
+    int k = 0;
+    if (eda_branch) {
+        // largest k with cdf[k] <= u1 (cdf[0] = 0 <= u1 < 1 = cdf[n_cos])
+        int lo = 0, hi = tb.n_cos;
+        c_lo = 0.f; c_hi = 1.f;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            const float v = row[mid];
+            if (v <= u1) { lo = mid; c_lo = v; } else { hi = mid; c_hi = v; }
+        }
+        k = lo;
+        mu = fmaf((float)k + u3, 2.f / (float)tb.n_cos, -1.f);
+        s = sqrtf(fmaxf((1.f - mu) * (1.f + mu), 0.f));
+        axis = a;
+    } else {
+        hg_sample(u1, m.g, mu, s);
+        axis = w_prev;
+    }
+    const V3 w = from_frame(axis, mu, s, u2);
+    const float p_hg = hg_pdf(dot(w_prev, w), m.g);
+    float p_mix = p_hg;
+    if (gam > 0.f) {
+        if (!eda_branch) {
+            k = (int)floorf((dot(w, a) + 1.f) * 0.5f * (float)tb.n_cos);
+            k = min(max(k, 0), tb.n_cos - 1);
+            c_lo = row[k];
+            c_hi = row[k + 1];
+        }
+        const float p_eda = (c_hi - c_lo) * (float)tb.n_cos * kInv4Pi;
+        p_mix = gam * p_eda + (1.f - gam) * p_hg;
+    }
+    weight = p_hg / p_mix;
+    return w;
+}
+
+// Compensated addition: s + e == a + b exactly (Knuth TwoSum).
+__device__ __forceinline__ float two_sum_err(float a, float b, float s)
+{
+#pragma clang fp contract(off)
+    const float bb = s - a;
+    return (a - (s - bb)) + (b - bb);
+}
+
+}  // namespace darts

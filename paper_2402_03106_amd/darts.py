@@ -1,0 +1,289 @@
+"""Python binding of libdarts (include/darts.h): argument marshalling only.
+
+Every step of the path runs in the HIP kernels of ``csrc/darts.hip``; torch
+provides device memory and the stream.  The functions keep the C names:
+``table_bytes``, ``build_da_tables``, ``render_transient``, ``render_paths``,
+``render_transient_backward``, ``debug_pointwise``, ``last_error``.  Scenes
+are the plain dictionaries of ``paper_2402_03106_amd.workloads``.
+
+There is no CPU fallback: if ``libdarts.so`` is missing or no GPU is visible
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdarts.so")
+
+OK, ERR_INVALID_ARG, ERR_DEVICE, ERR_UNSUPPORTED, ERR_TABLE_MISMATCH = 0, -1, -2, -3, -4
+RIS_DIST, EDA_DIR, ELL_TEXP, ELL_UNIFORM, DIRECT_REUSE = 0x1, 0x2, 0x4, 0x8, 0x10
+MODES = {
+    "darts": RIS_DIST | EDA_DIR | ELL_TEXP,
+    "uniform": ELL_UNIFORM,
+    "vanilla": DIRECT_REUSE,
+    "da_only": RIS_DIST | ELL_UNIFORM,
+    "eda_only": EDA_DIR | ELL_TEXP,
+    "texp_only": ELL_TEXP,
+}
+MAX_EMITTERS = 8
+ST_NAMES = ["paths", "vertices", "connections", "early_exit", "medium_exit", "ris_all_invalid",
+            "eda_branch", "truncated", "zero_paths"]
+ST_COUNT = 16
+PW_IN, PW_OUT = 16, 8
+PW = {name: i for i, name in enumerate(
+    ["philox", "hg_pdf", "hg_sample", "da_logphi", "texp", "ellipse", "sobol", "onb", "box_exit",
+     "ris", "direction"])}
+
+
+class DartsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libdarts error {code}: {msg}")
+        self.code = code
+
+
+class _Medium(C.Structure):
+    _fields_ = [("sigma_s", C.c_double), ("sigma_a", C.c_double), ("g", C.c_double)]
+
+
+class _Emitter(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("start", C.c_float), ("power", C.c_float)]
+
+
+class _Sensor(C.Structure):
+    _fields_ = [("kind", C.c_int), ("origin", C.c_float * 3), ("dir", C.c_float * 3),
+                ("du", C.c_float * 3), ("dv", C.c_float * 3), ("width", C.c_int), ("height", C.c_int)]
+
+
+class _Geometry(C.Structure):
+    _fields_ = [("kind", C.c_int), ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+
+
+class _Bins(C.Structure):
+    _fields_ = [("l_lo", C.c_float), ("l_hi", C.c_float), ("n_bins", C.c_int)]
+
+
+class _Scene(C.Structure):
+    _fields_ = [("medium", _Medium), ("geom", _Geometry), ("emitters", C.POINTER(_Emitter)),
+                ("n_emitters", C.c_int), ("sensor", _Sensor), ("bins", _Bins)]
+
+
+class _Dims(C.Structure):
+    _fields_ = [("n_cs", C.c_int), ("n_s", C.c_int), ("n_cos", C.c_int), ("s_max", C.c_float)]
+
+
+class _Table(C.Structure):
+    _fields_ = [("medium", _Medium), ("dims", _Dims), ("cdf_dev", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("n_paths", C.c_uint64), ("path_offset", C.c_uint64), ("seed", C.c_uint64),
+                ("max_bounces", C.c_int), ("n_ris", C.c_int), ("alpha", C.c_float), ("flags", C.c_uint)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64 = C.c_void_p, C.c_int64
+        L.darts_last_error.restype = C.c_char_p
+        L.darts_abi_version.restype = C.c_int
+        L.darts_table_bytes.argtypes = [C.POINTER(_Dims), C.POINTER(C.c_size_t)]
+        L.darts_build_da_tables.argtypes = [C.POINTER(_Medium), C.POINTER(_Dims), vp, vp]
+        L.darts_render_transient.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Table),
+                                             vp, vp, vp, vp, vp]
+        L.darts_render_paths.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Table), vp, vp]
+        L.darts_render_transient_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Table),
+                                                      vp, vp, vp]
+        L.darts_debug_pointwise.argtypes = [C.c_int, vp, vp, i64, C.POINTER(_Medium), C.POINTER(_Table), vp]
+        L.darts_set_target_lanes.argtypes = [i64]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().darts_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise DartsError(rc, last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f3(v):
+    return (C.c_float * 3)(*[float(x) for x in v])
+
+
+def medium(m: dict) -> _Medium:
+    return _Medium(float(m["sigma_s"]), float(m["sigma_a"]), float(m["g"]))
+
+
+def dims(d: dict) -> _Dims:
+    return _Dims(int(d["n_cs"]), int(d["n_s"]), int(d["n_cos"]), float(d["s_max"]))
+
+
+class _SceneHolder:
+    def __init__(self, sc: dict):
+        ems = sc["emitters"]
+        self.em = (_Emitter * len(ems))(*[_Emitter(_f3(e["pos"]), float(e.get("start", 0.0)),
+                                                   float(e.get("power", 1.0))) for e in ems])
+        s, g, b = sc["sensor"], sc["geometry"], sc["bins"]
+        self.c = _Scene(medium(sc["medium"]),
+                        _Geometry(int(g["kind"]), _f3(g.get("lo", (0, 0, 0))), _f3(g.get("hi", (0, 0, 0)))),
+                        C.cast(self.em, C.POINTER(_Emitter)), len(ems),
+                        _Sensor(int(s["kind"]), _f3(s["origin"]), _f3(s.get("dir", (0, 0, -1))),
+                                _f3(s.get("du", (0, 0, 0))), _f3(s.get("dv", (0, 0, 0))),
+                                int(s.get("width", 1)), int(s.get("height", 1))),
+                        _Bins(float(b["l_lo"]), float(b["l_hi"]), int(b["n_bins"])))
+
+
+def params(p: dict, mode) -> _Params:
+    flags = MODES[mode] if isinstance(mode, str) else int(mode)
+    return _Params(int(p["n_paths"]), int(p.get("path_offset", 0)), int(p["seed"]), int(p["max_bounces"]),
+                   int(p.get("n_ris", 8)), float(p.get("alpha", 0.5)), flags)
+
+
+def image_shape(sc: dict):
+    s = sc["sensor"]
+    return (int(sc["bins"]["n_bins"]), int(s.get("height", 1)), int(s.get("width", 1)))
+
+
+# --------------------------------------------------------------------------
+# Tables
+# --------------------------------------------------------------------------
+@dataclass
+class Table:
+    """A built direction table: device float tensor [n_cs, n_s, n_cos + 1]
+    plus the medium and dims it was built for."""
+    cdf: torch.Tensor
+    medium: dict
+    dims: dict
+
+    def c_struct(self) -> _Table:
+        return _Table(medium(self.medium), dims(self.dims), C.c_void_p(self.cdf.data_ptr()))
+
+
+def table_bytes(d: dict) -> int:
+    n = C.c_size_t()
+    _check(lib().darts_table_bytes(C.byref(dims(d)), C.byref(n)))
+    return int(n.value)
+
+
+def build_da_tables(med: dict, d: dict, out: torch.Tensor | None = None, stream=None,
+                    device="cuda") -> Table:
+    nbytes = table_bytes(d)
+    shape = (int(d["n_cs"]), int(d["n_s"]), int(d["n_cos"]) + 1)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=device)
+    if out.numel() * 4 != nbytes or out.dtype != torch.float32:
+        raise ValueError("table tensor has the wrong size or dtype")
+    _check(lib().darts_build_da_tables(C.byref(medium(med)), C.byref(dims(d)), _ptr(out), _stream(stream)))
+    return Table(out, dict(med), dict(d))
+
+
+# --------------------------------------------------------------------------
+# Render
+# --------------------------------------------------------------------------
+def render_transient(sc: dict, p: dict, mode, table: Table | None = None, image_hi=None, image_lo=None,
+                     image_m2=None, stats=None, want_m2: bool = False, want_stats: bool = False,
+                     stream=None, device="cuda"):
+    """Accumulate raw sums into (image_hi, image_lo[, image_m2]); allocates
+    zeroed outputs when none are given.  Returns (hi, lo, m2, stats)."""
+    shape = image_shape(sc)
+    if image_hi is None:
+        image_hi = torch.zeros(shape, dtype=torch.float32, device=device)
+    if image_lo is None:
+        image_lo = torch.zeros(shape, dtype=torch.float32, device=device)
+    if want_m2 and image_m2 is None:
+        image_m2 = torch.zeros(shape, dtype=torch.float32, device=device)
+    if want_stats and stats is None:
+        stats = torch.zeros(ST_COUNT, dtype=torch.int64, device=device)
+    for t in (image_hi, image_lo, image_m2):
+        if t is not None and (tuple(t.shape) != shape or t.dtype != torch.float32):
+            raise ValueError(f"image tensors must be float32 {shape}")
+    h = _SceneHolder(sc)
+    tb = C.byref(table.c_struct()) if table is not None else None
+    _check(lib().darts_render_transient(C.byref(h.c), C.byref(params(p, mode)), tb, _ptr(image_hi),
+                                        _ptr(image_lo), _ptr(image_m2), _ptr(stats), _stream(stream)))
+    return image_hi, image_lo, image_m2, stats
+
+
+def render_paths(sc: dict, p: dict, mode, table: Table | None = None, out=None, stream=None, device="cuda"):
+    n = int(p["n_paths"])
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=device)
+    h = _SceneHolder(sc)
+    tb = C.byref(table.c_struct()) if table is not None else None
+    _check(lib().darts_render_paths(C.byref(h.c), C.byref(params(p, mode)), tb, _ptr(out), _stream(stream)))
+    return out
+
+
+def render_transient_backward(sc: dict, p: dict, mode, table: Table | None, grad_image: torch.Tensor,
+                              grad_out=None, stream=None):
+    if grad_out is None:
+        grad_out = torch.zeros(3, dtype=torch.float64, device=grad_image.device)
+    h = _SceneHolder(sc)
+    tb = C.byref(table.c_struct()) if table is not None else None
+    _check(lib().darts_render_transient_backward(C.byref(h.c), C.byref(params(p, mode)), tb,
+                                                 _ptr(grad_image.contiguous()), _ptr(grad_out), _stream(stream)))
+    return grad_out
+
+
+def debug_pointwise(fn: str, inputs: torch.Tensor, med: dict | None = None, table: Table | None = None,
+                    stream=None) -> torch.Tensor:
+    if inputs.dtype != torch.float32 or inputs.dim() != 2 or inputs.shape[1] != PW_IN:
+        raise ValueError(f"inputs must be float32 [n, {PW_IN}]")
+    out = torch.zeros((inputs.shape[0], PW_OUT), dtype=torch.float32, device=inputs.device)
+    m = C.byref(medium(med)) if med is not None else None
+    tb = C.byref(table.c_struct()) if table is not None else None
+    _check(lib().darts_debug_pointwise(PW[fn], _ptr(inputs.contiguous()), _ptr(out), inputs.shape[0], m, tb,
+                                       _stream(stream)))
+    return out
+
+
+def set_target_lanes(n: int):
+    _check(lib().darts_set_target_lanes(int(n)))
+
+
+def stats_dict(stats: torch.Tensor) -> dict:
+    s = stats.cpu().tolist()
+    return {k: int(s[i]) for i, k in enumerate(ST_NAMES)}
+
+
+def paths_per_cell(sc: dict, p: dict, mode) -> torch.Tensor:
+    """Paths mapped to each cell by the stratified map (path id i lands in
+    cell i mod n_cells); vanilla reuses a path for all bins of its pixel."""
+    shape = image_shape(sc)
+    nc = shape[0] * shape[1] * shape[2]
+    n, off = int(p["n_paths"]), int(p.get("path_offset", 0))
+    ids = torch.arange(nc, dtype=torch.int64)
+    first = (ids - off) % nc
+    cnt = torch.where(first < n, (n - 1 - first) // nc + 1, torch.zeros_like(first)).to(torch.float64)
+    cnt = cnt.reshape(shape)
+    if (MODES[mode] if isinstance(mode, str) else int(mode)) & DIRECT_REUSE:
+        cnt = cnt.sum(0, keepdim=True).expand(shape).clone()
+    return cnt

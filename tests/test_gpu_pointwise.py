@@ -1,0 +1,264 @@
+"""GPU building blocks vs the FP64 oracle, one item per thread through
+darts_debug_pointwise.  Bar: bit-exact for integer work (Philox, candidate
+uniforms); relative 1e-5 (absolute floor 1e-6 for unit-bounded quantities)
+for the FP32 samplers and densities; discrete choices (RIS pick, MIS branch,
+cos-bin) may flip only where FP32 rounding sits on a decision boundary."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2402_03106_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_03106_amd import darts
+    darts.lib()
+    return darts
+
+
+class Bits(int):
+    """A 32-bit integer argument, passed to the kernel by bit pattern."""
+
+
+def run(D, fn, rows, med=None, table=None):
+    """rows: lists of floats and Bits.  Returns (out float64 [n, 8],
+    float inputs as float64 [n, 16], integer inputs as uint32 [n, 16])."""
+    inp = np.zeros((len(rows), D.PW_IN), F32)
+    ib = inp.view(np.uint32)
+    for i, r in enumerate(rows):
+        for j, v in enumerate(r):
+            if isinstance(v, Bits):
+                ib[i, j] = int(v) & 0xFFFFFFFF
+            else:
+                inp[i, j] = v
+    x = torch.from_numpy(inp.copy()).cuda()
+    out = D.debug_pointwise(fn, x, med, table)
+    torch.cuda.synchronize()
+    fl = np.where(np.isfinite(inp), inp, np.where(np.isinf(inp), inp, 0)).astype(np.float64)
+    return out.cpu().numpy().astype(np.float64), fl, ib.copy()
+
+
+def ubits(v):
+    return Bits(int(v))
+
+
+def rel_ok(a, b, rtol=1e-5, atol=0.0):
+    return np.abs(a - b) <= rtol * np.abs(b) + atol
+
+
+def test_philox_bit_exact(D, oracle):
+    rng = np.random.default_rng(10)
+    rows, refs = [], []
+    kat = [([0, 0, 0, 0], [0, 0]), ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2),
+           ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0])]
+    for _ in range(2000):
+        kat.append((list(rng.integers(0, 2 ** 32, 4)), list(rng.integers(0, 2 ** 32, 2))))
+    for ctr, key in kat:
+        rows.append([int(v) for v in ctr + key])
+        refs.append(oracle.philox(ctr, key))
+    inp = np.zeros((len(rows), D.PW_IN), np.uint32)
+    inp[:, :6] = np.array(rows, np.uint64).astype(np.uint32)
+    out = D.debug_pointwise("philox", torch.from_numpy(inp.view(F32).copy()).cuda())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[:, :4].view(np.uint32)
+    assert np.array_equal(got, np.array(refs, np.uint32))
+
+
+def test_sobol_bit_exact(D, oracle):
+    L = oracle.lib()
+    rng = np.random.default_rng(11)
+    rows, ref = [], []
+    for _ in range(3000):
+        r, c, e = int(rng.integers(32)), int(rng.integers(8)), int(rng.integers(0, 2 ** 32))
+        rows.append([ubits(r), ubits(c), ubits(e)])
+        ref.append(L.ref_sobol_u(r, c, e))
+    out, _, _ = run(D, "sobol", rows)
+    assert np.array_equal(out[:, 0], np.array(ref))
+
+
+def test_hg_pdf(D, oracle):
+    L = oracle.lib()
+    rng = np.random.default_rng(12)
+    gs = np.concatenate([[-0.95, -0.3, 0.0, 1e-4, 0.5, 0.7, 0.95], rng.uniform(-0.95, 0.95, 40)]).astype(F32)
+    mus = np.concatenate([[-1, -0.5, 0, 0.5, 0.999, 1], rng.uniform(-1, 1, 40)]).astype(F32)
+    rows = [[m, g] for g in gs for m in mus]
+    out, inp, _ = run(D, "hg_pdf", rows)
+    ref = np.array([L.ref_hg_pdf(m, g) for m, g in inp[:, :2]])
+    assert np.all(rel_ok(out[:, 0], ref)), np.max(np.abs(out[:, 0] / ref - 1))
+
+
+def test_hg_sample(D, oracle):
+    L = oracle.lib()
+    rng = np.random.default_rng(13)
+    gs = np.concatenate([[-0.95, -0.3, 0.0, 1e-6, 1e-3, 0.5, 0.7, 0.95], rng.uniform(-0.95, 0.95, 30)]).astype(F32)
+    xis = np.concatenate([[0.0, 1e-7, 0.5, 1 - 2 ** -24], rng.random(60)]).astype(F32)
+    rows = [[x, g] for g in gs for x in xis]
+    out, inp, _ = run(D, "hg_sample", rows)
+    mu_ref = np.array([L.ref_hg_sample_mu(x, g) for x, g in inp[:, :2]])
+    sin_ref = np.sqrt(np.maximum((1 - mu_ref) * (1 + mu_ref), 0))
+    assert np.all(rel_ok(out[:, 0], mu_ref, 1e-5, 1e-6)), np.max(np.abs(out[:, 0] - mu_ref))
+    assert np.all(rel_ok(out[:, 1], sin_ref, 1e-5, 1e-6)), np.max(np.abs(out[:, 1] - sin_ref))
+
+
+@pytest.mark.parametrize("med", [dict(sigma_s=1.0, sigma_a=0.01, g=0.0), dict(sigma_s=4.75, sigma_a=0.25, g=0.7)])
+def test_da_log_phi(D, oracle, med):
+    L = oracle.lib()
+    m = C.byref(oracle.medium(med))
+    rng = np.random.default_rng(14)
+    rows = [[r, s] for r, s in zip(rng.uniform(0, 10, 3000).astype(F32), rng.uniform(1e-3, 40, 3000).astype(F32))]
+    out, inp, _ = run(D, "da_logphi", rows, med)
+    D_ = 1.0 / (3 * (med["sigma_a"] + med["sigma_s"] * (1 - med["g"])))
+    ref = np.array([L.ref_da_log_phi(m, r, s) for r, s in inp[:, :2]]) + 1.5 * math.log(4 * math.pi * D_)
+    assert np.all(rel_ok(out[:, 0], ref, 1e-5, 1e-5)), np.max(np.abs(out[:, 0] - ref) / np.maximum(np.abs(ref), 1))
+
+
+def test_truncated_exponential(D, oracle):
+    L = oracle.lib()
+    rng = np.random.default_rng(15)
+    rows = []
+    for _ in range(3000):
+        rows.append([rng.random(), rng.uniform(0.01, 20), rng.choice([rng.uniform(1e-3, 5), np.inf])])
+    rows += [[0.0, 5.0, 2.0], [1 - 2 ** -24, 5.0, 2.0], [1e-7, 0.1, 1e-3]]
+    rows = [[F32(a) for a in r] for r in rows]
+    out, inp, _ = run(D, "texp", rows)
+    xr = np.array([L.ref_texp_sample(u, s, w) for u, s, w in inp[:, :3]])
+    pr = np.array([L.ref_texp_pdf(x, s, w) for x, (u, s, w) in zip(xr, inp[:, :3])])
+    assert np.all(rel_ok(out[:, 0], xr, 1e-5, 1e-12)), np.max(np.abs(out[:, 0] / np.maximum(xr, 1e-30) - 1))
+    assert np.all(rel_ok(out[:, 1], pr, 1e-5)), np.max(np.abs(out[:, 1] / pr - 1))
+
+
+def test_ellipse(D, oracle):
+    L = oracle.lib()
+    rng = np.random.default_rng(16)
+    rows = []
+    for _ in range(4000):
+        Cd = rng.uniform(1e-3, 10)
+        S = Cd * (1 + 10 ** rng.uniform(-4, 1))
+        mu = rng.choice([rng.uniform(-1, 1), 1 - 10 ** rng.uniform(-7, -1)])
+        rows.append([F32(S), F32(Cd), F32(mu), F32(rng.uniform(0.1, 3))])
+    out, inp, _ = run(D, "ellipse", rows)
+    t = np.array([L.ref_ell_t(S, Cd, mu) for S, Cd, mu in inp[:, :3]])
+    r = inp[:, 0] - t
+    pt = np.array([L.ref_ell_pdf_t(pS, S, Cd, mu, tt, 0) for (S, Cd, mu, pS), tt in zip(inp[:, :4], t)])
+    # t, r and p_t of the FP64 oracle use the plain formulas (r = S - t);
+    # the kernel's cancellation-free forms agree to FP32 rounding
+    assert np.all(rel_ok(out[:, 0], t, 1e-5)), np.max(np.abs(out[:, 0] / t - 1))
+    assert np.all(rel_ok(out[:, 1], r, 1e-5)), np.max(np.abs(out[:, 1] / r - 1))
+    assert np.all(rel_ok(out[:, 2], pt, 1e-5)), np.max(np.abs(out[:, 2] / pt - 1))
+
+
+def test_onb(D, oracle):
+    L = oracle.lib()
+    rng = np.random.default_rng(17)
+    ns = [[0, 0, 1], [0, 0, -1], [1, 0, 0], [0, 1, 0]]
+    for v in rng.normal(size=(2000, 3)):
+        ns.append(list(v / np.linalg.norm(v)))
+    rows = [[F32(a) for a in n] for n in ns]
+    out, inp, _ = run(D, "onb", rows)
+    for o, n in zip(out, inp[:, :3]):
+        b1 = (C.c_double * 3)()
+        b2 = (C.c_double * 3)()
+        L.ref_onb((C.c_double * 3)(*n), b1, b2)
+        assert np.allclose(o[:3], b1[:], atol=2e-6) and np.allclose(o[3:6], b2[:], atol=2e-6)
+
+
+def test_box_exit(D, oracle):
+    L = oracle.lib()
+    rng = np.random.default_rng(18)
+    rows = []
+    for _ in range(3000):
+        x = rng.uniform(-0.999, 0.999, 3)
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        rows.append([*x, *w, -1, -1, -1, 1, 1, 1])
+    rows.append([0, 0, 0, 0, 0, 1, -1, -1, -1, 1, 1, 1])
+    rows = [[F32(a) for a in r] for r in rows]
+    out, inp, _ = run(D, "box_exit", rows)
+    g = oracle.geometry({"kind": 1, "lo": (-1, -1, -1), "hi": (1, 1, 1)})
+    ref = np.array([L.ref_box_exit(C.byref(g), (C.c_double * 3)(*r[:3]), (C.c_double * 3)(*r[3:6])) for r in inp])
+    assert np.all(rel_ok(out[:, 0], ref, 1e-5, 1e-6))
+
+
+def test_ris_step(D, oracle):
+    """Whole RIS free-flight step: validity, selected distance, weight."""
+    L = oracle.lib()
+    med = dict(sigma_s=4.75, sigma_a=0.25, g=0.7)
+    m = C.byref(oracle.medium(med))
+    rng = np.random.default_rng(19)
+    rows = []
+    xe = np.array([0, 0, 1.5])
+    for _ in range(4000):
+        x = rng.uniform(-1, 1, 3)
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        Cd = np.linalg.norm(xe - x)
+        R_hi = Cd + rng.choice([rng.uniform(0, 0.3), rng.uniform(0, 20)])
+        d_m = rng.choice([rng.uniform(0.01, 3), np.inf])
+        rows.append([*x, *w, *xe, R_hi, d_m, ubits(int(rng.integers(32))), ubits(int(rng.integers(0, 2 ** 32))),
+                     rng.random()])
+    out, inp, ib = run(D, "ris", rows, med)
+    n_ok = n_cmp = 0
+    for o, r, rb in zip(out, inp, ib):
+        row, eps = int(rb[11]), int(rb[12])
+        d, fac = C.c_double(), C.c_double()
+        okr = L.ref_ris_step(m, 8, (C.c_double * 3)(*r[0:3]), (C.c_double * 3)(*r[3:6]),
+                             (C.c_double * 3)(*r[6:9]), r[9], r[10], row, eps, r[13], C.byref(d), C.byref(fac), 0)
+        n_cmp += 1
+        if okr == int(o[0]) and (okr == 0 or (rel_ok(o[1], d.value, 1e-5, 1e-7) and rel_ok(o[2], fac.value, 1e-4))):
+            n_ok += 1
+    assert n_ok >= 0.998 * n_cmp, (n_ok, n_cmp)
+
+
+def test_direction_sampling(D, oracle):
+    """EDA/HG mixture with MIS weight on a real table."""
+    L = oracle.lib()
+    w = W.box_hg_small()
+    med, dims = w["scene"]["medium"], w["dims"]
+    table = D.build_da_tables(med, dims)
+    _, cdf = oracle.build_table(med, dims)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(20)
+    rows = []
+    xe = np.array([0, 0, 1.5])
+    for _ in range(4000):
+        x = rng.uniform(-1, 1, 3)
+        wp = rng.normal(size=3)
+        wp /= np.linalg.norm(wp)
+        Cd = np.linalg.norm(xe - x)
+        S = Cd * (1 + 10 ** rng.uniform(-3, 1))
+        u = rng.integers(0, 2 ** 32, 4)
+        rows.append([*x, *xe, *wp, S, *[ubits(int(v)) for v in u], 1.0, 0.5])
+    out, inp, ib = run(D, "direction", rows, med, table)
+    mm, dd = C.byref(oracle.medium(med)), C.byref(oracle.dims(dims))
+    cp = np.ascontiguousarray(cdf).ctypes.data_as(C.POINTER(C.c_float))
+    n_ok = 0
+    for o, r, rb in zip(out, inp, ib):
+        u = [L.ref_u01(int(v)) for v in rb[10:14]]
+        wo, wt, eb = (C.c_double * 3)(), C.c_double(), C.c_int()
+        L.ref_sample_direction(mm, dd, cp, 0.5, 1, (C.c_double * 3)(*r[0:3]), (C.c_double * 3)(*r[3:6]),
+                               (C.c_double * 3)(*r[6:9]), r[9], (C.c_double * 4)(*u), wo, C.byref(wt), C.byref(eb), 0)
+        if (int(o[4]) == eb.value and np.allclose(o[:3], wo[:], atol=2e-5)
+                and rel_ok(o[3], wt.value, 1e-4)):
+            n_ok += 1
+    assert n_ok >= 0.995 * len(rows), n_ok
+
+
+def test_table_matches_oracle(D, oracle):
+    for w in [W.box_hg_small(), W.infinite_point()]:
+        med, dims = w["scene"]["medium"], w["dims"]
+        t = D.build_da_tables(med, dims)
+        torch.cuda.synchronize()
+        _, cdf = oracle.build_table(med, dims)
+        got = t.cdf.cpu().numpy()
+        assert got.shape == cdf.shape
+        assert np.max(np.abs(got.astype(np.float64) - cdf)) <= 1e-6
+        assert np.all(got[..., 0] == 0) and np.all(got[..., -1] == 1)
