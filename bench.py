@@ -1,0 +1,264 @@
+"""Benchmark: transient paths/s of the DARTS hot path on one MI355X.
+
+A step is one pass of the whole hot path over one frame of synthetic input:
+build the elliptical-DA direction table for the medium, then render one frame
+of the box workload (64x64 sensor x 256 time bins = 2^20 cells) with 2^28
+paths (256 per cell).  `value` is DARTS paths/s with everything resident in
+HBM.  The line also carries
+  - `roofline`: the render kernel's algorithmic FP32 FLOP/s (FLOPs per vertex
+    step times the steps of one launch, over the kernel's mean duration timed
+    with HIP events on its own stream) against the MI355X vector peak;
+  - `cpu_baseline`: the FP64 oracle on the host cores, on a bounded sample
+    of the same workload;
+  - `uniform`: the temporally uniform baseline (uniform length-sum
+    connection, exponential distance, phase sampling) on the same frame;
+  - `time_to_mse`: time to reach MSE <= 1e-4 (cells normalised by the 0.95
+    quantile, as in the paper's parameter study) for DARTS and uniform,
+    from per-cell second moments (both estimators are unbiased, so MSE is
+    their variance, which falls as 1/N).
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "transient paths/s and time-to-MSE 1e-4, DARTS vs uniform sampling, 1×MI355X"
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic floating-point operations per part of a vertex step, counted
+# from the algorithm: +, -, *, /, min/max and compares 1, fma 2, each exp, log,
+# sqrt, rsqrt, sin/cos 1 (integer RNG work is not counted).
+FLOPS = {
+    "connect_test": 31,     # focal geometry, residual range, boundary clip (every step)
+    "connect_texp": 88,     # truncated-exponential S, t(S), p(t), phase, transmittance
+    "connect_uniform": 76,  # the same with S uniform
+    "flight_test": 4,       # medium-event probability and Bernoulli draw
+    "ris": 293,             # 8 candidates: distance, residual, validity, log DA fluence;
+                            # FP64 normalisation and selection; weight
+    "exp_distance": 9,      # plain exponential distance
+    "move": 20,             # advance, distance to emitter, early-exit test
+    "direction": 79,        # frame, phase pdf, MIS weight, boundary distance
+    "direction_eda": 15,    # gamma, table cell, EDA pdf, mixture pdf (EDA enabled)
+    "eda_branch": 15,       # inverse transform over the cos bins
+    "hg_branch": 30,        # HG inverse CDF
+    "hg_bin": 9,            # cos bin of a phase-sampled direction (EDA enabled)
+}
+
+
+def algorithmic_flops(s: dict, mode: str) -> float:
+    """FLOPs of one launch from its statistics counters."""
+    steps = s["vertices"] - s["early_exit"]             # vertices that passed the early-exit test
+    flights = steps - s["truncated"]
+    draws = flights - s["medium_exit"]
+    moves = draws - s["ris_all_invalid"]
+    dirs = moves - (s["early_exit"] - s["setup_exit"])
+    eda = s["eda_branch"]
+    f = steps * FLOPS["connect_test"] + flights * FLOPS["flight_test"] + moves * FLOPS["move"]
+    f += dirs * FLOPS["direction"]
+    if mode == "darts":
+        f += s["connections"] * FLOPS["connect_texp"] + draws * FLOPS["ris"]
+        f += dirs * FLOPS["direction_eda"] + eda * FLOPS["eda_branch"] + (dirs - eda) * (FLOPS["hg_branch"] + FLOPS["hg_bin"])
+    else:
+        f += s["connections"] * FLOPS["connect_uniform"] + draws * FLOPS["exp_distance"] + dirs * FLOPS["hg_branch"]
+    return float(f), steps
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--paths-log2", type=int, default=28)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mse", action="store_true", help="skip the time-to-MSE measurement")
+    ap.add_argument("--no-uniform", action="store_true", help="skip the uniform-baseline throughput")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(multi-GPU sharding is a design note, not part of the build)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2402_03106_amd import darts
+    from paper_2402_03106_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    darts.lib()
+    n = 1 << a.paths_log2
+    w = W.with_(W.box_hg(), n_paths=n)
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    shape = darts.image_shape(sc)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    hi = torch.zeros(shape, dtype=torch.float32, device=dev)
+    lo = torch.zeros(shape, dtype=torch.float32, device=dev)
+    cdf = torch.empty((dm["n_cs"], dm["n_s"], dm["n_cos"] + 1), dtype=torch.float32, device=dev)
+
+    def step(mode, ev=None):
+        table = darts.build_da_tables(sc["medium"], dm, out=cdf)
+        if ev is not None:
+            ev[0].record(stream)
+        darts.render_transient(sc, pr, mode, table, hi, lo)
+        if ev is not None:
+            ev[1].record(stream)
+
+    def timed(mode, steps, warmup):
+        for _ in range(warmup):
+            step(mode)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(mode, evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+        return wall, kern_ms
+
+    def count_steps(mode):
+        table = darts.build_da_tables(sc["medium"], dm, out=cdf)
+        h2, l2 = torch.zeros_like(hi), torch.zeros_like(lo)
+        _, _, _, st = darts.render_transient(sc, pr, mode, table, h2, l2, want_stats=True)
+        torch.cuda.synchronize()
+        s = darts.stats_dict(st)
+        flops, steps = algorithmic_flops(s, mode)
+        return s, steps, flops
+
+    wall, kern_ms = timed("darts", a.steps, a.warmup)
+    stats, n_steps, flops = count_steps("darts")
+    mean_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
+    achieved = flops / mean_kern_s / 1e12
+    value = a.steps * n / wall
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "box_hg: box [-1,1]^3, sigma_t=5, albedo 0.95, HG g=0.7, emitter (0,0,1.5); "
+                        "64x64 orthographic sensor x 256 bins over [0,40); 64x64x32 FP32 direction table",
+            "paths_per_step": n, "paths_per_cell": n >> 20, "mode": "darts (RIS 8 + EDA/MIS + texp ellipse)",
+            "step": "build_da_tables + render_transient",
+        },
+        "render_kernel_ms": mean_kern_s * 1e3,
+        "vertex_steps_per_launch": n_steps,
+        "mean_steps_per_path": n_steps / n,
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "flops_per_launch": flops, "flops_per_vertex_step": flops / n_steps,
+        },
+        "stats": stats,
+    }
+    print(f"[bench] darts {value:.4g} paths/s, kernel {mean_kern_s*1e3:.2f} ms, "
+          f"{achieved:.2f} TFLOP/s algorithmic", file=sys.stderr, flush=True)
+
+    if not a.no_uniform:
+        wall_u, kern_u = timed("uniform", max(2, a.steps // 2), 1)
+        st_u, n_steps_u, flops_u = count_steps("uniform")
+        ku = sum(kern_u) / len(kern_u) / 1e3
+        out["uniform"] = {"paths_per_s": max(2, a.steps // 2) * n / wall_u, "render_kernel_ms": ku * 1e3,
+                          "mean_steps_per_path": n_steps_u / n, "algorithmic_tflops": flops_u / ku / 1e12}
+        print(f"[bench] uniform {out['uniform']['paths_per_s']:.4g} paths/s", file=sys.stderr, flush=True)
+
+    if not a.no_mse:
+        out["time_to_mse"] = time_to_mse(darts, torch, np, sc, pr, dm, out)
+        print(f"[bench] time to MSE {out['time_to_mse']}", file=sys.stderr, flush=True)
+
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+        print(f"[bench] cpu {out['cpu_baseline']}", file=sys.stderr, flush=True)
+
+    print(json.dumps(out), flush=True)
+
+
+def time_to_mse(darts, torch, np, sc, pr, dm, out, target=1e-4):
+    """MSE(N) = mean over cells of Var(cell estimate) / q95^2; both
+    estimators are unbiased so MSE is the variance, estimated from per-path
+    second moments of an N0-path render and scaled as 1/N.  The wall time to
+    reach the target is N*/throughput plus one table build."""
+    n0 = 1 << 26
+    p0 = dict(pr, n_paths=n0, path_offset=1 << 40, seed=0xEF)
+    res = {}
+    means = {}
+    for mode in ["darts", "uniform"]:
+        table = darts.build_da_tables(sc["medium"], dm)
+        hi, lo, m2, _ = darts.render_transient(sc, p0, mode, table, want_m2=True)
+        torch.cuda.synchronize()
+        n = darts.paths_per_cell(sc, p0, mode).numpy()
+        s = (hi.double() + lo.double()).cpu().numpy()
+        mm = m2.double().cpu().numpy()
+        mean = s / n
+        var_path = np.maximum(mm / n - mean ** 2, 0) * n / np.maximum(n - 1, 1)
+        means[mode] = mean
+        res[mode] = var_path
+    q95 = float(np.quantile(means["darts"], 0.95))
+    ncell = means["darts"].size
+    t0 = time.perf_counter()
+    darts.build_da_tables(sc["medium"], dm)
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    rep = {"target": target, "normalisation": "0.95 quantile of the DARTS image", "q95": q95,
+           "method": "per-cell variance from a 2^26-path render (seed 0xEF), MSE ~ 1/N, "
+                     "wall time = N*/measured paths/s + table build"}
+    thr = {"darts": out["value"], "uniform": out.get("uniform", {}).get("paths_per_s")}
+    for mode in ["darts", "uniform"]:
+        # MSE with N paths in total (N/ncell per cell)
+        mse_per_path_per_cell = float(res[mode].mean()) / q95 ** 2
+        n_star = mse_per_path_per_cell * ncell / target
+        rep[mode] = {"paths_needed": n_star, "mse_at_2^28": mse_per_path_per_cell * ncell / (1 << 28)}
+        if thr[mode]:
+            rep[mode]["seconds"] = n_star / thr[mode] + t_table
+    if "seconds" in rep["darts"] and "seconds" in rep["uniform"]:
+        rep["uniform_over_darts"] = rep["uniform"]["seconds"] / rep["darts"]["seconds"]
+    return rep
+
+
+def cpu_baseline(w, seconds):
+    """The oracle as it stands on the host cores: DARTS on the same box
+    workload, doubling the sample until about `seconds` of work."""
+    from oracle import ref
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    _, cdf = ref.build_table(sc["medium"], dm, n_threads=threads)
+    n = 1 << 16
+    while True:
+        p = dict(pr, n_paths=n)
+        t0 = time.perf_counter()
+        ref.render(sc, p, "darts", cdf, dm, n_threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= seconds or n >= (1 << 26):
+            break
+        n = n * 2 if dt * 2.5 < seconds else int(n * seconds / max(dt, 1e-3))
+    return {"value": n / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} DARTS paths of the box workload (ids 0..{n - 1}), FP64, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -117,11 +117,16 @@ typedef struct {
     unsigned flags;        /* DARTS_* strategy bits                              */
 } darts_params;
 
-/* Statistics counters (uint64 each, accumulated with atomics). */
+/* Statistics counters (uint64 each, accumulated with atomics): paths
+ * started; vertices that reached the early-exit test; connections that added
+ * a non-zero contribution; early exits (nothing reachable inside the gate);
+ * walks that left the medium; RIS steps with no valid candidate; EDA-branch
+ * direction samples; paths stopped at max_bounces; paths that contributed
+ * nothing; early exits already at the path's first vertex. */
 enum {
     DARTS_ST_PATHS = 0, DARTS_ST_VERTICES, DARTS_ST_CONNECTIONS, DARTS_ST_EARLY_EXIT,
     DARTS_ST_MEDIUM_EXIT, DARTS_ST_RIS_ALL_INVALID, DARTS_ST_EDA_BRANCH,
-    DARTS_ST_TRUNCATED, DARTS_ST_ZERO_PATHS, DARTS_ST_COUNT = 16
+    DARTS_ST_TRUNCATED, DARTS_ST_ZERO_PATHS, DARTS_ST_SETUP_EXIT, DARTS_ST_COUNT = 16
 };
 
 /* Size in bytes of the cdf array of a table of these dimensions.
@@ -199,6 +204,9 @@ enum {
     DARTS_PW_DIRECTION,   /* in: x[3], xe[3], w_prev[3], S, u[4], use_eda, alpha
                                                          out: w[3], weight, eda_branch
                                                          (medium, table)               */
+    DARTS_PW_MATH,        /* in: x                       out: rcp, rsqrt, log2, exp2 of x,
+                                                         sin 2 pi x, cos 2 pi x (hardware
+                                                         transcendental unit)          */
     DARTS_PW_COUNT
 };
 int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n,

@@ -72,7 +72,10 @@ double ref_u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
 
 /* Random-number layout shared with the GPU library (an interface, not code):
  * key = (seed low 32, seed high 32); counter = (path low 32, path high 32,
- * vertex index or 0xFFFFFFFF for camera set-up, stream). */
+ * vertex index, stream).  Stream 0 of vertex 0 (where no direction is
+ * sampled) drives the camera set-up; stream 0 of vertex k >= 1 the direction
+ * at vertex k; stream 1 of vertex k the connection and the free flight from
+ * vertex k.  The forward walk uses stream 2 (0xFFFFFFFF for its set-up). */
 static void draw(uint64_t seed, uint64_t path, uint32_t vertex, uint32_t stream, uint32_t out[4])
 {
     uint32_t ctr[4] = { (uint32_t)path, (uint32_t)(path >> 32), vertex, stream };
@@ -482,7 +485,7 @@ static void setup_path(const ref_scene *sc, const ref_params *pr, uint64_t p, pa
     ps->pixel = ps->cell % npix;
     int64_t b = ps->cell / npix;
     uint32_t r[4];
-    draw(pr->seed, p, CAMERA_VERTEX, 0, r);
+    draw(pr->seed, p, 0u, 0, r);
     double u0 = ref_u01(r[0]), u1 = ref_u01(r[1]), u2 = ref_u01(r[2]);
     double pos[3], w[3];
     if (sn->kind == 1) {
@@ -785,6 +788,28 @@ static int nthreads_eff(int n)
     (void)n;
     return 1;
 #endif
+}
+
+int ref_render_paths_steps(const ref_scene *sc, const ref_params *pr,
+                           const ref_table_dims *dims, const float *cdf,
+                           int32_t *path_steps, int n_threads)
+{
+    if (check_args(sc, pr)) return -1;
+    if (pr->flags & (REF_DIRECT_REUSE | REF_FORWARD)) return -1;
+    int nt = nthreads_eff(n_threads);
+    int64_t n = (int64_t)pr->n_paths;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        ref_stats S;
+        memset(&S, 0, sizeof S);
+        int64_t cell;
+        trace_darts(sc, pr, dims, cdf, pr->path_offset + (uint64_t)i, &cell, &S);
+        path_steps[i] = (int32_t)(S.st[REF_ST_VERTICES] - S.st[REF_ST_EARLY_EXIT]);
+    }
+    (void)nt;
+    return 0;
 }
 
 int ref_render_paths(const ref_scene *sc, const ref_params *pr,

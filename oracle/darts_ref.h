@@ -152,6 +152,12 @@ int ref_render_paths(const ref_scene *sc, const ref_params *pr,
                      const ref_table_dims *dims, const float *cdf,
                      double *path_value, int64_t *path_cell, int n_threads);
 
+/* Number of vertex steps (vertices that passed the early-exit test) of each
+ * path, for work-distribution studies. */
+int ref_render_paths_steps(const ref_scene *sc, const ref_params *pr,
+                           const ref_table_dims *dims, const float *cdf,
+                           int32_t *path_steps, int n_threads);
+
 /* Per-path contributions for an explicit list of path ids. */
 int ref_render_path_list(const ref_scene *sc, const ref_params *pr,
                          const ref_table_dims *dims, const float *cdf,

@@ -134,6 +134,9 @@ def lib():
         L.ref_render_paths.restype = C.c_int
         L.ref_render_paths.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
                                        C.POINTER(C.c_float), pd, C.POINTER(C.c_int64), C.c_int]
+        L.ref_render_paths_steps.restype = C.c_int
+        L.ref_render_paths_steps.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
+                                             C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int]
         L.ref_render_path_list.restype = C.c_int
         L.ref_render_path_list.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
                                            C.POINTER(C.c_float), C.POINTER(C.c_uint64), C.c_int64, pd,
@@ -266,6 +269,21 @@ def render_paths(sc: dict, p: dict, mode: str, table=None, dims_: dict | None = 
     if rc:
         raise ValueError(f"ref_render_paths failed: {rc}")
     return val, cell
+
+
+def render_paths_steps(sc: dict, p: dict, mode: str, table=None, dims_: dict | None = None, n_threads: int = 0):
+    """Vertex steps per path (DARTS family)."""
+    holder = _SceneHolder(sc)
+    pr = params(p, mode)
+    out = np.zeros(int(p["n_paths"]), np.int32)
+    cdf = None if table is None else np.ascontiguousarray(table, np.float32)
+    dptr = C.byref(dims(dims_)) if (cdf is not None) else None
+    cptr = cdf.ctypes.data_as(C.POINTER(C.c_float)) if cdf is not None else None
+    rc = lib().ref_render_paths_steps(C.byref(holder.c), C.byref(pr), dptr, cptr,
+                                      out.ctypes.data_as(C.POINTER(C.c_int32)), int(n_threads))
+    if rc:
+        raise ValueError(f"ref_render_paths_steps failed: {rc}")
+    return out
 
 
 def render_path_list(sc: dict, p: dict, mode: str, ids, table=None, dims_: dict | None = None,

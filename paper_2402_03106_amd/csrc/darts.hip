@@ -58,6 +58,7 @@ struct KParams {
     int sensor_kind;
     float origin[3], dir[3], du[3], dv[3];
     int width, height;
+    float inv_width, inv_height;
     float beta0;
     float l_lo, l_hi, delta;
     int n_bins;
@@ -67,10 +68,11 @@ struct KParams {
     float alpha;
     unsigned flags;
     int64_t npix, ncells;
-    // work decomposition: launch covers ids [q0*ncells + r0, q1*ncells + r1)
+    // work decomposition: the launch covers path ids [q0*ncells + r0, q1*ncells + r1);
+    // cell c holds repetitions m in [q0 + (c < r0), q1 + (c < r1)); waves own
+    // tiles of 64 cells and chunks of chunk_reps repetitions
     uint64_t q0, r0, q1, r1;
-    uint64_t n_items;
-    uint64_t chunk;
+    uint64_t n_tiles, max_reps, chunk_reps, n_waves;
     Table tb;
     float *hi, *lo, *m2;
     unsigned long long *stats;
@@ -80,12 +82,17 @@ struct KParams {
 };
 
 constexpr int kBlock = 256;
-constexpr uint32_t kCameraVertex = 0xFFFFFFFFu;
 
 enum { OUT_IMAGE = 0, OUT_PATHS = 1, OUT_GRAD = 2 };
 
+// Per-lane statistics counters; with ON = false every increment compiles away.
+template <bool ON>
 struct Stats {
     uint32_t v[DARTS_ST_COUNT];
+    __device__ __forceinline__ void inc(int i, uint32_t by = 1u)
+    {
+        if (ON) v[i] += by;
+    }
 };
 
 // Per-path state carried across vertices.
@@ -97,16 +104,30 @@ struct PathState {
     float C;          // distance to the emitter
     float dm;         // distance to the boundary along w (inf: infinite medium)
     int k;            // vertex index
-    int em;           // emitter index
+    V3 xe;            // chosen emitter position
+    float em_scale;   // its intensity power / (4 pi) divided by its selection probability
     float acc;        // sum of this path's contributions
     // derivative bookkeeping for the backward pass (detached sampling)
     float L_med;      // in-medium length walked so far
     float dlog_g;     // sum of d log f_HG / dg over walk vertices so far
 };
 
-__device__ __forceinline__ V3 em_pos(const KParams &P, int j)
+// Emitter j's position, start and scale by an unrolled select over the
+// kernel-argument arrays (a dynamic index into the by-value parameter block
+// would force a copy of the block to scratch memory).
+__device__ __forceinline__ void emitter(const KParams &P, int j, V3 &pos, float &start, float &scale)
 {
-    return V3{P.em_pos[j][0], P.em_pos[j][1], P.em_pos[j][2]};
+    pos = V3{P.em_pos[0][0], P.em_pos[0][1], P.em_pos[0][2]};
+    start = P.em_start[0];
+    scale = P.em_scale[0];
+#pragma unroll
+    for (int i = 1; i < DARTS_MAX_EMITTERS; ++i) {
+        if (i < P.n_em && i == j) {
+            pos = V3{P.em_pos[i][0], P.em_pos[i][1], P.em_pos[i][2]};
+            start = P.em_start[i];
+            scale = P.em_scale[i];
+        }
+    }
 }
 
 __device__ __forceinline__ float dlog_hg_dg(float mu, float g)
@@ -116,43 +137,45 @@ __device__ __forceinline__ float dlog_hg_dg(float mu, float g)
 }
 
 // Path set-up (Section III; Section V-A: the target interval is fixed per
-// path by the stratified cell map).  Returns false if the path cannot
-// contribute (camera ray misses the medium, or nothing reachable).
-__device__ bool setup_path(const KParams &P, uint64_t p, int64_t bin, int px, int py,
-                           PathState &s, Stats &st, bool vanilla)
+// path by the stratified cell map) from the camera uniforms r (stream 0 of
+// vertex 0).  Returns false if the path cannot contribute (the camera ray
+// misses the medium, or nothing is reachable inside the gate).
+template <class ST>
+__device__ bool setup_path(const KParams &P, U4 r, int64_t bin, int px, int py, PathState &s, ST &st,
+                           bool vanilla)
 {
-    const U4 r = philox((uint32_t)p, (uint32_t)(p >> 32), kCameraVertex, 0u, P.key0, P.key1);
     const float u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z);
     V3 pos, w;
     if (P.sensor_kind == 1) {
-        const float fu = ((float)px + u0) / (float)P.width, fv = ((float)py + u1) / (float)P.height;
+        const float fu = ((float)px + u0) * P.inv_width, fv = ((float)py + u1) * P.inv_height;
         pos = V3{P.origin[0] + fu * P.du[0] + fv * P.dv[0], P.origin[1] + fu * P.du[1] + fv * P.dv[1],
                  P.origin[2] + fu * P.du[2] + fv * P.dv[2]};
         w = V3{P.dir[0], P.dir[1], P.dir[2]};
     } else {
         pos = V3{P.origin[0], P.origin[1], P.origin[2]};
         const float mu = 1.f - 2.f * u0;
-        const float sn = sqrtf(fmaxf((1.f - mu) * (1.f + mu), 0.f));
+        const float sn = hw_sqrt(fmaxf((1.f - mu) * (1.f + mu), 0.f));
         float sp, cp;
-        sincospif(2.f * u1, &sp, &cp);
+        sincos_rev(u1, sp, cp);
         w = V3{sn * cp, sn * sp, mu};
     }
     int j = (int)(u2 * (float)P.n_em);
     j = min(j, P.n_em - 1);
-    s.em = j;
+    float start;
+    emitter(P, j, s.xe, start, s.em_scale);
     s.beta = P.beta0;
     s.k = 0;
     s.acc = 0.f;
     s.L_med = 0.f;
     s.dlog_g = 0.f;
     if (vanilla) {
-        s.G_lo = P.l_lo - P.em_start[j];
-        s.G_hi = P.l_hi - P.em_start[j];
+        s.G_lo = P.l_lo - start;
+        s.G_hi = P.l_hi - start;
     } else {
-        s.G_lo = fmaf((float)bin, P.delta, P.l_lo) - P.em_start[j];
-        s.G_hi = fmaf((float)(bin + 1), P.delta, P.l_lo) - P.em_start[j];
+        s.G_lo = fmaf((float)bin, P.delta, P.l_lo) - start;
+        s.G_hi = fmaf((float)(bin + 1), P.delta, P.l_lo) - start;
     }
-    st.v[DARTS_ST_PATHS]++;
+    st.inc(DARTS_ST_PATHS);
     float t_in = 0.f, t_out = kInf;
     if (P.box) {
         if (!box_entry(P.bx, pos, w, t_in, t_out)) return false;
@@ -161,9 +184,13 @@ __device__ bool setup_path(const KParams &P, uint64_t p, int64_t bin, int px, in
     s.w = w;
     s.Le = t_in;
     s.dm = P.box ? t_out - t_in : kInf;
-    s.C = length(em_pos(P, j) - s.x);
-    st.v[DARTS_ST_VERTICES]++;
-    if (s.G_hi - s.Le <= s.C) { st.v[DARTS_ST_EARLY_EXIT]++; return false; }
+    s.C = length(s.xe - s.x);
+    st.inc(DARTS_ST_VERTICES);
+    if (s.G_hi - s.Le <= s.C) {
+        st.inc(DARTS_ST_EARLY_EXIT);
+        st.inc(DARTS_ST_SETUP_EXIT);
+        return false;
+    }
     return true;
 }
 
@@ -176,12 +203,14 @@ __device__ bool setup_path(const KParams &P, uint64_t p, int64_t bin, int px, in
 // the log path throughput w.r.t. (sigma_s, sigma_a, g) of the connected path.
 __device__ float connect(const KParams &P, const PathState &s, float u4, float *dlog)
 {
-    const V3 xe = em_pos(P, s.em);
+    const V3 xe = s.xe;
     const V3 de = xe - s.x;
     const float C = s.C;
     if (!(C > 0.f)) return 0.f;
-    const float b = dot(s.w, de);
-    const float cm = fmaxf(C - b, 0.f);
+    // cm = C (1 - mu) = C |w - a|^2 / 2 with a the unit vector to the emitter:
+    // no cancellation when the ray points almost at the emitter
+    const V3 dw = s.w - de * rcp(C);
+    const float cm = 0.5f * C * dot(dw, dw);
     const float R_lo = s.G_lo - s.Le, R_hi = s.G_hi - s.Le;
     float S_exit = kInf;
     if (P.box) S_exit = s.dm + length(fma3(s.x, s.w, s.dm) - xe);
@@ -192,8 +221,9 @@ __device__ float connect(const KParams &P, const PathState &s, float u4, float *
     const bool texp = (P.flags & DARTS_ELL_TEXP) != 0;
     float S, mass = 0.f;
     if (texp) {
-        mass = texp_mass(m.sigma_t, W);
-        S = S_lo + texp_sample(u4, m.inv_sigma_t, mass, expf(-m.sigma_t * W));
+        float emass;
+        mass = one_minus_exp_neg(m.sigma_t * W, emass);
+        S = S_lo + texp_sample(u4, m.ln2_over_sigma_t, mass, emass);
     } else {
         S = fmaf(u4, W, S_lo);
     }
@@ -201,17 +231,18 @@ __device__ float connect(const KParams &P, const PathState &s, float u4, float *
     ellipse(S, C, cm, den, t, r);
     if (!(den > 0.f) || !(r > 0.f)) return 0.f;
     const V3 xc = fma3(s.x, s.w, t);
-    const V3 wc = (xe - xc) * (1.f / r);
+    const float ir = rcp(r);
+    const V3 wc = (xe - xc) * ir;
     const float r_in = P.box ? fminf(r, box_exit(P.bx, xc, wc)) : r;
     const float mu_c = dot(s.w, wc);
     const float f = hg_pdf(mu_c, m.g);
-    const float scale = s.beta * P.em_scale[s.em] * f / (r * den);
+    const float scale = s.beta * s.em_scale * f * ir * rcp(den);
     float c;
     if (texp) {
         // e^{-sigma_t (t + r_in)} / p(S) = (mass / sigma_t) e^{-sigma_t (S_lo - (r - r_in))}
-        c = scale * m.albedo * mass * __expf(-m.sigma_t * (S_lo - (r - r_in)));
+        c = scale * m.albedo * mass * fast_exp(-m.sigma_t * (S_lo - (r - r_in)));
     } else {
-        c = scale * m.sigma_s * W * __expf(-m.sigma_t * (t + r_in));
+        c = scale * m.sigma_s * W * fast_exp(-m.sigma_t * (t + r_in));
     }
     if (dlog) {
         const float Lm = s.L_med + t + r_in;               // in-medium length
@@ -223,41 +254,57 @@ __device__ float connect(const KParams &P, const PathState &s, float u4, float *
     return c;
 }
 
-// One vertex of the DARTS family: connection at vertex k, then free flight
-// (medium-event Bernoulli, Eq. (12); DA-RIS or exponential distance), the
-// early-exit test at the new vertex and direction sampling there.  Returns
-// false when the path has ended.
-template <int OUT>
-__device__ bool step_darts(const KParams &P, uint64_t p, PathState &s, Stats &st, float grad_w, double *gacc)
+// Direction at vertex k >= 1 (DARTS family), from stream 0 of vertex k.
+template <int OUT, class ST>
+__device__ __forceinline__ void direction_darts(const KParams &P, PathState &s, U4 r0, ST &st)
+{
+    const Medium &m = P.med;
+    const V3 de = s.xe - s.x;
+    float weight;
+    bool eb;
+    const V3 wp = s.w;
+    s.w = sample_direction(m, P.tb, P.alpha, (P.flags & DARTS_EDA_DIR) != 0, de * rcp(s.C), s.C, s.G_hi - s.Le,
+                           wp, r0, weight, eb);
+    if (OUT == OUT_GRAD) s.dlog_g += dlog_hg_dg(dot(wp, s.w), m.g);
+    st.inc(DARTS_ST_EDA_BRANCH, eb ? 1u : 0u);
+    s.beta *= weight;
+    s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
+}
+
+// Connection at vertex k and free flight from it (DARTS family, stream 1 of
+// vertex k): medium-event Bernoulli (Eq. (12)), DA-RIS or exponential
+// distance, then the early-exit test at the new vertex.  Returns false when
+// the path has ended.
+template <int OUT, class ST>
+__device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &st, float grad_w, double *gacc)
 {
     const Medium &m = P.med;
     const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
     float dl[3];
     const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD ? dl : nullptr);
     if (c != 0.f) {
-        st.v[DARTS_ST_CONNECTIONS]++;
+        st.inc(DARTS_ST_CONNECTIONS);
         s.acc += c;
         if (OUT == OUT_GRAD) {
             const double cw = (double)c * (double)grad_w;
             gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
         }
     }
-    if (s.k == P.max_bounces - 1) { st.v[DARTS_ST_TRUNCATED]++; return false; }
-    const float pc = P.box ? texp_mass(m.sigma_t, s.dm) : 1.f;
+    if (s.k == P.max_bounces - 1) { st.inc(DARTS_ST_TRUNCATED); return false; }
+    float epc = 0.f;
+    const float pc = P.box ? one_minus_exp_neg(m.sigma_t * s.dm, epc) : 1.f;
     const float u5 = u01(r1.y);
-    if (!(u5 < pc)) { st.v[DARTS_ST_MEDIUM_EXIT]++; return false; }
-    const V3 xe = em_pos(P, s.em);
+    if (!(u5 < pc)) { st.inc(DARTS_ST_MEDIUM_EXIT); return false; }
     float d, factor;
     if (P.flags & DARTS_RIS_DIST) {
-        const V3 de = xe - s.x;
-        const float epc = P.box ? expf(-m.sigma_t * s.dm) : 0.f;
+        const V3 de = s.xe - s.x;
         if (!ris_distance(m, s.C * s.C, dot(s.w, de), s.G_hi - s.Le, pc, epc, r1.y & 31u, r1.z, u01(r1.w), d,
                           factor)) {
-            st.v[DARTS_ST_RIS_ALL_INVALID]++;
+            st.inc(DARTS_ST_RIS_ALL_INVALID);
             return false;
         }
     } else {
-        d = texp_sample(u5, m.inv_sigma_t, 1.f, 0.f);   // plain exponential, given u5 < pc
+        d = texp_sample(u5, m.ln2_over_sigma_t, 1.f, 0.f);   // plain exponential, given u5 < pc
         factor = m.albedo;
     }
     s.x = fma3(s.x, s.w, d);
@@ -265,21 +312,9 @@ __device__ bool step_darts(const KParams &P, uint64_t p, PathState &s, Stats &st
     s.L_med += d;
     s.beta *= factor;
     s.k += 1;
-    const V3 de = xe - s.x;
-    s.C = length(de);
-    st.v[DARTS_ST_VERTICES]++;
-    const float R_hi = s.G_hi - s.Le;
-    if (R_hi <= s.C) { st.v[DARTS_ST_EARLY_EXIT]++; return false; }
-    const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 0u, P.key0, P.key1);
-    float weight;
-    bool eb;
-    const V3 wp = s.w;
-    s.w = sample_direction(m, P.tb, P.alpha, (P.flags & DARTS_EDA_DIR) != 0, de * (1.f / s.C), s.C, R_hi,
-                           wp, r0, weight, eb);
-    if (OUT == OUT_GRAD) s.dlog_g += dlog_hg_dg(dot(wp, s.w), m.g);
-    st.v[DARTS_ST_EDA_BRANCH] += eb ? 1u : 0u;
-    s.beta *= weight;
-    s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
+    s.C = length(s.xe - s.x);
+    st.inc(DARTS_ST_VERTICES);
+    if (s.G_hi - s.Le <= s.C) { st.inc(DARTS_ST_EARLY_EXIT); return false; }
     return true;
 }
 
@@ -294,120 +329,184 @@ __device__ __forceinline__ void add_compensated(float *hi, float *lo, int64_t i,
 // Vanilla transient path tracing (the paper's baseline): exponential free
 // flight, phase sampling, a shadow connection at every medium vertex, each
 // connection binned by its total length.
-__device__ bool step_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathState &s, Stats &st)
+__device__ __forceinline__ void direction_vanilla(const KParams &P, PathState &s, U4 r0)
+{
+    float mu, sn;
+    hg_sample(u01(r0.y), P.med.g, mu, sn);
+    s.w = from_frame(s.w, mu, sn, u01(r0.z));
+    s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
+}
+
+template <class ST>
+__device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathState &s, ST &st)
 {
     const Medium &m = P.med;
     const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
     const float pc = P.box ? texp_mass(m.sigma_t, s.dm) : 1.f;
     const float u5 = u01(r1.y);
-    if (!(u5 < pc)) { st.v[DARTS_ST_MEDIUM_EXIT]++; return false; }
-    const float d = texp_sample(u5, m.inv_sigma_t, 1.f, 0.f);
+    if (!(u5 < pc)) { st.inc(DARTS_ST_MEDIUM_EXIT); return false; }
+    const float d = texp_sample(u5, m.ln2_over_sigma_t, 1.f, 0.f);
     s.x = fma3(s.x, s.w, d);
     s.Le += d;
     s.beta *= m.albedo;
     s.k += 1;
-    const V3 xe = em_pos(P, s.em);
-    const V3 de = xe - s.x;
+    const V3 de = s.xe - s.x;
     const float r = length(de);
     s.C = r;
     {
-        const V3 wc = de * (1.f / r);
+        const float ir = rcp(r);
+        const V3 wc = de * ir;
         const float r_in = P.box ? fminf(r, box_exit(P.bx, s.x, wc)) : r;
-        const float L = s.Le + r + P.em_start[s.em];
+        // total length with the emitter's start offset: G_lo = l_lo - start
+        const float L = s.Le + r + (P.l_lo - s.G_lo);
         const int bin = (int)floorf((L - P.l_lo) / P.delta);
         if (L >= P.l_lo && bin >= 0 && bin < P.n_bins) {
-            const float v = s.beta * P.em_scale[s.em] * hg_pdf(dot(s.w, wc), m.g) * __expf(-m.sigma_t * r_in) / (r * r);
+            const float v = s.beta * s.em_scale * hg_pdf(dot(s.w, wc), m.g) * fast_exp(-m.sigma_t * r_in) * ir * ir;
             const int64_t cell = (int64_t)bin * P.npix + pixel;
             add_compensated(P.hi, P.lo, cell, v, 0.f);
             if (P.m2) unsafeAtomicAdd(P.m2 + cell, v * v);
-            st.v[DARTS_ST_CONNECTIONS]++;
+            st.inc(DARTS_ST_CONNECTIONS);
             s.acc += v;
         }
     }
-    if (s.k == P.max_bounces) { st.v[DARTS_ST_TRUNCATED]++; return false; }
-    st.v[DARTS_ST_VERTICES]++;
-    if (s.G_hi - s.Le <= s.C) { st.v[DARTS_ST_EARLY_EXIT]++; return false; }
-    const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 0u, P.key0, P.key1);
-    float mu, sn;
-    hg_sample(u01(r0.y), m.g, mu, sn);
-    s.w = from_frame(s.w, mu, sn, u01(r0.z));
-    s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
+    if (s.k == P.max_bounces) { st.inc(DARTS_ST_TRUNCATED); return false; }
+    st.inc(DARTS_ST_VERTICES);
+    if (s.G_hi - s.Le <= s.C) { st.inc(DARTS_ST_EARLY_EXIT); return false; }
     return true;
 }
+
+// Render kernel.  Each wave owns a tile of 64 consecutive cells (later time
+// bins first) and a range of repetitions; its lanes pull the next path of the
+// tile as soon as their current path ends (ballot + popcount on a wave-uniform
+// counter, no memory atomics), so lanes stay busy until the tile's pool is
+// empty.  One loop iteration is: stream-0 Philox of the current vertex ->
+// camera set-up (fresh path) or direction sampling; stream-1 Philox ->
+// connection and free flight.  Per-cell sums are compensated LDS
+// accumulators (one slot per tile cell), flushed with one compensated global
+// atomic pair per cell when the wave's pool is drained.
+enum { LANE_NEED = 0, LANE_FRESH = 1, LANE_ACTIVE = 2, LANE_DONE = 3 };
 
 template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS>
 __global__ __launch_bounds__(kBlock) void render_kernel(KParams P)
 {
-    const uint64_t w = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool have = w < P.n_items;
-    const int64_t cp = have ? (int64_t)(w % (uint64_t)P.ncells) : 0;
-    const int64_t c = P.ncells - 1 - cp;          // latest time bin first
-    const uint64_t j = have ? w / (uint64_t)P.ncells : 0;
-    const uint64_t m_lo = P.q0 + ((uint64_t)c < P.r0 ? 1 : 0);
-    const uint64_t m_hi = P.q1 + ((uint64_t)c < P.r1 ? 1 : 0);
-    uint64_t m = m_lo + j * P.chunk;
-    uint64_t m_end = have ? min(m + P.chunk, m_hi) : m;
-    const int64_t bin = c / P.npix;
-    const int64_t pixel = c - bin * P.npix;
-    const int px = (int)(pixel % P.width), py = (int)(pixel / P.width);
-    const float grad_w = (OUT == OUT_GRAD && have) ? P.grad_image[c] : 0.f;
+    __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const bool have = wave < P.n_waves;
+    const uint64_t tile = have ? wave % P.n_tiles : 0;
+    const uint64_t chunk = have ? wave / P.n_tiles : 0;
+    const int64_t c0 = (int64_t)(P.n_tiles - 1 - tile) * 64;         // later bins first
+    const uint64_t j_begin = chunk * P.chunk_reps * 64;
+    const uint64_t j_end = have ? min((chunk + 1) * P.chunk_reps, P.max_reps) * 64 : j_begin;
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    acc_hi[threadIdx.x] = 0.f;
+    acc_lo[threadIdx.x] = 0.f;
+    acc_m2[threadIdx.x] = 0.f;
 
-    Stats st;
+    Stats<STATS> st;
 #pragma unroll
     for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     PathState s;
-    bool alive = false;
+    uint64_t next = j_begin;
+    int state = have ? LANE_NEED : LANE_DONE;
     uint64_t p = 0;
-    float lane_hi = 0.f, lane_lo = 0.f, lane_m2 = 0.f;
+    int slot = 0;
+    int64_t bin = 0, pixel = 0;
+    float grad_w = 0.f;
     double gacc[3] = {0.0, 0.0, 0.0};
 
     while (true) {
-        if (!alive) {
-            if (m >= m_end) break;
-            p = (uint64_t)c + m * (uint64_t)P.ncells;
-            ++m;
-            alive = setup_path(P, p, bin, px, py, s, st, MODE == 1);
-            if (!alive) {
-                st.v[DARTS_ST_ZERO_PATHS]++;
-                if (OUT == OUT_PATHS) P.path_out[p - P.path_offset] = 0.f;
-                continue;
+        const bool want = state == LANE_NEED;
+        const uint64_t need = __ballot(want);
+        if (need) {
+            if (want) {
+                const uint64_t j = next + (uint64_t)__popcll(need & lanes_below);
+                if (j >= j_end) {
+                    state = LANE_DONE;
+                } else {
+                    const int sl = (int)(j & 63);
+                    const uint64_t rep = j >> 6;
+                    const int64_t cell = c0 + sl;
+                    const uint64_t m = P.q0 + ((uint64_t)cell < P.r0 ? 1 : 0) + rep;
+                    const uint64_t m_hi = P.q1 + ((uint64_t)cell < P.r1 ? 1 : 0);
+                    if (cell < P.ncells && m < m_hi) {
+                        p = (uint64_t)cell + m * (uint64_t)P.ncells;
+                        slot = sl;
+                        if (P.ncells < 0x7FFFFFFF) {
+                            const uint32_t c32 = (uint32_t)cell, np = (uint32_t)P.npix;
+                            bin = c32 / np;
+                            pixel = c32 - (uint32_t)bin * np;
+                        } else {
+                            bin = cell / P.npix;
+                            pixel = cell - bin * P.npix;
+                        }
+                        if (OUT == OUT_GRAD) grad_w = P.grad_image[cell];
+                        state = LANE_FRESH;
+                    }   // else: an empty slot of a ragged range; pull again next iteration
+                }
             }
+            next += (uint64_t)__popcll(need);
         }
-        if (MODE == 1) alive = step_vanilla(P, p, pixel, s, st);
-        else alive = step_darts<OUT>(P, p, s, st, grad_w, gacc);
-        if (!alive) {
-            if (s.acc == 0.f) st.v[DARTS_ST_ZERO_PATHS]++;
-            if (MODE == 0) {
-                if (OUT == OUT_PATHS) {
-                    P.path_out[p - P.path_offset] = s.acc;
-                } else if (OUT == OUT_IMAGE) {
-                    const float ns = lane_hi + s.acc;
-                    lane_lo += two_sum_err(lane_hi, s.acc, ns);
-                    lane_hi = ns;
-                    lane_m2 = fmaf(s.acc, s.acc, lane_m2);
+        if (__ballot(state != LANE_DONE) == 0) break;
+        if (state == LANE_FRESH || state == LANE_ACTIVE) {
+            const bool fresh = state == LANE_FRESH;
+            const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), fresh ? 0u : (uint32_t)s.k, 0u, P.key0, P.key1);
+            bool alive = true;
+            if (fresh) {
+                const int px = (int)(pixel % P.width), py = (int)(pixel / P.width);
+                alive = setup_path(P, r0, bin, px, py, s, st, MODE == 1);
+                if (!alive) s.acc = 0.f;
+            } else if (MODE == 1) {
+                direction_vanilla(P, s, r0);
+            } else {
+                direction_darts<OUT>(P, s, r0, st);
+            }
+            if (alive) {
+                if (MODE == 1) alive = fly_vanilla(P, p, pixel, s, st);
+                else alive = connect_and_fly<OUT>(P, p, s, st, grad_w, gacc);
+            }
+            if (alive) {
+                state = LANE_ACTIVE;
+            } else {
+                state = LANE_NEED;
+                if (s.acc == 0.f) st.inc(DARTS_ST_ZERO_PATHS);
+                if (MODE == 0) {
+                    if (OUT == OUT_PATHS) {
+                        P.path_out[p - P.path_offset] = s.acc;
+                    } else if (OUT == OUT_IMAGE && s.acc != 0.f) {
+                        const float old = atomicAdd(&acc_hi[wbase + slot], s.acc);
+                        const float e = two_sum_err(old, s.acc, old + s.acc);
+                        if (e != 0.f) atomicAdd(&acc_lo[wbase + slot], e);
+                        if (P.m2) atomicAdd(&acc_m2[wbase + slot], s.acc * s.acc);
+                    }
                 }
             }
         }
     }
 
     if (MODE == 0 && OUT == OUT_IMAGE && have) {
-        if (lane_hi != 0.f || lane_lo != 0.f) add_compensated(P.hi, P.lo, c, lane_hi, lane_lo);
-        if (P.m2 && lane_m2 != 0.f) unsafeAtomicAdd(P.m2 + c, lane_m2);
+        const int64_t cell = c0 + lane;
+        const float h = acc_hi[threadIdx.x], l = acc_lo[threadIdx.x];
+        if (cell < P.ncells) {
+            if (h != 0.f || l != 0.f) add_compensated(P.hi, P.lo, cell, h, l);
+            if (P.m2 && acc_m2[threadIdx.x] != 0.f) unsafeAtomicAdd(P.m2 + cell, acc_m2[threadIdx.x]);
+        }
     }
     if (OUT == OUT_GRAD) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             double v = gacc[i];
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            if ((threadIdx.x & 63) == 0 && v != 0.0) unsafeAtomicAdd(P.grad_out + i, v);
+            if (lane == 0 && v != 0.0) unsafeAtomicAdd(P.grad_out + i, v);
         }
     }
     if (STATS) {
 #pragma unroll
-        for (int i = 0; i < DARTS_ST_ZERO_PATHS + 1; ++i) {
+        for (int i = 0; i < DARTS_ST_SETUP_EXIT + 1; ++i) {
             uint32_t v = st.v[i];
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            if ((threadIdx.x & 63) == 0 && v) atomicAdd(P.stats + i, (unsigned long long)v);
+            if (lane == 0 && v) atomicAdd(P.stats + i, (unsigned long long)v);
         }
     }
 }
@@ -542,10 +641,11 @@ __global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
     case DARTS_PW_HG_SAMPLE: hg_sample(a[0], a[1], o[0], o[1]); break;
     case DARTS_PW_DA_LOGPHI: o[0] = da_log_phi_rel(Q.med, a[0] * a[0], a[1]); break;
     case DARTS_PW_TEXP: {
-        const float mass = texp_mass(a[1], a[2]);
-        const float x = texp_sample(a[0], 1.f / a[1], mass, expf(-a[1] * a[2]));
+        float emass = 0.f;
+        const float mass = isinf(a[2]) ? 1.f : one_minus_exp_neg(a[1] * a[2], emass);
+        const float x = texp_sample(a[0], 0.69314718055994530942f / a[1], mass, emass);
         o[0] = x;
-        o[1] = a[1] * __expf(-a[1] * x) / mass;
+        o[1] = a[1] * fast_exp(-a[1] * x) * rcp(mass);
         break;
     }
     case DARTS_PW_ELLIPSE: {
@@ -572,8 +672,8 @@ __global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
         const float R_hi = a[9], d_m = a[10];
         const V3 de = xe - x;
         const float C = length(de);
-        const float pc = isinf(d_m) ? 1.f : texp_mass(Q.med.sigma_t, d_m);
-        const float epc = isinf(d_m) ? 0.f : expf(-Q.med.sigma_t * d_m);
+        float epc = 0.f;
+        const float pc = isinf(d_m) ? 1.f : one_minus_exp_neg(Q.med.sigma_t * d_m, epc);
         float d = 0.f, f = 0.f;
         const bool okk = ris_distance(Q.med, C * C, dot(w, de), R_hi, pc, epc, bits(a[11]) & 31u, bits(a[12]), a[13],
                                       d, f);
@@ -588,8 +688,15 @@ __global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
         const float C = length(de);
         float wt;
         bool eb;
-        const V3 w = sample_direction(Q.med, Q.tb, a[15], a[14] != 0.f, de * (1.f / C), C, S, wp, r, wt, eb);
+        const V3 w = sample_direction(Q.med, Q.tb, a[15], a[14] != 0.f, de * rcp(C), C, S, wp, r, wt, eb);
         o[0] = w.x; o[1] = w.y; o[2] = w.z; o[3] = wt; o[4] = eb ? 1.f : 0.f;
+        break;
+    }
+    case DARTS_PW_MATH: {
+        const float x = a[0];
+        o[0] = rcp(x); o[1] = rsq(x); o[2] = log2_hw(x); o[3] = exp2_hw(x);
+        sincos_rev(x, o[4], o[5]);
+        o[6] = hw_sqrt(x);
         break;
     }
     default: break;
@@ -631,6 +738,7 @@ Medium make_medium(const darts_medium &m)
     o.g = (float)m.g;
     const double D = 1.0 / (3.0 * (m.sigma_a + m.sigma_s * (1.0 - m.g)));
     o.inv4D = (float)(1.0 / (4.0 * D));
+    o.ln2_over_sigma_t = (float)(0.69314718055994530942 / (m.sigma_s + m.sigma_a));
     return o;
 }
 
@@ -655,7 +763,7 @@ int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &
     return DARTS_OK;
 }
 
-int64_t g_target_lanes = 1 << 20;
+int64_t g_target_waves = 1 << 14;
 
 int make_params(const darts_scene *sc, const darts_params *pr, const darts_table *table, KParams &P,
                 bool per_path_only)
@@ -715,6 +823,8 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     }
     P.width = sn.width;
     P.height = sn.height;
+    P.inv_width = 1.f / (float)sn.width;
+    P.inv_height = 1.f / (float)sn.height;
     P.beta0 = sn.kind == 0 ? (float)(4.0 * M_PI) : 1.f;
     P.l_lo = sc->bins.l_lo;
     P.l_hi = sc->bins.l_hi;
@@ -737,15 +847,19 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     P.r0 = pr->path_offset % nc;
     P.q1 = end / nc;
     P.r1 = end % nc;
-    // paths per cell: at most ceil(n / nc) + 1; split into chunks so that the
-    // launch has about g_target_lanes lanes
-    const uint64_t reps = pr->n_paths / nc + 2;
-    uint64_t n_chunks = (uint64_t)std::max<int64_t>(1, (g_target_lanes + P.ncells - 1) / P.ncells);
-    n_chunks = std::min(n_chunks, reps);
-    P.chunk = (reps + n_chunks - 1) / n_chunks;
-    n_chunks = (reps + P.chunk - 1) / P.chunk;
-    P.n_items = nc * n_chunks;
-    if (P.n_items / kBlock > 0x7FFFFFFFull) return fail(DARTS_ERR_INVALID_ARG, "launch too large");
+    // repetitions per cell: at most ceil(n / nc) + 1.  Waves own tiles of 64
+    // cells; the repetitions are split into chunks (of at least 32, so that a
+    // wave's pool amortises its last path) until the launch has about
+    // g_target_waves waves.
+    P.max_reps = (P.q1 + (P.r1 > 0 ? 1 : 0)) - P.q0;
+    P.n_tiles = (nc + 63) / 64;
+    uint64_t n_chunks = (uint64_t)std::max<int64_t>(1, (g_target_waves + (int64_t)P.n_tiles - 1) / (int64_t)P.n_tiles);
+    n_chunks = std::max<uint64_t>(1, std::min(n_chunks, (P.max_reps + 31) / 32));
+    P.chunk_reps = (P.max_reps + n_chunks - 1) / n_chunks;
+    if (P.chunk_reps == 0) P.chunk_reps = 1;
+    n_chunks = (P.max_reps + P.chunk_reps - 1) / P.chunk_reps;
+    P.n_waves = P.n_tiles * n_chunks;
+    if (P.n_waves / (kBlock / 64) > 0x7FFFFFFFull) return fail(DARTS_ERR_INVALID_ARG, "launch too large");
     P.hi = P.lo = P.m2 = nullptr;
     P.stats = nullptr;
     P.path_out = nullptr;
@@ -757,7 +871,7 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
 template <int MODE, int OUT>
 int launch_render(const KParams &P, bool stats, hipStream_t stream)
 {
-    const uint64_t blocks = (P.n_items + kBlock - 1) / kBlock;
+    const uint64_t blocks = (P.n_waves + kBlock / 64 - 1) / (kBlock / 64);
     if (blocks == 0 || P.n_paths == 0) return ok();
     if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, stream, P);
     else hipLaunchKernelGGL((render_kernel<MODE, OUT, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, stream, P);
@@ -874,11 +988,11 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
     return ok();
 }
 
-// Tuning knob (not part of the stable ABI): lanes a render launch aims for.
-int darts_set_target_lanes(int64_t lanes)
+// Tuning knob (not part of the stable ABI): waves a render launch aims for.
+int darts_set_target_waves(int64_t waves)
 {
-    if (lanes < 64) return fail(DARTS_ERR_INVALID_ARG, "target lanes must be >= 64");
-    g_target_lanes = lanes;
+    if (waves < 1) return fail(DARTS_ERR_INVALID_ARG, "target waves must be >= 1");
+    g_target_waves = waves;
     return ok();
 }
 

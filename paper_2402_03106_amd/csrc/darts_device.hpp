@@ -12,13 +12,30 @@ constexpr float kPi = 3.14159265358979323846f;
 constexpr float kInv4Pi = 0.0795774715459476679f;   // 1 / (4 pi)
 constexpr float kInf = __builtin_huge_valf();
 
+// Hardware transcendental helpers (gfx950 VALU transcendental unit):
+// v_rcp_f32, v_rsq_f32 and v_sqrt_f32 (1 ulp), v_log_f32 / v_exp_f32 (base 2), and
+// v_sin_f32 / v_cos_f32, whose argument is in revolutions.  Their accuracy on
+// the ranges used here is checked against FP64 by the diagnostics tests.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_log(float x) { return log2_hw(x) * 0.693147180559945309f; }
+__device__ __forceinline__ float fast_exp(float x) { return exp2_hw(x * 1.44269504088896341f); }
+__device__ __forceinline__ void sincos_rev(float u, float &s, float &c)   // sin, cos of 2 pi u
+{
+    s = __builtin_amdgcn_sinf(u);
+    c = __builtin_amdgcn_cosf(u);
+}
+
 struct V3 { float x, y, z; };
 __device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
 __device__ __forceinline__ V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ V3 operator*(V3 a, float s) { return V3{a.x * s, a.y * s, a.z * s}; }
 __device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ float length(V3 a) { return sqrtf(dot(a, a)); }
+__device__ __forceinline__ float length(V3 a) { return hw_sqrt(dot(a, a)); }
 __device__ __forceinline__ V3 fma3(V3 x, V3 w, float t) { return V3{fmaf(w.x, t, x.x), fmaf(w.y, t, x.y), fmaf(w.z, t, x.z)}; }
 
 // ---------------------------------------------------------------------------
@@ -34,10 +51,10 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;   // one 32x32->64 multiply each
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
     }
     return U4{c0, c1, c2, c3};
@@ -64,32 +81,34 @@ __device__ __forceinline__ float hg_pdf(float mu, float g)
 {
     const float den = g >= 0.f ? fmaf(2.f * g, 1.f - mu, (1.f - g) * (1.f - g))
                                : fmaf(-2.f * g, 1.f + mu, (1.f + g) * (1.f + g));
-    return (1.f - g) * (1.f + g) * kInv4Pi * rsqrtf(den) / den;
+    const float r = rsq(den);
+    return (1.f - g) * (1.f + g) * kInv4Pi * (r * r * r);
 }
 
 // Inverse CDF of HG in mu, rewritten without cancellation: with
 // t = 1 - g + 2 g xi and q = (1 - g^2)/t,
 //   1 - mu = (1 - g)(1 - xi)(q + 1 - g)/t,   1 + mu = (1 + g) xi (q + 1 + g)/t,
-// both sums of positive terms for every |g| < 1 (g = 0 gives mu = 2 xi - 1).
+// both products of non-negative terms for every |g| < 1 (g = 0 gives
+// mu = 2 xi - 1).
 __device__ __forceinline__ void hg_sample(float xi, float g, float &mu, float &sin_t)
 {
     const float t = fmaf(2.f * g, xi, 1.f - g);
-    const float it = 1.f / t;
+    const float it = rcp(t);
     const float q = (1.f - g) * (1.f + g) * it;
     const float omu = (1.f - g) * (1.f - xi) * (q + 1.f - g) * it;
     const float opu = (1.f + g) * xi * (q + 1.f + g) * it;
     mu = fminf(fmaxf(0.5f * (opu - omu), -1.f), 1.f);
-    sin_t = sqrtf(fmaxf(omu * opu, 0.f));
+    sin_t = hw_sqrt(fmaxf(omu * opu, 0.f));
 }
 
 // Orthonormal basis completing unit n (Duff et al., JCGT 2017, branchless).
 __device__ __forceinline__ void onb(V3 n, V3 &b1, V3 &b2)
 {
     const float sign = copysignf(1.f, n.z);
-    const float a = -1.f / (sign + n.z);
+    const float a = -rcp(sign + n.z);
     const float b = n.x * n.y * a;
-    b1 = V3{1.f + sign * n.x * n.x * a, sign * b, -sign * n.x};
-    b2 = V3{b, sign + n.y * n.y * a, -n.y};
+    b1 = V3{fmaf(sign * n.x * n.x, a, 1.f), sign * b, -sign * n.x};
+    b2 = V3{b, fmaf(n.y * n.y, a, sign), -n.y};
 }
 
 // Direction at cosine mu (sine s) to axis n, azimuth 2 pi u.
@@ -98,7 +117,7 @@ __device__ __forceinline__ V3 from_frame(V3 n, float mu, float s, float u)
     V3 b1, b2;
     onb(n, b1, b2);
     float sp, cp;
-    sincospif(2.f * u, &sp, &cp);
+    sincos_rev(u, sp, cp);
     const float a1 = s * cp, a2 = s * sp;
     return V3{fmaf(a1, b1.x, fmaf(a2, b2.x, mu * n.x)),
               fmaf(a1, b1.y, fmaf(a2, b2.y, mu * n.y)),
@@ -106,43 +125,55 @@ __device__ __forceinline__ V3 from_frame(V3 n, float mu, float s, float u)
 }
 
 // ---------------------------------------------------------------------------
-// Truncated exponential on [0, width) (Eq. (13)-(14)) with
-// mass = 1 - e^{-sigma width} and emass = e^{-sigma width}.
+// Truncated exponential on [0, width) (Eq. (13)-(14)).
 // ---------------------------------------------------------------------------
+// 1 - e^{-x} for x >= 0 without cancellation: for small x Kahan's rescaling
+// (1 - u) x / (-log u) with u the rounded e^{-x} (1 - u exact).
+__device__ __forceinline__ float one_minus_exp_neg(float x, float &emx)
+{
+    const float u = fast_exp(-x);
+    emx = u;
+    if (x > 0.5f) return 1.f - u;
+    if (u == 1.f) return x;
+    return (1.f - u) * x * rcp(-fast_log(u));
+}
 __device__ __forceinline__ float texp_mass(float sigma, float width)   // 1 - e^{-sigma width}
 {
-    return -expm1f(-sigma * width);
+    float e;
+    return one_minus_exp_neg(sigma * width, e);
 }
 
-// x = -log(1 - mass u) / sigma without cancellation:  when mass u < 1/2 the
-// logarithm is log1p by Kahan's rescaling (log(v) y / (1 - v) with v the
-// rounded 1 - y, exact v - 1); otherwise 1 - mass u = (1 - u) + u emass is a
-// sum of non-negative terms with 1 - u exact (u >= 1/2).
-__device__ __forceinline__ float texp_sample(float u, float inv_sigma, float mass, float emass)
+// x = -log(1 - mass u) / sigma with mass = 1 - emass, emass = e^{-sigma width},
+// without cancellation: when mass u < 1/2, log1p by Kahan's rescaling
+// (log(v) y / (v - 1) with v the rounded 1 - y and v - 1 exact); otherwise
+// 1 - mass u = (1 - u) + u emass is a sum of non-negative terms with 1 - u
+// exact (u >= 1/2).  ln2_over_sigma = ln 2 / sigma (log2 hardware result).
+__device__ __forceinline__ float texp_sample(float u, float ln2_over_sigma, float mass, float emass)
 {
     const float y = mass * u;
     const bool small = y < 0.5f;
     const float v = small ? 1.f - y : fmaf(u, emass, 1.f - u);
-    const float L = logf(v);
-    const float nl = small ? (v == 1.f ? y : L * y / (v - 1.f)) : -L;
-    return nl * inv_sigma;
+    const float L = log2_hw(v);
+    const float nl = small ? (v == 1.f ? y * 1.44269504088896341f : L * y * rcp(v - 1.f)) : -L;
+    return nl * ln2_over_sigma;
 }
+
 // ---------------------------------------------------------------------------
 // Index-matched box.
 // ---------------------------------------------------------------------------
 struct Box { float lo[3], hi[3]; };
 
-// Distance from x (inside) along unit w to the boundary.
+// Distance from x (inside) along w to the boundary, iw = componentwise 1/w.
+__device__ __forceinline__ float box_exit_inv(const Box &b, V3 x, V3 w, V3 iw)
+{
+    const float tx = w.x > 0.f ? (b.hi[0] - x.x) * iw.x : (w.x < 0.f ? (b.lo[0] - x.x) * iw.x : kInf);
+    const float ty = w.y > 0.f ? (b.hi[1] - x.y) * iw.y : (w.y < 0.f ? (b.lo[1] - x.y) * iw.y : kInf);
+    const float tz = w.z > 0.f ? (b.hi[2] - x.z) * iw.z : (w.z < 0.f ? (b.lo[2] - x.z) * iw.z : kInf);
+    return fmaxf(fminf(fminf(tx, ty), tz), 0.f);
+}
 __device__ __forceinline__ float box_exit(const Box &b, V3 x, V3 w)
 {
-    float t = kInf;
-    const float xs[3] = {x.x, x.y, x.z}, ws[3] = {w.x, w.y, w.z};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (ws[a] > 0.f) t = fminf(t, (b.hi[a] - xs[a]) / ws[a]);
-        else if (ws[a] < 0.f) t = fminf(t, (b.lo[a] - xs[a]) / ws[a]);
-    }
-    return fmaxf(t, 0.f);
+    return box_exit_inv(b, x, w, V3{rcp(w.x), rcp(w.y), rcp(w.z)});
 }
 
 // Slab test for a ray from x along w; returns false on a miss.
@@ -156,7 +187,8 @@ __device__ __forceinline__ bool box_entry(const Box &b, V3 x, V3 w, float &t_in,
         if (ws[a] == 0.f) {
             hit = hit && !(xs[a] < b.lo[a] || xs[a] > b.hi[a]);
         } else {
-            const float t1 = (b.lo[a] - xs[a]) / ws[a], t2 = (b.hi[a] - xs[a]) / ws[a];
+            const float iw = rcp(ws[a]);
+            const float t1 = (b.lo[a] - xs[a]) * iw, t2 = (b.hi[a] - xs[a]) * iw;
             tn = fmaxf(tn, fminf(t1, t2));
             tf = fminf(tf, fmaxf(t1, t2));
         }
@@ -172,14 +204,15 @@ __device__ __forceinline__ bool box_entry(const Box &b, V3 x, V3 w, float &t_in,
 struct Medium {
     float sigma_s, sigma_a, sigma_t, inv_sigma_t, albedo, g;
     float inv4D;      // 1 / (4 D), D = 1 / (3 (sigma_a + sigma_s (1 - g)))  (Eq. (9))
+    float ln2_over_sigma_t;
 };
 
 // log of the DA fluence without its constant -1.5 log(4 pi D) (Eq. (9));
 // s > 0 is the residual time, r2 the squared distance to the emitter.
 __device__ __forceinline__ float da_log_phi_rel(const Medium &m, float r2, float s)
 {
-    const float is = 1.f / s;
-    return -1.5f * __logf(s) - r2 * m.inv4D * is - m.sigma_a * s;
+    const float is = rcp(s);
+    return fmaf(-1.5f * 0.693147180559945309f, log2_hw(s), -fmaf(r2 * m.inv4D, is, m.sigma_a * s));
 }
 
 // ---------------------------------------------------------------------------
@@ -193,7 +226,7 @@ __device__ __forceinline__ void ellipse(float S, float C, float cm, float &den, 
 {
     const float sc = S - C;
     den = sc + cm;
-    const float ih = 0.5f / den;
+    const float ih = 0.5f * rcp(den);
     t = sc * (S + C) * ih;
     r = fmaf(sc, sc, 2.f * S * cm) * ih;
 }
@@ -202,7 +235,7 @@ __device__ __forceinline__ void ellipse(float S, float C, float cm, float &den, 
 // DA distance sampling by RIS with 8 candidates (Section IV-C).  Candidates
 // follow the truncated exponential on [0, d_m) (pc = 1 - e^{-sigma_t d_m});
 // weights are the DA fluence at the upper residual time R_hi - d (zero
-// outside the residual-time ellipsoid); the selection and the normalisation
+// outside the residual-time ellipsoid); the normalisation and the selection
 // run in FP64.  On success returns the distance and the factor
 // albedo * mean(w) / w_selected that multiplies the path throughput.
 // b = dot(w, x_e - x), C2 = |x_e - x|^2, epc = 1 - pc = e^{-sigma_t d_m}.
@@ -213,12 +246,13 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
 {
     float dc[8], lp[8];
     float lmax = -kInf;
+    const float two_b = 2.f * b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const float ui = sobol_u(row, (uint32_t)i, eps);
-        const float di = texp_sample(ui, m.inv_sigma_t, pc, epc);
+        const float di = texp_sample(ui, m.ln2_over_sigma_t, pc, epc);
         const float si = R_hi - di;
-        const float r2 = fmaf(di, di - 2.f * b, C2);
+        const float r2 = fmaf(di, di - two_b, C2);
         const bool valid = (si > 0.f) && (r2 < si * si);
         const float l = valid ? da_log_phi_rel(m, r2, si) : -kInf;
         dc[i] = di;
@@ -229,7 +263,7 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
     float wv[8];
     double wsum = 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { wv[i] = __expf(lp[i] - lmax); wsum += (double)wv[i]; }
+    for (int i = 0; i < 8; ++i) { wv[i] = fast_exp(lp[i] - lmax); wsum += (double)wv[i]; }
     const double target = (double)u_sel * wsum;
     double cum = 0.0;
     float dsel = dc[7], wsel = wv[7];
@@ -247,7 +281,7 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
         for (int i = 0; i < 8; ++i) if (wv[i] > 0.f) { dsel = dc[i]; wsel = wv[i]; }
     }
     d_out = dsel;
-    factor = (float)((double)m.albedo * (wsum * 0.125) / (double)wsel);
+    factor = m.albedo * ((float)wsum * 0.125f) * rcp(wsel);
     return true;
 }
 
@@ -269,8 +303,8 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
     float gam = 0.f;
     const float *row = nullptr;
     if (use_eda && C > 0.f) {
-        const float kappa = C / S;
-        gam = kappa / (kappa + alpha);
+        const float kappa = C * rcp(S);
+        gam = kappa * rcp(kappa + alpha);
         const int i = min(max((int)(kappa * (float)tb.n_cs), 0), tb.n_cs - 1);
         const int j = min(max((int)(S * tb.ns_over_smax), 0), tb.n_s - 1);
         row = tb.cdf + ((size_t)i * tb.n_s + j) * (size_t)(tb.n_cos + 1);
@@ -290,7 +324,7 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
         }
         k = lo;
         mu = fmaf((float)k + u3, 2.f / (float)tb.n_cos, -1.f);
-        s = sqrtf(fmaxf((1.f - mu) * (1.f + mu), 0.f));
+        s = hw_sqrt(fmaxf((1.f - mu) * (1.f + mu), 0.f));
         axis = a;
     } else {
         hg_sample(u1, m.g, mu, s);
@@ -307,9 +341,9 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
             c_hi = row[k + 1];
         }
         const float p_eda = (c_hi - c_lo) * (float)tb.n_cos * kInv4Pi;
-        p_mix = gam * p_eda + (1.f - gam) * p_hg;
+        p_mix = fmaf(gam, p_eda - p_hg, p_hg);
     }
-    weight = p_hg / p_mix;
+    weight = p_hg * rcp(p_mix);
     return w;
 }
 

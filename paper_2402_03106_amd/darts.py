@@ -31,12 +31,12 @@ MODES = {
 }
 MAX_EMITTERS = 8
 ST_NAMES = ["paths", "vertices", "connections", "early_exit", "medium_exit", "ris_all_invalid",
-            "eda_branch", "truncated", "zero_paths"]
+            "eda_branch", "truncated", "zero_paths", "setup_exit"]
 ST_COUNT = 16
 PW_IN, PW_OUT = 16, 8
 PW = {name: i for i, name in enumerate(
     ["philox", "hg_pdf", "hg_sample", "da_logphi", "texp", "ellipse", "sobol", "onb", "box_exit",
-     "ris", "direction"])}
+     "ris", "direction", "math"])}
 
 
 class DartsError(RuntimeError):
@@ -104,7 +104,7 @@ def lib() -> C.CDLL:
         L.darts_render_transient_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Table),
                                                       vp, vp, vp]
         L.darts_debug_pointwise.argtypes = [C.c_int, vp, vp, i64, C.POINTER(_Medium), C.POINTER(_Table), vp]
-        L.darts_set_target_lanes.argtypes = [i64]
+        L.darts_set_target_waves.argtypes = [i64]
         _lib = L
     return _lib
 
@@ -265,8 +265,8 @@ def debug_pointwise(fn: str, inputs: torch.Tensor, med: dict | None = None, tabl
     return out
 
 
-def set_target_lanes(n: int):
-    _check(lib().darts_set_target_lanes(int(n)))
+def set_target_waves(n: int):
+    _check(lib().darts_set_target_waves(int(n)))
 
 
 def stats_dict(stats: torch.Tensor) -> dict:

@@ -262,3 +262,30 @@ def test_table_matches_oracle(D, oracle):
         assert got.shape == cdf.shape
         assert np.max(np.abs(got.astype(np.float64) - cdf)) <= 1e-6
         assert np.all(got[..., 0] == 0) and np.all(got[..., -1] == 1)
+
+
+def test_hardware_transcendentals(D):
+    """Accuracy of the transcendental-unit instructions the kernels rely on,
+    over the argument ranges they see: relative error of rcp / rsqrt, absolute
+    error of log2 (never used on arguments near 1 where only absolute accuracy
+    would be available), relative error of exp2 on (-127, 0], absolute error
+    of sin/cos of 2 pi u on [0, 1)."""
+    rng = np.random.default_rng(21)
+    pos = np.concatenate([10 ** rng.uniform(-6, 6, 20000), rng.uniform(0.5, 2, 20000)]).astype(F32)
+    out, inp, _ = run(D, "math", [[x] for x in pos])
+    x = inp[:, 0]
+    rel = lambda a, b: np.max(np.abs(a / b - 1))
+    print("rcp", rel(out[:, 0], 1 / x), "rsq", rel(out[:, 1], 1 / np.sqrt(x)),
+          "log2 abs", np.max(np.abs(out[:, 2] - np.log2(x))))
+    assert rel(out[:, 0], 1 / x) < 3e-7
+    assert rel(out[:, 1], 1 / np.sqrt(x)) < 3e-7
+    assert np.max(np.abs(out[:, 2] - np.log2(x))) < 2e-6
+    far = np.abs(np.log2(x)) > 0.25
+    assert np.max(np.abs(out[far, 2] / np.log2(x[far]) - 1)) < 2e-6
+    neg = (-rng.uniform(0, 126, 20000)).astype(F32)
+    out, inp, _ = run(D, "math", [[x] for x in neg])
+    assert rel(out[:, 3], 2.0 ** inp[:, 0]) < 2e-6
+    u = rng.random(20000).astype(F32)
+    out, inp, _ = run(D, "math", [[x] for x in u])
+    assert np.max(np.abs(out[:, 4] - np.sin(2 * np.pi * inp[:, 0]))) < 2e-6
+    assert np.max(np.abs(out[:, 5] - np.cos(2 * np.pi * inp[:, 0]))) < 2e-6

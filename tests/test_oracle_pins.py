@@ -477,9 +477,10 @@ def test_estimators_agree_all_orders(oracle, mode):
     """Box medium, emitter and point detector outside it (bounded weights):
     DARTS, the uniform-S baseline, vanilla path tracing and both ablation
     arms against the forward analog walk, which shares no sampling step."""
-    mf, sf, _ = _box_point(oracle, "forward", 1 << 21)
+    mf, sf, _ = _box_point(oracle, "forward", 1 << 22)
     m, s, _ = _box_point(oracle, mode, 1 << 21)
-    ok = (sf > 0) & (mf > 1e-4 * mf.max())      # bins the forward walk resolves
+    # bins both estimators resolve (relative standard error below 15%)
+    ok = (sf > 0) & (s > 0) & (sf < 0.15 * np.abs(mf)) & (s < 0.15 * np.abs(m))
     z = (m - mf)[ok] / np.sqrt(s ** 2 + sf ** 2)[ok]
     assert np.max(np.abs(z)) < 4.0, np.round(z, 1)
     assert abs(m[ok].sum() / mf[ok].sum() - 1) < 0.02
