@@ -82,6 +82,11 @@ struct KParams {
 };
 
 constexpr int kBlock = 256;
+// Minimum resident waves per SIMD the render kernel is compiled for (caps its
+// VGPR budget at 512 / waves).
+#ifndef DARTS_RENDER_WAVES_PER_SIMD
+#define DARTS_RENDER_WAVES_PER_SIMD 4
+#endif
 
 enum { OUT_IMAGE = 0, OUT_PATHS = 1, OUT_GRAD = 2 };
 
@@ -120,6 +125,7 @@ __device__ __forceinline__ void emitter(const KParams &P, int j, V3 &pos, float 
     pos = V3{P.em_pos[0][0], P.em_pos[0][1], P.em_pos[0][2]};
     start = P.em_start[0];
     scale = P.em_scale[0];
+    if (P.n_em == 1) return;
 #pragma unroll
     for (int i = 1; i < DARTS_MAX_EMITTERS; ++i) {
         if (i < P.n_em && i == j) {
@@ -195,56 +201,84 @@ __device__ bool setup_path(const KParams &P, U4 r, int64_t bin, int px, int py, 
 }
 
 // Generalised shadow connection through a control vertex on the current ray
-// (Section V-B, case I, with the boundary clipping S_M): samples the length
-// sum S in [max(R_lo, C), min(R_hi, S_exit)), places the control vertex at
-// the polar distance t(S) (Eq. (21)) and weights it with p(t) = p(S) (S - C
+// (Section V-B, case I, with the boundary clipping S_M): the length sum S is
+// sampled in [max(R_lo, C), min(R_hi, S_exit)), the control vertex placed at
+// the polar distance t(S) (Eq. (21)) and weighted with p(t) = p(S) (S - C
 // mu)/(S - t) (Eq. (22), Jacobian taken as the text defines it).
-// Returns the contribution; dlog (if not null) receives the derivative of
-// the log path throughput w.r.t. (sigma_s, sigma_a, g) of the connected path.
-__device__ float connect(const KParams &P, const PathState &s, float u4, float *dlog)
+struct Conn {
+    V3 x, w, xe;      // vertex, ray direction, emitter
+    float C;          // |xe - x|
+    float S_lo, S_hi; // length-sum range
+    float scale;      // throughput times emitter intensity / selection probability
+    float u;          // uniform for S
+};
+
+// Range of the length sum; false if no control vertex can close the path.
+__device__ __forceinline__ bool connect_range(const KParams &P, const PathState &s, float &S_lo, float &S_hi)
 {
-    const V3 xe = s.xe;
-    const V3 de = xe - s.x;
-    const float C = s.C;
-    if (!(C > 0.f)) return 0.f;
-    // cm = C (1 - mu) = C |w - a|^2 / 2 with a the unit vector to the emitter:
-    // no cancellation when the ray points almost at the emitter
-    const V3 dw = s.w - de * rcp(C);
-    const float cm = 0.5f * C * dot(dw, dw);
+    if (!(s.C > 0.f)) return false;
     const float R_lo = s.G_lo - s.Le, R_hi = s.G_hi - s.Le;
     float S_exit = kInf;
-    if (P.box) S_exit = s.dm + length(fma3(s.x, s.w, s.dm) - xe);
-    const float S_lo = fmaxf(R_lo, C), S_hi = fminf(R_hi, S_exit);
-    if (!(S_lo < S_hi)) return 0.f;
-    const float W = S_hi - S_lo;
+    if (P.box) S_exit = s.dm + length(fma3(s.x, s.w, s.dm) - s.xe);
+    S_lo = fmaxf(R_lo, s.C);
+    S_hi = fminf(R_hi, S_exit);
+    return S_lo < S_hi;
+}
+
+// Contribution of one connection; mu_c and the in-medium lengths t, r_in
+// are returned for the derivative bookkeeping of the backward pass.
+__device__ __forceinline__ float connect_eval(const KParams &P, const Conn &q, float &mu_c, float &t_out, float &r_in_out)
+{
     const Medium &m = P.med;
+    const V3 de = q.xe - q.x;
+    const float C = q.C;
+    // cm = C (1 - mu) = C |w - a|^2 / 2 with a the unit vector to the emitter:
+    // no cancellation when the ray points almost at the emitter
+    const V3 dw = q.w - de * rcp(C);
+    const float cm = 0.5f * C * dot(dw, dw);
+    const float W = q.S_hi - q.S_lo;
     const bool texp = (P.flags & DARTS_ELL_TEXP) != 0;
     float S, mass = 0.f;
     if (texp) {
         float emass;
         mass = one_minus_exp_neg(m.sigma_t * W, emass);
-        S = S_lo + texp_sample(u4, m.ln2_over_sigma_t, mass, emass);
+        S = q.S_lo + texp_sample(q.u, m.ln2_over_sigma_t, mass, emass);
     } else {
-        S = fmaf(u4, W, S_lo);
+        S = fmaf(q.u, W, q.S_lo);
     }
     float den, t, r;
     ellipse(S, C, cm, den, t, r);
+    mu_c = 0.f;
+    t_out = 0.f;
+    r_in_out = 0.f;
     if (!(den > 0.f) || !(r > 0.f)) return 0.f;
-    const V3 xc = fma3(s.x, s.w, t);
+    const V3 xc = fma3(q.x, q.w, t);
     const float ir = rcp(r);
-    const V3 wc = (xe - xc) * ir;
+    const V3 wc = (q.xe - xc) * ir;
     const float r_in = P.box ? fminf(r, box_exit(P.bx, xc, wc)) : r;
-    const float mu_c = dot(s.w, wc);
+    mu_c = dot(q.w, wc);
+    t_out = t;
+    r_in_out = r_in;
     const float f = hg_pdf(mu_c, m.g);
-    const float scale = s.beta * s.em_scale * f * ir * rcp(den);
-    float c;
+    const float scale = q.scale * f * ir * rcp(den);
     if (texp) {
         // e^{-sigma_t (t + r_in)} / p(S) = (mass / sigma_t) e^{-sigma_t (S_lo - (r - r_in))}
-        c = scale * m.albedo * mass * fast_exp(-m.sigma_t * (S_lo - (r - r_in)));
-    } else {
-        c = scale * m.sigma_s * W * fast_exp(-m.sigma_t * (t + r_in));
+        return scale * m.albedo * mass * fast_exp(-m.sigma_t * (q.S_lo - (r - r_in)));
     }
+    return scale * m.sigma_s * W * fast_exp(-m.sigma_t * (t + r_in));
+}
+
+// Direct connection (range + contribution); dlog (if not null) receives the
+// derivative of the log path throughput w.r.t. (sigma_s, sigma_a, g).
+__device__ float connect(const KParams &P, const PathState &s, float u4, float *dlog)
+{
+    Conn q;
+    if (!connect_range(P, s, q.S_lo, q.S_hi)) return 0.f;
+    q.x = s.x; q.w = s.w; q.xe = s.xe; q.C = s.C; q.scale = s.beta * s.em_scale; q.u = u4;
+    float mu_c, t, r_in;
+    const float c = connect_eval(P, q, mu_c, t, r_in);
     if (dlog) {
+        const Medium &m = P.med;
         const float Lm = s.L_med + t + r_in;               // in-medium length
         const float n = (float)(s.k + 1);                  // scattering vertices
         dlog[0] = n / m.sigma_s - Lm;
@@ -275,19 +309,28 @@ __device__ __forceinline__ void direction_darts(const KParams &P, PathState &s, 
 // vertex k): medium-event Bernoulli (Eq. (12)), DA-RIS or exponential
 // distance, then the early-exit test at the new vertex.  Returns false when
 // the path has ended.
-template <int OUT, class ST>
-__device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &st, float grad_w, double *gacc)
+template <int OUT, bool QUEUE, class ST>
+__device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &st, float grad_w, double *gacc,
+                                bool &push, Conn &q)
 {
     const Medium &m = P.med;
     const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
-    float dl[3];
-    const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD ? dl : nullptr);
-    if (c != 0.f) {
-        st.inc(DARTS_ST_CONNECTIONS);
-        s.acc += c;
-        if (OUT == OUT_GRAD) {
-            const double cw = (double)c * (double)grad_w;
-            gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
+    if (QUEUE) {
+        // defer the contribution to the wave's connection queue
+        push = connect_range(P, s, q.S_lo, q.S_hi);
+        if (push) {
+            q.x = s.x; q.w = s.w; q.xe = s.xe; q.C = s.C; q.scale = s.beta * s.em_scale; q.u = u01(r1.x);
+        }
+    } else {
+        float dl[3];
+        const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD ? dl : nullptr);
+        if (c != 0.f) {
+            st.inc(DARTS_ST_CONNECTIONS);
+            s.acc += c;
+            if (OUT == OUT_GRAD) {
+                const double cw = (double)c * (double)grad_w;
+                gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
+            }
         }
     }
     if (s.k == P.max_bounces - 1) { st.inc(DARTS_ST_TRUNCATED); return false; }
@@ -386,10 +429,65 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
 // atomic pair per cell when the wave's pool is drained.
 enum { LANE_NEED = 0, LANE_FRESH = 1, LANE_ACTIVE = 2, LANE_DONE = 3 };
 
-template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS>
-__global__ __launch_bounds__(kBlock) void render_kernel(KParams P)
+// Connection queue (image mode without second moments): a lane whose vertex
+// admits a connection pushes it into its wave's LDS ring of 128 entries; as
+// soon as 64 are pending, all 64 lanes evaluate one each and add it to the
+// cell accumulators, so the connection arithmetic runs with full lanes
+// instead of with the few lanes that connect in a given iteration.
+constexpr int kQueue = 128;
+constexpr int kQFields = 12;
+
+__device__ __forceinline__ void compensated_lds_add(float *hi, float *lo, int i, float v)
+{
+    const float old = atomicAdd(&hi[i], v);
+    const float e = two_sum_err(old, v, old + v);
+    if (e != 0.f) atomicAdd(&lo[i], e);
+}
+
+// Emitter index of a position (the queue stores an index, not the position).
+__device__ __forceinline__ int emitter_index(const KParams &P, V3 xe)
+{
+    int j = 0;
+    if (P.n_em == 1) return 0;
+#pragma unroll
+    for (int i = 1; i < DARTS_MAX_EMITTERS; ++i)
+        if (i < P.n_em && xe.x == P.em_pos[i][0] && xe.y == P.em_pos[i][1] && xe.z == P.em_pos[i][2]) j = i;
+    return j;
+}
+
+// Evaluate queue entries [head, head + n) (lane i takes entry head + i) and
+// add them to the cell accumulators of this wave.
+template <class ST>
+__device__ __forceinline__ void drain_queue(const KParams &P, const float *cq, uint32_t head, uint32_t n,
+                                            float *acc_hi, float *acc_lo, ST &st)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    if (lane < n) {
+        const float *e = cq + ((head + lane) & (kQueue - 1));
+        Conn q;
+        q.x = V3{e[0 * kQueue], e[1 * kQueue], e[2 * kQueue]};
+        q.w = V3{e[3 * kQueue], e[4 * kQueue], e[5 * kQueue]};
+        q.C = e[6 * kQueue]; q.S_lo = e[7 * kQueue]; q.S_hi = e[8 * kQueue];
+        q.scale = e[9 * kQueue]; q.u = e[10 * kQueue];
+        const int packed = __float_as_int(e[11 * kQueue]);
+        float start, sc;
+        emitter(P, packed >> 8, q.xe, start, sc);
+        float mu_c, t, r_in;
+        const float c = connect_eval(P, q, mu_c, t, r_in);
+        if (c != 0.f) {
+            st.inc(DARTS_ST_CONNECTIONS);
+            compensated_lds_add(acc_hi, acc_lo, packed & 63, c);
+        }
+    }
+}
+
+template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, bool QUEUE>
+__global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_kernel(KParams P)
 {
     __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
+    __shared__ float cq_mem[QUEUE ? (kBlock / 64) * kQFields * kQueue : 1];
+    float *cq = cq_mem + (QUEUE ? (threadIdx.x >> 6) * kQFields * kQueue : 0);
+    uint32_t q_head = 0, q_count = 0;   // wave-uniform
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -404,7 +502,8 @@ __global__ __launch_bounds__(kBlock) void render_kernel(KParams P)
     acc_lo[threadIdx.x] = 0.f;
     acc_m2[threadIdx.x] = 0.f;
 
-    Stats<STATS> st;
+    using ST_T = Stats<STATS>;
+    ST_T st;
 #pragma unroll
     for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     PathState s;
@@ -449,6 +548,8 @@ __global__ __launch_bounds__(kBlock) void render_kernel(KParams P)
             next += (uint64_t)__popcll(need);
         }
         if (__ballot(state != LANE_DONE) == 0) break;
+        bool push = false;
+        Conn qc;
         if (state == LANE_FRESH || state == LANE_ACTIVE) {
             const bool fresh = state == LANE_FRESH;
             const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), fresh ? 0u : (uint32_t)s.k, 0u, P.key0, P.key1);
@@ -464,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void render_kernel(KParams P)
             }
             if (alive) {
                 if (MODE == 1) alive = fly_vanilla(P, p, pixel, s, st);
-                else alive = connect_and_fly<OUT>(P, p, s, st, grad_w, gacc);
+                else alive = connect_and_fly<OUT, QUEUE>(P, p, s, st, grad_w, gacc, push, qc);
             }
             if (alive) {
                 state = LANE_ACTIVE;
@@ -474,15 +575,39 @@ __global__ __launch_bounds__(kBlock) void render_kernel(KParams P)
                 if (MODE == 0) {
                     if (OUT == OUT_PATHS) {
                         P.path_out[p - P.path_offset] = s.acc;
-                    } else if (OUT == OUT_IMAGE && s.acc != 0.f) {
-                        const float old = atomicAdd(&acc_hi[wbase + slot], s.acc);
-                        const float e = two_sum_err(old, s.acc, old + s.acc);
-                        if (e != 0.f) atomicAdd(&acc_lo[wbase + slot], e);
+                    } else if (OUT == OUT_IMAGE && !QUEUE && s.acc != 0.f) {
+                        compensated_lds_add(acc_hi + wbase, acc_lo + wbase, slot, s.acc);
                         if (P.m2) atomicAdd(&acc_m2[wbase + slot], s.acc * s.acc);
                     }
                 }
             }
         }
+        if (QUEUE) {
+            const uint64_t pm = __ballot(push);
+            if (pm) {
+                if (push) {
+                    const uint32_t pos = (q_head + q_count + (uint32_t)__popcll(pm & lanes_below)) & (kQueue - 1);
+                    float *e = cq + pos;
+                    e[0 * kQueue] = qc.x.x; e[1 * kQueue] = qc.x.y; e[2 * kQueue] = qc.x.z;
+                    e[3 * kQueue] = qc.w.x; e[4 * kQueue] = qc.w.y; e[5 * kQueue] = qc.w.z;
+                    e[6 * kQueue] = qc.C; e[7 * kQueue] = qc.S_lo; e[8 * kQueue] = qc.S_hi;
+                    e[9 * kQueue] = qc.scale; e[10 * kQueue] = qc.u;
+                    e[11 * kQueue] = __int_as_float(slot | (emitter_index(P, qc.xe) << 8));
+                }
+                q_count += (uint32_t)__popcll(pm);
+            }
+            if (q_count >= 64) {
+                __builtin_amdgcn_wave_barrier();
+                drain_queue<ST_T>(P, cq, q_head, 64, acc_hi + wbase, acc_lo + wbase, st);
+                q_head = (q_head + 64) & (kQueue - 1);
+                q_count -= 64;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    if (QUEUE && q_count > 0) {
+        __builtin_amdgcn_wave_barrier();
+        drain_queue<ST_T>(P, cq, q_head, q_count, acc_hi + wbase, acc_lo + wbase, st);
     }
 
     if (MODE == 0 && OUT == OUT_IMAGE && have) {
@@ -764,6 +889,7 @@ int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &
 }
 
 int64_t g_target_waves = 1 << 14;
+bool g_use_queue = false;
 
 int make_params(const darts_scene *sc, const darts_params *pr, const darts_table *table, KParams &P,
                 bool per_path_only)
@@ -873,8 +999,17 @@ int launch_render(const KParams &P, bool stats, hipStream_t stream)
 {
     const uint64_t blocks = (P.n_waves + kBlock / 64 - 1) / (kBlock / 64);
     if (blocks == 0 || P.n_paths == 0) return ok();
-    if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, stream, P);
-    else hipLaunchKernelGGL((render_kernel<MODE, OUT, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, stream, P);
+    // the queue loses the per-path sums that the second moments and the
+    // statistics counters need; those launches evaluate connections in place
+    const bool queue = MODE == 0 && OUT == OUT_IMAGE && P.m2 == nullptr && !stats && g_use_queue;
+    const dim3 grid((uint32_t)blocks), block(kBlock);
+    if (queue) {
+        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, true>), grid, block, 0, stream, P);
+        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, true>), grid, block, 0, stream, P);
+    } else {
+        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, false>), grid, block, 0, stream, P);
+        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, false>), grid, block, 0, stream, P);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "render launch failed: %s", hipGetErrorString(e));
     return ok();
@@ -985,6 +1120,14 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
     hipLaunchKernelGGL(pointwise_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, (hipStream_t)stream, Q);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "pointwise launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+// Tuning knob (not part of the stable ABI): evaluate connections through the
+// wave's LDS queue (1) or in place (0, default) in image mode without m2.
+int darts_set_connection_queue(int on)
+{
+    g_use_queue = on != 0;
     return ok();
 }
 

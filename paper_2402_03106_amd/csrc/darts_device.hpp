@@ -144,17 +144,18 @@ __device__ __forceinline__ float texp_mass(float sigma, float width)   // 1 - e^
 }
 
 // x = -log(1 - mass u) / sigma with mass = 1 - emass, emass = e^{-sigma width},
-// without cancellation: when mass u < 1/2, log1p by Kahan's rescaling
-// (log(v) y / (v - 1) with v the rounded 1 - y and v - 1 exact); otherwise
-// 1 - mass u = (1 - u) + u emass is a sum of non-negative terms with 1 - u
+// without cancellation: for y = mass u < 1/100 the series
+// y + y^2/2 + y^3/3 + y^4/4 (relative error < y^4/5); for 1/100 <= y < 1/2
+// the logarithm of the rounded 1 - y (relative error < 6e-6); otherwise
+// 1 - mass u = (1 - u) + u emass, a sum of non-negative terms with 1 - u
 // exact (u >= 1/2).  ln2_over_sigma = ln 2 / sigma (log2 hardware result).
 __device__ __forceinline__ float texp_sample(float u, float ln2_over_sigma, float mass, float emass)
 {
     const float y = mass * u;
-    const bool small = y < 0.5f;
-    const float v = small ? 1.f - y : fmaf(u, emass, 1.f - u);
+    const float v = y < 0.5f ? 1.f - y : fmaf(u, emass, 1.f - u);
     const float L = log2_hw(v);
-    const float nl = small ? (v == 1.f ? y * 1.44269504088896341f : L * y * rcp(v - 1.f)) : -L;
+    const float series = y * fmaf(y, fmaf(y, fmaf(y, 0.25f, 0.333333343f), 0.5f), 1.f) * 1.44269504088896341f;
+    const float nl = y < 0.01f ? series : -L;
     return nl * ln2_over_sigma;
 }
 
@@ -244,8 +245,11 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
                                              float epc, uint32_t row, uint32_t eps, float u_sel,
                                              float &d_out, float &factor)
 {
-    float dc[8], lp[8];
-    float lmax = -kInf;
+    // Phi_i = (4 pi D s_i)^{-3/2} exp(E_i),  E_i = -r_i^2 / (4 D s_i) - sigma_a s_i:
+    // the weights s_i^{-3/2} exp(E_i - E_max) share one rsq per candidate and
+    // cannot underflow for the candidate with the largest exponent.
+    float dc[8], q[8], E[8];
+    float emax = -kInf;
     const float two_b = 2.f * b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -254,16 +258,18 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
         const float si = R_hi - di;
         const float r2 = fmaf(di, di - two_b, C2);
         const bool valid = (si > 0.f) && (r2 < si * si);
-        const float l = valid ? da_log_phi_rel(m, r2, si) : -kInf;
+        const float rq = rsq(si);
+        const float e = -fmaf(r2 * m.inv4D, rq * rq, m.sigma_a * si);
         dc[i] = di;
-        lp[i] = l;
-        lmax = fmaxf(lmax, l);
+        q[i] = valid ? rq * rq * rq : 0.f;
+        E[i] = valid ? e : -kInf;
+        emax = fmaxf(emax, E[i]);
     }
-    if (!(lmax > -kInf)) return false;
+    if (!(emax > -kInf)) return false;
     float wv[8];
     double wsum = 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { wv[i] = fast_exp(lp[i] - lmax); wsum += (double)wv[i]; }
+    for (int i = 0; i < 8; ++i) { wv[i] = q[i] * fast_exp(E[i] - emax); wsum += (double)wv[i]; }
     const double target = (double)u_sel * wsum;
     double cum = 0.0;
     float dsel = dc[7], wsel = wv[7];

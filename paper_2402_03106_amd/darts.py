@@ -105,6 +105,7 @@ def lib() -> C.CDLL:
                                                       vp, vp, vp]
         L.darts_debug_pointwise.argtypes = [C.c_int, vp, vp, i64, C.POINTER(_Medium), C.POINTER(_Table), vp]
         L.darts_set_target_waves.argtypes = [i64]
+        L.darts_set_connection_queue.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -263,6 +264,10 @@ def debug_pointwise(fn: str, inputs: torch.Tensor, med: dict | None = None, tabl
     _check(lib().darts_debug_pointwise(PW[fn], _ptr(inputs.contiguous()), _ptr(out), inputs.shape[0], m, tb,
                                        _stream(stream)))
     return out
+
+
+def set_connection_queue(on: bool):
+    _check(lib().darts_set_connection_queue(1 if on else 0))
 
 
 def set_target_waves(n: int):
