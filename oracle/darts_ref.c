@@ -106,6 +106,12 @@ double ref_hg_sample_mu(double xi, double g)
     return mu;
 }
 
+/* d/dg of log f_HG(mu; g) = log(1 - g^2) - 1.5 log(1 + g^2 - 2 g mu) + const. */
+static double dlog_hg_dg(double mu, double g)
+{
+    return -2.0 * g / (1.0 - g * g) + 3.0 * (mu - g) / (1.0 + g * g - 2.0 * g * mu);
+}
+
 /* Orthonormal basis (b1, b2) completing the unit vector n (Duff et al. 2017,
  * "Building an orthonormal basis, revisited", branchless form). */
 void ref_onb(const double n[3], double b1[3], double b2[3])
@@ -530,8 +536,9 @@ typedef struct {
 /* Generalised shadow connection through a control vertex on the current
  * ray (Section V-B, case I; Eq. (21)-(22)).  Returns the contribution. */
 static double connect_elliptical(const ref_scene *sc, const ref_params *pr, const path_state *ps,
-                                 double dm, double u4)
+                                 double dm, double u4, double *t_out, double *rin_out, double *mu_c_out)
 {
+    *t_out = 0.0; *rin_out = 0.0; *mu_c_out = 0.0;
     const ref_medium *m = &sc->medium;
     double st = m->sigma_s + m->sigma_a;
     double de[3];
@@ -567,15 +574,23 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
     double r_in = fmin(r, ref_box_exit(&sc->geom, xc, wc));
     double Ie = ps->em->power / (4.0 * PI);
     double trans = exp(-st * t) * (pr->mutation == REF_MUT_NO_EMITTER_TRANS ? 1.0 : exp(-st * r_in));
+    *t_out = t; *rin_out = r_in; *mu_c_out = dot3(ps->w, wc);
     return ps->beta * ps->J * m->sigma_s * ref_hg_pdf(dot3(ps->w, wc), m->g) * trans * Ie / (r * r * pt);
 }
 
 /* DARTS family (DARTS, uniform-S baseline and the ablation arms): one path,
  * following the recursive residual-time estimator (Eq. (6)-(7)): at every
  * vertex a control-vertex connection, then a free flight. */
+/* When grad is not NULL, grad[0..2] receives the sum over the path's
+ * connections of contribution x d log f / d(sigma_s, sigma_a, g), f the
+ * throughput of the connected path (sigma_s per scattering vertex,
+ * exp(-sigma_t x in-medium length), one phase function per scattering
+ * vertex): the detached-sampling derivative of the estimate. */
 static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_table_dims *dm_t,
-                          const float *cdf, uint64_t p, int64_t *cell, ref_stats *S)
+                          const float *cdf, uint64_t p, int64_t *cell, ref_stats *S, double *grad)
 {
+    double L_med = 0.0, dlg = 0.0;   /* in-medium walk length; sum of dlog f_HG/dg */
+    if (grad) { grad[0] = grad[1] = grad[2] = 0.0; }
     const ref_medium *m = &sc->medium;
     double st = m->sigma_s + m->sigma_a;
     path_state ps;
@@ -601,14 +616,25 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
             ref_sample_direction(m, dm_t, cdf, pr->alpha, (pr->flags & REF_EDA_DIR) != 0,
                                  ps.x, ps.em->pos, ps.w, R_hi, u, wn, &weight, &eb, pr->mutation);
             S->st[REF_ST_EDA_BRANCH] += (uint64_t)eb;
+            dlg += dlog_hg_dg(dot3(ps.w, wn), m->g);
             for (int i = 0; i < 3; ++i) ps.w[i] = wn[i];
             ps.beta *= weight;
             dm = ref_box_exit(&sc->geom, ps.x, ps.w);
         }
         uint32_t r1[4];
         draw(pr->seed, p, (uint32_t)k, 1, r1);
-        double c = connect_elliptical(sc, pr, &ps, dm, ref_u01(r1[0]));
-        if (c != 0.0) S->st[REF_ST_CONNECTIONS]++;
+        double tc, rin, muc;
+        double c = connect_elliptical(sc, pr, &ps, dm, ref_u01(r1[0]), &tc, &rin, &muc);
+        if (c != 0.0) {
+            S->st[REF_ST_CONNECTIONS]++;
+            if (grad) {
+                double Lm = L_med + tc + rin;
+                double n_sc = pr->mutation == REF_MUT_GRAD_NO_COUNT ? 0.0 : (double)(k + 1);
+                grad[0] += c * (n_sc / m->sigma_s - Lm);
+                grad[1] += c * (-Lm);
+                grad[2] += c * (dlg + dlog_hg_dg(muc, m->g));
+            }
+        }
         acc += c;
         if (k == pr->max_bounces - 1) { S->st[REF_ST_TRUNCATED]++; break; }
         /* free flight: medium-event Bernoulli (Eq. (12)) */
@@ -629,6 +655,7 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
         }
         axpy3(ps.x, ps.w, d, ps.x);
         ps.Le += d;
+        L_med += d;
         ps.beta *= factor;
         dm = ref_box_exit(&sc->geom, ps.x, ps.w);
     }
@@ -805,7 +832,7 @@ int ref_render_paths_steps(const ref_scene *sc, const ref_params *pr,
         ref_stats S;
         memset(&S, 0, sizeof S);
         int64_t cell;
-        trace_darts(sc, pr, dims, cdf, pr->path_offset + (uint64_t)i, &cell, &S);
+        trace_darts(sc, pr, dims, cdf, pr->path_offset + (uint64_t)i, &cell, &S, NULL);
         path_steps[i] = (int32_t)(S.st[REF_ST_VERTICES] - S.st[REF_ST_EARLY_EXIT]);
     }
     (void)nt;
@@ -828,7 +855,7 @@ int ref_render_paths(const ref_scene *sc, const ref_params *pr,
         ref_stats S;
         memset(&S, 0, sizeof S);
         int64_t cell;
-        path_value[i] = trace_darts(sc, pr, dims, cdf, pr->path_offset + (uint64_t)i, &cell, &S);
+        path_value[i] = trace_darts(sc, pr, dims, cdf, pr->path_offset + (uint64_t)i, &cell, &S, NULL);
         path_cell[i] = cell;
     }
     (void)nt;
@@ -850,7 +877,7 @@ int ref_render_path_list(const ref_scene *sc, const ref_params *pr,
         ref_stats S;
         memset(&S, 0, sizeof S);
         int64_t cell;
-        path_value[i] = trace_darts(sc, pr, dims, cdf, ids[i], &cell, &S);
+        path_value[i] = trace_darts(sc, pr, dims, cdf, ids[i], &cell, &S, NULL);
     }
     (void)nt;
     return 0;
@@ -890,7 +917,7 @@ int ref_render_transient(const ref_scene *sc, const ref_params *pr,
 #pragma omp for schedule(dynamic, 256)
 #endif
             for (int64_t i = 0; i < n; ++i)
-                pv[i] = trace_darts(sc, pr, dims, cdf, pr->path_offset + (uint64_t)i, &pc[i], &ts[tid]);
+                pv[i] = trace_darts(sc, pr, dims, cdf, pr->path_offset + (uint64_t)i, &pc[i], &ts[tid], NULL);
         }
         for (int64_t i = 0; i < n; ++i) {
             image[pc[i]] += pv[i];
@@ -951,11 +978,35 @@ int ref_render_transient(const ref_scene *sc, const ref_params *pr,
     return 0;
 }
 
-/* Detached-sampling gradient: see ref_render_gradient below. */
+/* Detached-sampling gradient of L = sum_c grad_image[c] I[c] (I the raw
+ * per-cell sums) with respect to (sigma_s, sigma_a, g), path by path, then a
+ * serial sum in path order. */
 int ref_render_gradient(const ref_scene *sc, const ref_params *pr,
                         const ref_table_dims *dims, const float *cdf,
                         const double *grad_image, double *grad_out, int n_threads)
 {
-    (void)sc; (void)pr; (void)dims; (void)cdf; (void)grad_image; (void)grad_out; (void)n_threads;
-    return -3;
+    if (check_args(sc, pr)) return -1;
+    if (pr->flags & (REF_DIRECT_REUSE | REF_FORWARD)) return -1;
+    if ((pr->flags & REF_EDA_DIR) && (!cdf || !dims)) return -1;
+    int nt = nthreads_eff(n_threads);
+    int64_t n = (int64_t)pr->n_paths;
+    double *pg = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!pg) return -2;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        ref_stats S;
+        memset(&S, 0, sizeof S);
+        int64_t cell;
+        double g[3];
+        trace_darts(sc, pr, dims, cdf, pr->path_offset + (uint64_t)i, &cell, &S, g);
+        for (int a = 0; a < 3; ++a) pg[3 * i + a] = grad_image[cell] * g[a];
+    }
+    grad_out[0] = grad_out[1] = grad_out[2] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) grad_out[a] += pg[3 * i + a];
+    free(pg);
+    (void)nt;
+    return 0;
 }

@@ -86,6 +86,7 @@ typedef struct {
 #define REF_MUT_EDA_PDF_UNSCALED  3 /* EDA pdf missing the solid-angle scale  */
 #define REF_MUT_NO_EMITTER_TRANS  4 /* drop transmittance control->emitter    */
 #define REF_MUT_HG_SAMPLE_FLIP    5 /* HG sample mirrored (cos -> -cos)       */
+#define REF_MUT_GRAD_NO_COUNT     6 /* gradient: drop n / sigma_s              */
 
 /* Statistics, uint64 counters. */
 enum {

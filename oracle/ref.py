@@ -30,7 +30,7 @@ MODES = {
     "forward": FORWARD,
 }
 MUT = {"none": 0, "printed_jacobian": 1, "ris_no_mean": 2, "eda_pdf_unscaled": 3,
-       "no_emitter_trans": 4, "hg_sample_flip": 5}
+       "no_emitter_trans": 4, "hg_sample_flip": 5, "grad_no_count": 6}
 STATS = ["paths", "vertices", "connections", "early_exit", "medium_exit", "ris_all_invalid",
          "eda_branch", "truncated", "zero_paths", "ris_invalid_cands"]
 
@@ -304,9 +304,10 @@ def render_path_list(sc: dict, p: dict, mode: str, ids, table=None, dims_: dict 
     return val
 
 
-def render_gradient(sc: dict, p: dict, mode: str, grad_image, table=None, dims_=None, n_threads=0):
+def render_gradient(sc: dict, p: dict, mode: str, grad_image, table=None, dims_=None, n_threads=0,
+                    mutation: str = "none"):
     holder = _SceneHolder(sc)
-    pr = params(p, mode)
+    pr = params(p, mode, mutation)
     gi = np.ascontiguousarray(grad_image, np.float64)
     out = np.zeros(3, np.float64)
     cdf = None if table is None else np.ascontiguousarray(table, np.float32)

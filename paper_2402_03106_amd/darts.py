@@ -292,3 +292,41 @@ def paths_per_cell(sc: dict, p: dict, mode) -> torch.Tensor:
     if (MODES[mode] if isinstance(mode, str) else int(mode)) & DIRECT_REUSE:
         cnt = cnt.sum(0, keepdim=True).expand(shape).clone()
     return cnt
+
+
+# --------------------------------------------------------------------------
+# Differentiable rendering
+# --------------------------------------------------------------------------
+class TransientRender(torch.autograd.Function):
+    """Per-cell estimates I(theta) (raw sums / paths per cell) of a render as a
+    differentiable function of theta = (sigma_s, sigma_a, g).  The backward
+    pass replays the same paths (same ids, seed and tables) through
+    darts_render_transient_backward; nothing is stored between the passes
+    except the table and the per-cell path counts."""
+
+    @staticmethod
+    def forward(ctx, theta, scene, params_, mode, dims_):
+        vals = [float(v) for v in theta.detach().cpu().tolist()]
+        med = {"sigma_s": vals[0], "sigma_a": vals[1], "g": vals[2]}
+        sc = dict(scene, medium=med)
+        flags = MODES[mode] if isinstance(mode, str) else int(mode)
+        table = build_da_tables(med, dims_) if flags & EDA_DIR else None
+        hi, lo, _, _ = render_transient(sc, params_, mode, table)
+        n = paths_per_cell(sc, params_, mode).to(hi.device)
+        img = (hi.double() + lo.double()) / n.clamp(min=1)
+        ctx.sc, ctx.params, ctx.mode, ctx.table = sc, params_, mode, table
+        ctx.save_for_backward(n, theta)
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_img):
+        n, theta = ctx.saved_tensors
+        grad_raw = (grad_img / n.clamp(min=1)).float().contiguous()
+        g = render_transient_backward(ctx.sc, ctx.params, ctx.mode, ctx.table, grad_raw)
+        return g.to(device=theta.device, dtype=theta.dtype), None, None, None, None
+
+
+def transient_image(theta: torch.Tensor, scene: dict, params_: dict, mode, dims_: dict) -> torch.Tensor:
+    """Differentiable per-cell image (float64, [n_bins, H, W]) of the medium
+    theta = tensor([sigma_s, sigma_a, g])."""
+    return TransientRender.apply(theta, scene, params_, mode, dims_)

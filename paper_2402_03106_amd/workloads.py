@@ -94,6 +94,23 @@ def box_point() -> dict:
     }
 
 
+def box_hg_grad() -> dict:
+    """Differentiable rendering workload: the box geometry of ``box_hg`` at
+    sigma_s = 8, sigma_a = 0.2, g = 0.5 with a 128x128 sensor and 512 bins
+    over [0, 40); an L2 loss against a target rendered at sigma_s = 10,
+    sigma_a = 0.1, g = 0.6; gradients from 2^22 replayed paths."""
+    w = box_hg()
+    w["name"] = "box_hg_grad"
+    w["scene"]["medium"] = {"sigma_s": 8.0, "sigma_a": 0.2, "g": 0.5}
+    w["scene"]["sensor"]["width"] = 128
+    w["scene"]["sensor"]["height"] = 128
+    w["scene"]["bins"] = {"l_lo": 0.0, "l_hi": 40.0, "n_bins": 512}
+    w["params"]["n_paths"] = 1 << 22
+    w["params"]["seed"] = 0xC4
+    w["target_medium"] = {"sigma_s": 10.0, "sigma_a": 0.1, "g": 0.6}
+    return w
+
+
 def with_(w: dict, **changes) -> dict:
     """Copy of a workload with params/scene entries replaced, e.g.
     ``with_(w, n_paths=4096, medium={"sigma_s": 2.0, ...})``."""

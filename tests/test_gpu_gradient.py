@@ -1,0 +1,107 @@
+"""Adjoint (path-replay) gradients on the GPU: against the FP64 oracle's
+gradient on the same Philox streams, against central finite differences
+with common random numbers on the differentiable workload, and through the
+torch.autograd.Function."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2402_03106_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_03106_amd import darts
+    darts.lib()
+    return darts
+
+
+@pytest.mark.parametrize("wname,mode", [("box_point", "darts"), ("box_point", "uniform"),
+                                        ("box_hg_small", "darts"), ("box_hg_small", "da_only"),
+                                        ("infinite_point", "darts")])
+def test_gradient_matches_oracle(D, oracle, wname, mode):
+    w = getattr(W, wname)()
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    gimg = np.random.default_rng(1).random(oracle.image_shape(sc))
+    table = D.build_da_tables(sc["medium"], dm)
+    g = D.render_transient_backward(sc, pr, mode, table, torch.from_numpy(gimg).float().cuda())
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    _, cdf = oracle.build_table(sc["medium"], dm)
+    go = oracle.render_gradient(sc, pr, mode, gimg.astype(np.float32).astype(np.float64), cdf, dm)
+    print(wname, mode, g, go)
+    assert np.max(np.abs(g - go)) <= 2e-3 * np.max(np.abs(go)), (g, go)
+
+
+def _render(D, w, med, seed, n_paths):
+    sc, dm = dict(w["scene"], medium=med), w["dims"]
+    pr = dict(w["params"], seed=seed, n_paths=n_paths)
+    table = D.build_da_tables(med, dm)
+    hi, lo, _, _ = D.render_transient(sc, pr, "darts", table)
+    n = D.paths_per_cell(sc, pr, "darts").cuda().clamp(min=1)   # cells without paths read 0
+    return (hi.double() + lo.double()) / n, n, sc, pr, table
+
+
+@pytest.mark.parametrize("loss", ["l2_residual", "time_weighted"])
+def test_gradient_matches_finite_differences_c4(D, loss):
+    """The differentiable workload (128x128 sensor, 512 bins, 2^22 paths).
+    l2_residual: gradient of the L2 loss against the target medium's image,
+    with the residual 2 (I - I_target) taken from an independent render (so
+    that the gradient is a linear functional of the replayed render, without
+    the variance term a shared sample would add); at this sampling density
+    the residual is mostly noise, so this checks agreement within noise.
+    time_weighted: sum_c exp(-bin/64) I_c, a functional whose gradient is well
+    resolved.  Replay gradients vs central differences (h = 3%, common random
+    numbers, tables rebuilt at each perturbed medium) over 4 seeds."""
+    w = W.box_hg_grad()
+    n_paths = w["params"]["n_paths"]
+    tmed, med = w["target_medium"], w["scene"]["medium"]
+    if loss == "l2_residual":
+        target, _, _, _, _ = _render(D, w, tmed, 0xEF, n_paths * 4)
+        img_a, _, _, _, _ = _render(D, w, med, 0xA0, n_paths * 4)
+        weight = 2 * (img_a - target)                      # dL/dI at the current medium
+    else:
+        nb = w["scene"]["bins"]["n_bins"]
+        weight = torch.exp(-torch.arange(nb, dtype=torch.float64, device="cuda") / 64.0)[:, None, None] \
+            .expand(nb, w["scene"]["sensor"]["height"], w["scene"]["sensor"]["width"]).contiguous()
+    G, F = [], []
+    for seed in range(4):
+        img, n, sc, pr, table = _render(D, w, med, seed + 1, n_paths)
+        g = D.render_transient_backward(sc, pr, "darts", table, (weight / n).float())
+        torch.cuda.synchronize()
+        G.append(g.cpu().numpy())
+        fd = []
+        for key in ["sigma_s", "sigma_a", "g"]:
+            h = 0.03 * max(abs(med[key]), 0.1)
+            ip, _, _, _, _ = _render(D, w, dict(med, **{key: med[key] + h}), seed + 1, n_paths)
+            im, _, _, _, _ = _render(D, w, dict(med, **{key: med[key] - h}), seed + 1, n_paths)
+            fd.append(((weight * (ip - im)).sum() / (2 * h)).item())
+        F.append(fd)
+    G, F = np.array(G), np.array(F)
+    se = np.hypot(G.std(0, ddof=1), F.std(0, ddof=1)) / math.sqrt(len(G))
+    z = (G.mean(0) - F.mean(0)) / se
+    print(loss, "replay", G.mean(0), "+-", G.std(0, ddof=1) / 2, "fd", F.mean(0), "+-", F.std(0, ddof=1) / 2, "z", z)
+    assert np.max(np.abs(z)) < 4.0, (G.mean(0), F.mean(0), z)
+    if loss == "time_weighted":   # resolved: each component at least 5 standard errors from zero
+        assert np.all(np.abs(G.mean(0)) > 5 * G.std(0, ddof=1) / 2)
+
+
+def test_autograd_function(D):
+    w = W.box_hg_small()
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    theta = torch.tensor([4.75, 0.25, 0.7], dtype=torch.float64, requires_grad=True)
+    img = D.transient_image(theta, sc, pr, "darts", dm)
+    target = torch.zeros_like(img)
+    loss = ((img - target) ** 2).sum()
+    loss.backward()
+    n = D.paths_per_cell(sc, pr, "darts").cuda()
+    table = D.build_da_tables(sc["medium"], dm)
+    g = D.render_transient_backward(sc, pr, "darts", table, (2 * img.detach() / n).float())
+    torch.cuda.synchronize()
+    assert torch.allclose(theta.grad, g.cpu(), rtol=1e-6, atol=0)

@@ -583,3 +583,53 @@ def test_planted_mistakes_are_caught(oracle):
         est = _direction_moments(oracle, medb, w["dims"], cdf, x, xe, list(wprev), S=Cd * 1.6,
                                  mutation=mut, n=20000)
         assert np.max(np.abs(est - exact)) > 0.05, (mut, est, exact)
+
+
+# --------------------------------------------------------------------------
+# Gradient of a transient loss (detached sampling, path replay)
+# --------------------------------------------------------------------------
+def _gradient_vs_fd(oracle, mode, mutation="none", seeds=6, n=1 << 19, hrel=0.03):
+    w = W.box_point()
+    sc, dm = w["scene"], w["dims"]
+    med = sc["medium"]
+    gimg = np.random.default_rng(0).random(oracle.image_shape(sc))
+    tabs = {}
+
+    def table(m):
+        k = tuple(sorted(m.items()))
+        if k not in tabs:
+            tabs[k] = oracle.build_table(m, dm)[1]
+        return tabs[k]
+
+    G, F = [], []
+    for seed in range(seeds):
+        p = dict(w["params"], n_paths=n, seed=100 + seed)
+        G.append(oracle.render_gradient(sc, p, mode, gimg, table(med), dm, mutation=mutation))
+        fd = []
+        for key in ["sigma_s", "sigma_a", "g"]:
+            h = hrel * max(abs(med[key]), 0.1)
+            val = []
+            for sgn in (1, -1):
+                m2 = dict(med)
+                m2[key] += sgn * h
+                img, _, _ = oracle.render(dict(sc, medium=m2), p, mode, table(m2), dm)
+                val.append((gimg * img).sum())
+            fd.append((val[0] - val[1]) / (2 * h))
+        F.append(fd)
+    G, F = np.array(G), np.array(F)
+    z = (G.mean(0) - F.mean(0)) / np.hypot(G.std(0, ddof=1), F.std(0, ddof=1)) * math.sqrt(seeds)
+    return z, G.mean(0), F.mean(0)
+
+
+@pytest.mark.parametrize("mode", ["darts", "uniform"])
+def test_gradient_matches_finite_differences(oracle, mode):
+    """Path-replay gradient of L = sum_c w_c I_c with respect to (sigma_s,
+    sigma_a, g) against central differences (h = 3%, common random numbers,
+    tables rebuilt for each perturbed medium), averaged over seeds."""
+    z, g, fd = _gradient_vs_fd(oracle, mode)
+    assert np.max(np.abs(z)) < 4.0, (z, g, fd)
+
+
+def test_gradient_planted_mistake_is_caught(oracle):
+    z, g, fd = _gradient_vs_fd(oracle, "darts", mutation="grad_no_count", seeds=4)
+    assert abs(z[0]) > 6.0, (z, g, fd)
