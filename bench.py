@@ -83,14 +83,40 @@ def parse():
     ap.add_argument("--no-mse", action="store_true", help="skip the time-to-MSE measurement")
     ap.add_argument("--no-uniform", action="store_true", help="skip the uniform-baseline throughput")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after timing, copy this many bytes device-to-device once (a kernel of known "
+                         "traffic that calibrates the HBM byte counters of a profiler run)")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ["paper_2402_03106_amd/csrc/darts.hip", "paper_2402_03106_amd/csrc/darts_device.hpp"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per render launch from the committed counter profile, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "render_kernel_box_hg_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(multi-GPU sharding is a design note, not part of the build)"}))
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -171,7 +197,7 @@ def main():
         "mean_steps_per_path": n_steps / n,
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
             "flops_per_launch": flops, "flops_per_vertex_step": flops / n_steps,
         },
         "stats": stats,
@@ -188,8 +214,19 @@ def main():
         print(f"[bench] uniform {out['uniform']['paths_per_s']:.4g} paths/s", file=sys.stderr, flush=True)
 
     if not a.no_mse:
-        out["time_to_mse"] = time_to_mse(darts, torch, np, sc, pr, dm, out)
+        wall_v, _ = timed("vanilla", 2, 1)
+        thr = {"darts": value, "uniform": out.get("uniform", {}).get("paths_per_s"), "vanilla": 2 * n / wall_v}
+        out["time_to_mse"] = {
+            "box_hg": time_to_mse(darts, torch, np, w, thr, 1 << 26),
+            "infinite_point": time_to_mse(darts, torch, np, W.infinite_point(), None, 1 << 24),
+        }
         print(f"[bench] time to MSE {out['time_to_mse']}", file=sys.stderr, flush=True)
+    if a.copy_bytes > 0:
+        src = torch.empty(a.copy_bytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
 
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
@@ -198,45 +235,46 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_to_mse(darts, torch, np, sc, pr, dm, out, target=1e-4):
-    """MSE(N) = mean over cells of Var(cell estimate) / q95^2; both
-    estimators are unbiased so MSE is the variance, estimated from per-path
-    second moments of an N0-path render and scaled as 1/N.  The wall time to
-    reach the target is N*/throughput plus one table build."""
-    n0 = 1 << 26
+def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4):
+    """MSE(N) = mean over cells of Var(cell estimate) / q95^2 (q95: 0.95
+    quantile of the DARTS image, the paper's normalisation before MSE).  All
+    modes are unbiased, so MSE is their variance; it is estimated from per-path
+    second moments of an n0-path render (seed 0xEF, ids disjoint from the
+    timed frames) and scales as 1/N.  Wall time to the target = N* / measured
+    paths/s + one table build, for the workload's throughput `thr` (None: the
+    MSE-per-path products only)."""
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
     p0 = dict(pr, n_paths=n0, path_offset=1 << 40, seed=0xEF)
-    res = {}
-    means = {}
-    for mode in ["darts", "uniform"]:
-        table = darts.build_da_tables(sc["medium"], dm)
+    table = darts.build_da_tables(sc["medium"], dm)
+    var, means = {}, {}
+    for mode in ["darts", "uniform", "vanilla"]:
         hi, lo, m2, _ = darts.render_transient(sc, p0, mode, table, want_m2=True)
         torch.cuda.synchronize()
         n = darts.paths_per_cell(sc, p0, mode).numpy()
         s = (hi.double() + lo.double()).cpu().numpy()
         mm = m2.double().cpu().numpy()
-        mean = s / n
-        var_path = np.maximum(mm / n - mean ** 2, 0) * n / np.maximum(n - 1, 1)
+        mean = s / np.maximum(n, 1)
         means[mode] = mean
-        res[mode] = var_path
+        var[mode] = (np.maximum(mm / np.maximum(n, 1) - mean ** 2, 0), n / n0)   # per-path variance, paths per cell per path
     q95 = float(np.quantile(means["darts"], 0.95))
-    ncell = means["darts"].size
     t0 = time.perf_counter()
     darts.build_da_tables(sc["medium"], dm)
     torch.cuda.synchronize()
     t_table = time.perf_counter() - t0
-    rep = {"target": target, "normalisation": "0.95 quantile of the DARTS image", "q95": q95,
-           "method": "per-cell variance from a 2^26-path render (seed 0xEF), MSE ~ 1/N, "
-                     "wall time = N*/measured paths/s + table build"}
-    thr = {"darts": out["value"], "uniform": out.get("uniform", {}).get("paths_per_s")}
-    for mode in ["darts", "uniform"]:
-        # MSE with N paths in total (N/ncell per cell)
-        mse_per_path_per_cell = float(res[mode].mean()) / q95 ** 2
-        n_star = mse_per_path_per_cell * ncell / target
-        rep[mode] = {"paths_needed": n_star, "mse_at_2^28": mse_per_path_per_cell * ncell / (1 << 28)}
-        if thr[mode]:
-            rep[mode]["seconds"] = n_star / thr[mode] + t_table
-    if "seconds" in rep["darts"] and "seconds" in rep["uniform"]:
-        rep["uniform_over_darts"] = rep["uniform"]["seconds"] / rep["darts"]["seconds"]
+    rep = {"target": target, "q95": q95, "paths_for_variance": n0,
+           "note": "vanilla reuses each path for every bin of its pixel (temporal reuse); DARTS and uniform "
+                   "dedicate each path to one bin"}
+    for mode, (v, frac) in var.items():
+        mse_times_n = float(np.mean(v / np.maximum(frac, 1e-300))) / q95 ** 2   # MSE x total paths
+        r = {"mse_times_paths": mse_times_n, "paths_needed": mse_times_n / target}
+        if thr and thr.get(mode):
+            r["paths_per_s"] = thr[mode]
+            r["seconds"] = r["paths_needed"] / thr[mode] + t_table
+        rep[mode] = r
+    for mode in ["uniform", "vanilla"]:
+        if "seconds" in rep[mode] and "seconds" in rep["darts"]:
+            rep[f"{mode}_over_darts_time"] = rep[mode]["seconds"] / rep["darts"]["seconds"]
+        rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
     return rep
 
 

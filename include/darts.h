@@ -40,7 +40,7 @@ extern "C" {
 #define DARTS_OK                  0
 #define DARTS_ERR_INVALID_ARG    -1  /* bad sizes, parameters or null pointers  */
 #define DARTS_ERR_DEVICE         -2  /* a HIP runtime call failed               */
-#define DARTS_ERR_UNSUPPORTED    -3  /* valid request this build does not serve */
+#define DARTS_ERR_UNSUPPORTED    -3  /* valid request this library does not serve */
 #define DARTS_ERR_TABLE_MISMATCH -4  /* table built for another medium / dims   */
 
 #define DARTS_MAX_EMITTERS 8

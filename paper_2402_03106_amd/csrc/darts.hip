@@ -911,7 +911,7 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
         for (int a = 0; a < 3; ++a)
             if (!(sc->geom.hi[a] > sc->geom.lo[a])) return fail(DARTS_ERR_INVALID_ARG, "box needs hi > lo");
     if (pr->max_bounces < 1) return fail(DARTS_ERR_INVALID_ARG, "max_bounces must be >= 1");
-    if (pr->n_ris != 8) return fail(DARTS_ERR_UNSUPPORTED, "this build implements n_ris = 8 (the paper's choice)");
+    if (pr->n_ris != 8) return fail(DARTS_ERR_UNSUPPORTED, "only n_ris = 8 (the paper's candidate count) is implemented");
     if (!(pr->alpha >= 0.f)) return fail(DARTS_ERR_INVALID_ARG, "alpha must be >= 0");
     const unsigned f = pr->flags;
     if (f & ~(DARTS_RIS_DIST | DARTS_EDA_DIR | DARTS_ELL_TEXP | DARTS_ELL_UNIFORM | DARTS_DIRECT_REUSE))

@@ -44,10 +44,12 @@ def test_library_exports_every_declared_symbol(D):
 def test_library_has_no_torch_dependency(D):
     """The boundary is plain C: the shared library must not link torch."""
     maps = open(f"/proc/{os.getpid()}/maps").read()
-    assert D.LIB_PATH in maps
+    assert D.LIB_PATH in maps, [l for l in maps.splitlines() if "darts" in l]
     import subprocess
     out = subprocess.run(["ldd", D.LIB_PATH], capture_output=True, text=True).stdout
-    assert "torch" not in out and "c10" not in out
+    # library names only: the load addresses ldd prints are random hex
+    names = [ln.split()[0] for ln in out.splitlines() if ln.strip()]
+    assert not [n for n in names if "torch" in n or n.startswith("libc10")], names
 
 
 def test_table_bytes(D):
