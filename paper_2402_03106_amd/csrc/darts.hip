@@ -147,7 +147,7 @@ __device__ __forceinline__ float dlog_hg_dg(float mu, float g)
 // vertex 0).  Returns false if the path cannot contribute (the camera ray
 // misses the medium, or nothing is reachable inside the gate).
 template <class ST>
-__device__ bool setup_path(const KParams &P, U4 r, int64_t bin, int px, int py, PathState &s, ST &st,
+__device__ bool setup_path(const KParams &P, U4 r, int bin, int px, int py, PathState &s, ST &st,
                            bool vanilla)
 {
     const float u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z);
@@ -502,6 +502,25 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
     acc_lo[threadIdx.x] = 0.f;
     acc_m2[threadIdx.x] = 0.f;
 
+    // Lane l describes tile cell c0 + l (time bin, pixel, repetition bounds);
+    // a lane starting a path of cell c0 + sl reads lane sl's description with
+    // a cross-lane permute instead of dividing 64-bit indices per path.
+    int my_bin = 0, my_px = 0, my_py = 0;
+    int my_flags = 0;   // bit 0: the cell exists, bit 1: cell < r0, bit 2: cell < r1
+    float my_gw = 0.f;
+    {
+        const int64_t my_cell = c0 + lane;
+        if (have && my_cell < P.ncells) {
+            const int64_t b = my_cell / P.npix;
+            const int64_t pix = my_cell - b * P.npix;
+            my_bin = (int)b;
+            my_py = (int)(pix / P.width);
+            my_px = (int)(pix - (int64_t)my_py * P.width);
+            my_flags = 1 | ((uint64_t)my_cell < P.r0 ? 2 : 0) | ((uint64_t)my_cell < P.r1 ? 4 : 0);
+            if (OUT == OUT_GRAD) my_gw = P.grad_image[my_cell];
+        }
+    }
+
     using ST_T = Stats<STATS>;
     ST_T st;
 #pragma unroll
@@ -511,7 +530,8 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
     int state = have ? LANE_NEED : LANE_DONE;
     uint64_t p = 0;
     int slot = 0;
-    int64_t bin = 0, pixel = 0;
+    int bin = 0, px = 0, py = 0;
+    int64_t pixel = 0;
     float grad_w = 0.f;
     double gacc[3] = {0.0, 0.0, 0.0};
 
@@ -519,28 +539,27 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
         const bool want = state == LANE_NEED;
         const uint64_t need = __ballot(want);
         if (need) {
+            // whole wave active here: the permutes read every lane's description
+            const uint64_t j = next + (uint64_t)__popcll(need & lanes_below);
+            const int sl = (int)(j & 63);
+            const int fl = __shfl(my_flags, sl);
+            const int c_bin = __shfl(my_bin, sl), c_px = __shfl(my_px, sl), c_py = __shfl(my_py, sl);
+            const float c_gw = OUT == OUT_GRAD ? __shfl(my_gw, sl) : 0.f;
             if (want) {
-                const uint64_t j = next + (uint64_t)__popcll(need & lanes_below);
                 if (j >= j_end) {
                     state = LANE_DONE;
                 } else {
-                    const int sl = (int)(j & 63);
                     const uint64_t rep = j >> 6;
-                    const int64_t cell = c0 + sl;
-                    const uint64_t m = P.q0 + ((uint64_t)cell < P.r0 ? 1 : 0) + rep;
-                    const uint64_t m_hi = P.q1 + ((uint64_t)cell < P.r1 ? 1 : 0);
-                    if (cell < P.ncells && m < m_hi) {
-                        p = (uint64_t)cell + m * (uint64_t)P.ncells;
+                    const uint64_t m = P.q0 + (uint64_t)((fl >> 1) & 1) + rep;
+                    const uint64_t m_hi = P.q1 + (uint64_t)((fl >> 2) & 1);
+                    if ((fl & 1) && m < m_hi) {
+                        p = (uint64_t)(c0 + sl) + m * (uint64_t)P.ncells;
                         slot = sl;
-                        if (P.ncells < 0x7FFFFFFF) {
-                            const uint32_t c32 = (uint32_t)cell, np = (uint32_t)P.npix;
-                            bin = c32 / np;
-                            pixel = c32 - (uint32_t)bin * np;
-                        } else {
-                            bin = cell / P.npix;
-                            pixel = cell - bin * P.npix;
-                        }
-                        if (OUT == OUT_GRAD) grad_w = P.grad_image[cell];
+                        bin = c_bin;
+                        px = c_px;
+                        py = c_py;
+                        pixel = (int64_t)c_py * P.width + c_px;
+                        if (OUT == OUT_GRAD) grad_w = c_gw;
                         state = LANE_FRESH;
                     }   // else: an empty slot of a ragged range; pull again next iteration
                 }
@@ -555,7 +574,6 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
             const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), fresh ? 0u : (uint32_t)s.k, 0u, P.key0, P.key1);
             bool alive = true;
             if (fresh) {
-                const int px = (int)(pixel % P.width), py = (int)(pixel / P.width);
                 alive = setup_path(P, r0, bin, px, py, s, st, MODE == 1);
                 if (!alive) s.acc = 0.f;
             } else if (MODE == 1) {
