@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mse", action="store_true", help="skip the time-to-MSE measurement")
     ap.add_argument("--no-uniform", action="store_true", help="skip the uniform-baseline throughput")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched many-media launch")
+    ap.add_argument("--batched-reps", type=int, default=5, help="timed graph launches of the batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device once (a kernel of known "
@@ -221,6 +223,9 @@ def main():
             "infinite_point": time_to_mse(darts, torch, np, W.infinite_point(), None, 1 << 24),
         }
         print(f"[bench] time to MSE {out['time_to_mse']}", file=sys.stderr, flush=True)
+    if not a.no_batched:
+        out["batched"] = batched_bench(darts, torch, W, a.batched_reps)
+        print(f"[bench] batched {out['batched']}", file=sys.stderr, flush=True)
     if a.copy_bytes > 0:
         src = torch.empty(a.copy_bytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -235,38 +240,54 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4):
+def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4, k=16):
     """MSE(N) = mean over cells of Var(cell estimate) / q95^2 (q95: 0.95
     quantile of the DARTS image, the paper's normalisation before MSE).  All
-    modes are unbiased, so MSE is their variance; it is estimated from per-path
-    second moments of an n0-path render (seed 0xEF, ids disjoint from the
-    timed frames) and scales as 1/N.  Wall time to the target = N* / measured
-    paths/s + one table build, for the workload's throughput `thr` (None: the
-    MSE-per-path products only)."""
+    modes are unbiased, so MSE is their variance, which scales as 1/N.  It is
+    estimated from k independent batches of n0/k paths (seed 0xEF, ids disjoint
+    from the timed frames): the per-cell sample variance of the batch images
+    times n0/k is the variance of one path's worth of estimate.  For DARTS and
+    uniform, where a path feeds one cell, the per-path second moments of one
+    n0-path render give a second estimate (`mse_times_paths_m2`); vanilla
+    feeds one path into many bins, so only the batch estimate applies.  Wall
+    time to the target = N* / measured paths/s + one table build, for the
+    workload's throughput `thr` (None: the MSE-per-path products only).  The
+    times are extrapolated from the variance, not measured to convergence."""
     sc, pr, dm = w["scene"], w["params"], w["dims"]
-    p0 = dict(pr, n_paths=n0, path_offset=1 << 40, seed=0xEF)
+    nb = n0 // k
     table = darts.build_da_tables(sc["medium"], dm)
-    var, means = {}, {}
+    var, m2v, means = {}, {}, {}
     for mode in ["darts", "uniform", "vanilla"]:
-        hi, lo, m2, _ = darts.render_transient(sc, p0, mode, table, want_m2=True)
-        torch.cuda.synchronize()
-        n = darts.paths_per_cell(sc, p0, mode).numpy()
-        s = (hi.double() + lo.double()).cpu().numpy()
-        mm = m2.double().cpu().numpy()
-        mean = s / np.maximum(n, 1)
-        means[mode] = mean
-        var[mode] = (np.maximum(mm / np.maximum(n, 1) - mean ** 2, 0), n / n0)   # per-path variance, paths per cell per path
+        imgs = []
+        for i in range(k):
+            pb = dict(pr, n_paths=nb, path_offset=(1 << 40) + i * nb, seed=0xEF)
+            hi, lo, _, _ = darts.render_transient(sc, pb, mode, table)
+            n = darts.paths_per_cell(sc, pb, mode).numpy()
+            imgs.append((hi.double() + lo.double()).cpu().numpy() / np.maximum(n, 1))
+        imgs = np.stack(imgs)
+        means[mode] = imgs.mean(0)
+        var[mode] = imgs.var(0, ddof=1) * nb          # variance of one batch image x paths per batch
+        if mode != "vanilla":
+            p0 = dict(pr, n_paths=n0, path_offset=1 << 40, seed=0xEF)
+            hi, lo, m2, _ = darts.render_transient(sc, p0, mode, table, want_m2=True)
+            n = darts.paths_per_cell(sc, p0, mode).numpy()
+            mean = (hi.double() + lo.double()).cpu().numpy() / np.maximum(n, 1)
+            pv = np.maximum(m2.double().cpu().numpy() / np.maximum(n, 1) - mean ** 2, 0)
+            m2v[mode] = pv / np.maximum(n / n0, 1e-300)  # per-path variance / (paths per cell per path)
+    torch.cuda.synchronize()
     q95 = float(np.quantile(means["darts"], 0.95))
     t0 = time.perf_counter()
     darts.build_da_tables(sc["medium"], dm)
     torch.cuda.synchronize()
     t_table = time.perf_counter() - t0
-    rep = {"target": target, "q95": q95, "paths_for_variance": n0,
-           "note": "vanilla reuses each path for every bin of its pixel (temporal reuse); DARTS and uniform "
-                   "dedicate each path to one bin"}
-    for mode, (v, frac) in var.items():
-        mse_times_n = float(np.mean(v / np.maximum(frac, 1e-300))) / q95 ** 2   # MSE x total paths
+    rep = {"target": target, "q95": q95, "paths_for_variance": n0, "batches": k,
+           "note": "extrapolated from measured variance and throughput; vanilla reuses each path for "
+                   "every bin of its pixel (temporal reuse), DARTS and uniform dedicate each path to one bin"}
+    for mode in var:
+        mse_times_n = float(np.mean(var[mode])) / q95 ** 2   # MSE x total paths
         r = {"mse_times_paths": mse_times_n, "paths_needed": mse_times_n / target}
+        if mode in m2v:
+            r["mse_times_paths_m2"] = float(np.mean(m2v[mode])) / q95 ** 2
         if thr and thr.get(mode):
             r["paths_per_s"] = thr[mode]
             r["seconds"] = r["paths_needed"] / thr[mode] + t_table
@@ -276,6 +297,53 @@ def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4):
             rep[f"{mode}_over_darts_time"] = rep[mode]["seconds"] / rep["darts"]["seconds"]
         rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
     return rep
+
+
+def batched_bench(darts, torch, W, reps):
+    """The many-media sweep: 256 box media with uneven budgets in one
+    persistent launch (plan chosen by the autotuner), replayed as a captured
+    graph (clear + launch), against one render call per medium on the same
+    paths.  Tables are built once, outside the timed region."""
+    ws = W.batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tables = [darts.build_da_tables(w["scene"]["medium"], w["dims"]) for w in ws]
+    torch.cuda.synchronize()
+    t_tables = time.perf_counter() - t0
+    items = [(w["scene"], w["params"], "darts", t) for w, t in zip(ws, tables)]
+    n_paths = sum(int(w["params"]["n_paths"]) for w in ws)
+    b = darts.Batch(items)
+    hi, lo = b.empty()
+    t0 = time.perf_counter()
+    plan, tuned_ms = b.autotune(hi, lo, reps=2)
+    t_tune = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    b.graph_launch(hi, lo)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.graph_launch(hi, lo)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / reps
+    # one render call per medium, same paths, into the same batch images
+    views_hi, views_lo = b.images(hi), b.images(lo)
+    seq = []
+    for r in range(2):
+        e0.record(stream)
+        for (sc, p, mode, t), h, l in zip(items, views_hi, views_lo):
+            darts.render_transient(sc, p, mode, t, h, l)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        seq.append(e0.elapsed_time(e1))
+    seq_ms = min(seq)
+    return {"media": len(ws), "paths": n_paths, "plan": plan, "autotune_s": t_tune, "tuned_launch_ms": tuned_ms,
+            "graph_launch_ms": graph_ms, "paths_per_s": n_paths / graph_ms * 1e3,
+            "separate_calls_ms": seq_ms, "speedup_vs_separate_calls": seq_ms / graph_ms,
+            "table_build_s": t_tables,
+            "workload": "256 box media, sigma_s~U[0.5,20], albedo~U[0.8,0.999], g~U[-0.3,0.9], 32x32 x 128 bins "
+                        "over [0,40), budgets log-uniform in [2^12,2^18], 64x64x32 tables"}
 
 
 def cpu_baseline(w, seconds):

@@ -18,8 +18,10 @@
  *
  * Conventions for every entry point:
  *   - Pointers named *_dev are device pointers (hipMalloc'ed or torch CUDA
- *     tensors) owned by the caller; the library never allocates, frees or
- *     keeps device memory across calls and only writes the outputs named.
+ *     tensors) owned by the caller; the library only writes the outputs
+ *     named.  Apart from batch objects (darts_batch_*), which own their
+ *     device memory from create to destroy, it never allocates, frees or
+ *     keeps device memory across calls.
  *   - Host structs are read during the call only.
  *   - `stream` is a hipStream_t (NULL = default stream); all work is enqueued
  *     on it and the call returns without synchronising.
@@ -181,6 +183,83 @@ int darts_render_paths(const darts_scene *scene, const darts_params *params,
 int darts_render_transient_backward(const darts_scene *scene, const darts_params *params,
                                     const darts_table *table, const float *grad_image_dev,
                                     double *grad_out_dev, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched persistent render: many independent scenes (media, tables,
+ * sensors, bins, path budgets) rendered by one kernel launch.  Each scene is
+ * the same estimator as darts_render_transient with the same path ids, so a
+ * batch image equals the separate renders up to the order of the
+ * floating-point additions.  The scenes' paths are cut into work units that a
+ * grid sized to the device pulls from a device counter until none are left;
+ * the counter rewinds itself at the end of the launch, so a launch can be
+ * repeated and captured in a graph.  (This serves many-configuration sweeps
+ * such as the scattering-coefficient study of Section VI.)
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    darts_scene scene;          /* read at create (emitters copied)                  */
+    darts_params params;        /* DARTS family only (no DIRECT_REUSE)               */
+    const darts_table *table;   /* required with EDA_DIR; its cdf_dev must stay valid
+                                   while the batch is used                           */
+} darts_batch_item;
+
+/* Work decomposition (chosen by darts_batch_autotune or by hand):
+ *   order DARTS_BATCH_TILES: units of 64 consecutive cells x a range of
+ *     repetitions, per-cell sums privatised in LDS and flushed once per unit
+ *     (many paths per cell);
+ *   order DARTS_BATCH_IDS: units of consecutive path ids, each finished path
+ *     added to the image with a global atomic (few paths per cell).
+ * block_threads: 64 or 256; waves_per_cu: persistent grid = compute units x
+ * waves_per_cu waves (1..64); unit_paths: paths per unit (>= 64; tile units
+ * round it down to a multiple of 64). */
+#define DARTS_BATCH_TILES 0
+#define DARTS_BATCH_IDS   1
+typedef struct {
+    int order;
+    int block_threads;
+    int waves_per_cu;
+    int64_t unit_paths;
+} darts_batch_plan;
+
+typedef struct darts_batch darts_batch;   /* opaque */
+
+/* Default plan (tile order, 256 threads, 16 waves per CU, 8192-path units). */
+int darts_batch_default_plan(darts_batch_plan *plan);
+
+/* Validate the items (as darts_render_transient would; INVALID_ARG,
+ * UNSUPPORTED or TABLE_MISMATCH name the first bad item) and build the batch
+ * on the current device: device copies of the scene parameters, the unit list
+ * of `plan` (NULL = default) and the unit counter.  *out receives the handle;
+ * nothing is allocated when validation fails. */
+int darts_batch_create(const darts_batch_item *items, int n_items, const darts_batch_plan *plan,
+                       darts_batch **out);
+
+/* Scene i's image is elements [offsets[i], offsets[i+1]) of the batch output,
+ * laid out as darts_render_transient's.  offsets: host int64[n_items + 1]. */
+int darts_batch_image_offsets(const darts_batch *batch, int64_t *offsets);
+
+/* Replace the work decomposition (rebuilds the unit list; synchronous). */
+int darts_batch_set_plan(darts_batch *batch, const darts_batch_plan *plan);
+int darts_batch_get_plan(const darts_batch *batch, darts_batch_plan *plan);
+
+/* One launch that accumulates every scene's raw sums into image_hi_dev /
+ * image_lo_dev (device float[offsets[n_items]], compensated pair).  Calls on
+ * one batch must not overlap (they share the unit counter). */
+int darts_batch_render(darts_batch *batch, float *image_hi_dev, float *image_lo_dev, void *stream);
+
+/* Clear image_hi_dev / image_lo_dev and render, as one graph (a clearing
+ * kernel and the batch kernel) captured on first use for these buffers and
+ * launched on `stream` afterwards. */
+int darts_batch_graph_launch(darts_batch *batch, float *image_hi_dev, float *image_lo_dev, void *stream);
+
+/* Time candidate plans (orders x block sizes x grid sizes x unit sizes), each
+ * one warm-up launch plus `reps` timed launches on `stream` into the given
+ * images (used as scratch: their contents are overwritten), keep the fastest
+ * and return it with its mean launch time in ms.  Synchronous. */
+int darts_batch_autotune(darts_batch *batch, float *image_hi_dev, float *image_lo_dev, int reps,
+                         darts_batch_plan *chosen, double *best_ms, void *stream);
+
+/* Release the batch's device memory and graph. */
+int darts_batch_destroy(darts_batch *batch);
 
 /* Diagnostic: evaluate one device building block on n items (one thread per
  * item) with the same device functions the render kernel uses.  in_dev:

@@ -309,19 +309,12 @@ __device__ __forceinline__ void direction_darts(const KParams &P, PathState &s, 
 // vertex k): medium-event Bernoulli (Eq. (12)), DA-RIS or exponential
 // distance, then the early-exit test at the new vertex.  Returns false when
 // the path has ended.
-template <int OUT, bool QUEUE, class ST>
-__device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &st, float grad_w, double *gacc,
-                                bool &push, Conn &q)
+template <int OUT, class ST>
+__device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &st, float grad_w, double *gacc)
 {
     const Medium &m = P.med;
     const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
-    if (QUEUE) {
-        // defer the contribution to the wave's connection queue
-        push = connect_range(P, s, q.S_lo, q.S_hi);
-        if (push) {
-            q.x = s.x; q.w = s.w; q.xe = s.xe; q.C = s.C; q.scale = s.beta * s.em_scale; q.u = u01(r1.x);
-        }
-    } else {
+    {
         float dl[3];
         const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD ? dl : nullptr);
         if (c != 0.f) {
@@ -418,24 +411,26 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
     return true;
 }
 
-// Render kernel.  Each wave owns a tile of 64 consecutive cells (later time
-// bins first) and a range of repetitions; its lanes pull the next path of the
-// tile as soon as their current path ends (ballot + popcount on a wave-uniform
-// counter, no memory atomics), so lanes stay busy until the tile's pool is
-// empty.  One loop iteration is: stream-0 Philox of the current vertex ->
-// camera set-up (fresh path) or direction sampling; stream-1 Philox ->
-// connection and free flight.  Per-cell sums are compensated LDS
-// accumulators (one slot per tile cell), flushed with one compensated global
-// atomic pair per cell when the wave's pool is drained.
+// ---------------------------------------------------------------------------
+// Path pool.  A wave works through a range [j_begin, j_end) of path slots; its
+// lanes pull the next slot as soon as their current path ends (ballot +
+// popcount on a wave-uniform counter, no memory atomics), so lanes stay busy
+// until the range is exhausted.  One loop iteration is: stream-0 Philox of
+// the current vertex -> camera set-up (fresh path) or direction sampling;
+// stream-1 Philox -> connection and free flight.
+//
+// Two slot sources:
+//  - SRC_TILE: slot j is repetition j / 64 of cell c0 + (j mod 64) of a tile
+//    of 64 consecutive cells.  Per-cell sums go to compensated LDS
+//    accumulators (one slot per tile cell), flushed by the caller with one
+//    compensated global atomic pair per cell: the histogram is privatised.
+//  - SRC_IDS: slot j is path id j itself, in cell c0 + (j - j_begin) (wrapped
+//    once at n_cells; the caller keeps ranges no longer than n_cells).  Each
+//    finished path adds its sum to the global image with one compensated
+//    atomic pair: suited to scenes with few paths per cell.
+// ---------------------------------------------------------------------------
 enum { LANE_NEED = 0, LANE_FRESH = 1, LANE_ACTIVE = 2, LANE_DONE = 3 };
-
-// Connection queue (image mode without second moments): a lane whose vertex
-// admits a connection pushes it into its wave's LDS ring of 128 entries; as
-// soon as 64 are pending, all 64 lanes evaluate one each and add it to the
-// cell accumulators, so the connection arithmetic runs with full lanes
-// instead of with the few lanes that connect in a given iteration.
-constexpr int kQueue = 128;
-constexpr int kQFields = 12;
+enum { SRC_TILE = 0, SRC_IDS = 1 };
 
 __device__ __forceinline__ void compensated_lds_add(float *hi, float *lo, int i, float v)
 {
@@ -444,73 +439,24 @@ __device__ __forceinline__ void compensated_lds_add(float *hi, float *lo, int i,
     if (e != 0.f) atomicAdd(&lo[i], e);
 }
 
-// Emitter index of a position (the queue stores an index, not the position).
-__device__ __forceinline__ int emitter_index(const KParams &P, V3 xe)
+template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, int SRC>
+__device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end,
+                                         float *img_hi, float *img_lo, float *acc_hi, float *acc_lo,
+                                         float *acc_m2, Stats<STATS> &st, double *gacc)
 {
-    int j = 0;
-    if (P.n_em == 1) return 0;
-#pragma unroll
-    for (int i = 1; i < DARTS_MAX_EMITTERS; ++i)
-        if (i < P.n_em && xe.x == P.em_pos[i][0] && xe.y == P.em_pos[i][1] && xe.z == P.em_pos[i][2]) j = i;
-    return j;
-}
-
-// Evaluate queue entries [head, head + n) (lane i takes entry head + i) and
-// add them to the cell accumulators of this wave.
-template <class ST>
-__device__ __forceinline__ void drain_queue(const KParams &P, const float *cq, uint32_t head, uint32_t n,
-                                            float *acc_hi, float *acc_lo, ST &st)
-{
-    const uint32_t lane = threadIdx.x & 63;
-    if (lane < n) {
-        const float *e = cq + ((head + lane) & (kQueue - 1));
-        Conn q;
-        q.x = V3{e[0 * kQueue], e[1 * kQueue], e[2 * kQueue]};
-        q.w = V3{e[3 * kQueue], e[4 * kQueue], e[5 * kQueue]};
-        q.C = e[6 * kQueue]; q.S_lo = e[7 * kQueue]; q.S_hi = e[8 * kQueue];
-        q.scale = e[9 * kQueue]; q.u = e[10 * kQueue];
-        const int packed = __float_as_int(e[11 * kQueue]);
-        float start, sc;
-        emitter(P, packed >> 8, q.xe, start, sc);
-        float mu_c, t, r_in;
-        const float c = connect_eval(P, q, mu_c, t, r_in);
-        if (c != 0.f) {
-            st.inc(DARTS_ST_CONNECTIONS);
-            compensated_lds_add(acc_hi, acc_lo, packed & 63, c);
-        }
-    }
-}
-
-template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, bool QUEUE>
-__global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_kernel(KParams P)
-{
-    __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
-    __shared__ float cq_mem[QUEUE ? (kBlock / 64) * kQFields * kQueue : 1];
-    float *cq = cq_mem + (QUEUE ? (threadIdx.x >> 6) * kQFields * kQueue : 0);
-    uint32_t q_head = 0, q_count = 0;   // wave-uniform
     const int lane = threadIdx.x & 63;
-    const int wbase = threadIdx.x & ~63;
-    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const bool have = wave < P.n_waves;
-    const uint64_t tile = have ? wave % P.n_tiles : 0;
-    const uint64_t chunk = have ? wave / P.n_tiles : 0;
-    const int64_t c0 = (int64_t)(P.n_tiles - 1 - tile) * 64;         // later bins first
-    const uint64_t j_begin = chunk * P.chunk_reps * 64;
-    const uint64_t j_end = have ? min((chunk + 1) * P.chunk_reps, P.max_reps) * 64 : j_begin;
     const uint64_t lanes_below = (1ull << lane) - 1ull;
-    acc_hi[threadIdx.x] = 0.f;
-    acc_lo[threadIdx.x] = 0.f;
-    acc_m2[threadIdx.x] = 0.f;
 
-    // Lane l describes tile cell c0 + l (time bin, pixel, repetition bounds);
-    // a lane starting a path of cell c0 + sl reads lane sl's description with
-    // a cross-lane permute instead of dividing 64-bit indices per path.
+    // SRC_TILE: lane l describes tile cell c0 + l (time bin, pixel, repetition
+    // bounds); a lane starting a path of cell c0 + sl reads lane sl's
+    // description with a cross-lane permute instead of dividing 64-bit
+    // indices per path.
     int my_bin = 0, my_px = 0, my_py = 0;
     int my_flags = 0;   // bit 0: the cell exists, bit 1: cell < r0, bit 2: cell < r1
     float my_gw = 0.f;
-    {
+    if (SRC == SRC_TILE) {
         const int64_t my_cell = c0 + lane;
-        if (have && my_cell < P.ncells) {
+        if (j_begin < j_end && my_cell < P.ncells) {
             const int64_t b = my_cell / P.npix;
             const int64_t pix = my_cell - b * P.npix;
             my_bin = (int)b;
@@ -521,54 +467,75 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
         }
     }
 
-    using ST_T = Stats<STATS>;
-    ST_T st;
-#pragma unroll
-    for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     PathState s;
     uint64_t next = j_begin;
-    int state = have ? LANE_NEED : LANE_DONE;
+    int state = j_begin < j_end ? LANE_NEED : LANE_DONE;
     uint64_t p = 0;
     int slot = 0;
     int bin = 0, px = 0, py = 0;
-    int64_t pixel = 0;
+    int64_t pixel = 0, cell = 0;
     float grad_w = 0.f;
-    double gacc[3] = {0.0, 0.0, 0.0};
 
     while (true) {
         const bool want = state == LANE_NEED;
         const uint64_t need = __ballot(want);
         if (need) {
-            // whole wave active here: the permutes read every lane's description
             const uint64_t j = next + (uint64_t)__popcll(need & lanes_below);
-            const int sl = (int)(j & 63);
-            const int fl = __shfl(my_flags, sl);
-            const int c_bin = __shfl(my_bin, sl), c_px = __shfl(my_px, sl), c_py = __shfl(my_py, sl);
-            const float c_gw = OUT == OUT_GRAD ? __shfl(my_gw, sl) : 0.f;
-            if (want) {
+            if (SRC == SRC_TILE) {
+                // whole wave active here: the permutes read every lane's description
+                const int sl = (int)(j & 63);
+                const int fl = __shfl(my_flags, sl);
+                const int c_bin = __shfl(my_bin, sl), c_px = __shfl(my_px, sl), c_py = __shfl(my_py, sl);
+                const float c_gw = OUT == OUT_GRAD ? __shfl(my_gw, sl) : 0.f;
+                if (want) {
+                    if (j >= j_end) {
+                        state = LANE_DONE;
+                    } else {
+                        const uint64_t rep = j >> 6;
+                        const uint64_t m = P.q0 + (uint64_t)((fl >> 1) & 1) + rep;
+                        const uint64_t m_hi = P.q1 + (uint64_t)((fl >> 2) & 1);
+                        if ((fl & 1) && m < m_hi) {
+                            cell = c0 + sl;
+                            p = (uint64_t)cell + m * (uint64_t)P.ncells;
+                            slot = sl;
+                            bin = c_bin;
+                            px = c_px;
+                            py = c_py;
+                            pixel = (int64_t)c_py * P.width + c_px;
+                            if (OUT == OUT_GRAD) grad_w = c_gw;
+                            state = LANE_FRESH;
+                        }   // else: an empty slot of a ragged range; pull again next iteration
+                    }
+                }
+            } else if (want) {
                 if (j >= j_end) {
                     state = LANE_DONE;
                 } else {
-                    const uint64_t rep = j >> 6;
-                    const uint64_t m = P.q0 + (uint64_t)((fl >> 1) & 1) + rep;
-                    const uint64_t m_hi = P.q1 + (uint64_t)((fl >> 2) & 1);
-                    if ((fl & 1) && m < m_hi) {
-                        p = (uint64_t)(c0 + sl) + m * (uint64_t)P.ncells;
-                        slot = sl;
-                        bin = c_bin;
-                        px = c_px;
-                        py = c_py;
-                        pixel = (int64_t)c_py * P.width + c_px;
-                        if (OUT == OUT_GRAD) grad_w = c_gw;
-                        state = LANE_FRESH;
-                    }   // else: an empty slot of a ragged range; pull again next iteration
+                    p = j;
+                    cell = c0 + (int64_t)(j - j_begin);
+                    if (cell >= P.ncells) cell -= P.ncells;
+                    if (P.ncells <= 0xFFFFFFFFll) {
+                        const uint32_t c32 = (uint32_t)cell, np = (uint32_t)P.npix;
+                        const uint32_t b = c32 / np, pix = c32 - b * np;
+                        const uint32_t y = pix / (uint32_t)P.width;
+                        bin = (int)b;
+                        py = (int)y;
+                        px = (int)(pix - y * (uint32_t)P.width);
+                        pixel = pix;
+                    } else {
+                        const int64_t b = cell / P.npix;
+                        pixel = cell - b * P.npix;
+                        bin = (int)b;
+                        py = (int)(pixel / P.width);
+                        px = (int)(pixel - (int64_t)py * P.width);
+                    }
+                    if (OUT == OUT_GRAD) grad_w = P.grad_image[cell];
+                    state = LANE_FRESH;
                 }
             }
             next += (uint64_t)__popcll(need);
         }
         if (__ballot(state != LANE_DONE) == 0) break;
-        bool push = false;
-        Conn qc;
         if (state == LANE_FRESH || state == LANE_ACTIVE) {
             const bool fresh = state == LANE_FRESH;
             const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), fresh ? 0u : (uint32_t)s.k, 0u, P.key0, P.key1);
@@ -583,7 +550,7 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
             }
             if (alive) {
                 if (MODE == 1) alive = fly_vanilla(P, p, pixel, s, st);
-                else alive = connect_and_fly<OUT, QUEUE>(P, p, s, st, grad_w, gacc, push, qc);
+                else alive = connect_and_fly<OUT>(P, p, s, st, grad_w, gacc);
             }
             if (alive) {
                 state = LANE_ACTIVE;
@@ -593,40 +560,48 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
                 if (MODE == 0) {
                     if (OUT == OUT_PATHS) {
                         P.path_out[p - P.path_offset] = s.acc;
-                    } else if (OUT == OUT_IMAGE && !QUEUE && s.acc != 0.f) {
-                        compensated_lds_add(acc_hi + wbase, acc_lo + wbase, slot, s.acc);
-                        if (P.m2) atomicAdd(&acc_m2[wbase + slot], s.acc * s.acc);
+                    } else if (OUT == OUT_IMAGE && s.acc != 0.f) {
+                        if (SRC == SRC_TILE) {
+                            compensated_lds_add(acc_hi, acc_lo, slot, s.acc);
+                            if (P.m2) atomicAdd(&acc_m2[slot], s.acc * s.acc);
+                        } else {
+                            add_compensated(img_hi, img_lo, cell, s.acc, 0.f);
+                            if (P.m2) unsafeAtomicAdd(P.m2 + cell, s.acc * s.acc);
+                        }
                     }
                 }
             }
         }
-        if (QUEUE) {
-            const uint64_t pm = __ballot(push);
-            if (pm) {
-                if (push) {
-                    const uint32_t pos = (q_head + q_count + (uint32_t)__popcll(pm & lanes_below)) & (kQueue - 1);
-                    float *e = cq + pos;
-                    e[0 * kQueue] = qc.x.x; e[1 * kQueue] = qc.x.y; e[2 * kQueue] = qc.x.z;
-                    e[3 * kQueue] = qc.w.x; e[4 * kQueue] = qc.w.y; e[5 * kQueue] = qc.w.z;
-                    e[6 * kQueue] = qc.C; e[7 * kQueue] = qc.S_lo; e[8 * kQueue] = qc.S_hi;
-                    e[9 * kQueue] = qc.scale; e[10 * kQueue] = qc.u;
-                    e[11 * kQueue] = __int_as_float(slot | (emitter_index(P, qc.xe) << 8));
-                }
-                q_count += (uint32_t)__popcll(pm);
-            }
-            if (q_count >= 64) {
-                __builtin_amdgcn_wave_barrier();
-                drain_queue<ST_T>(P, cq, q_head, 64, acc_hi + wbase, acc_lo + wbase, st);
-                q_head = (q_head + 64) & (kQueue - 1);
-                q_count -= 64;
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
     }
-    if (QUEUE && q_count > 0) {
-        __builtin_amdgcn_wave_barrier();
-        drain_queue<ST_T>(P, cq, q_head, q_count, acc_hi + wbase, acc_lo + wbase, st);
-    }
+}
+
+// Single-scene render kernel: each wave owns a tile of 64 consecutive cells
+// (later time bins first, so the long paths start first) and a chunk of
+// repetitions, runs its pool with LDS accumulators and flushes one
+// compensated global atomic pair per cell.
+template <int MODE, int OUT, bool STATS>
+__global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_kernel(KParams P)
+{
+    __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const bool have = wave < P.n_waves;
+    const uint64_t tile = have ? wave % P.n_tiles : 0;
+    const uint64_t chunk = have ? wave / P.n_tiles : 0;
+    const int64_t c0 = (int64_t)(P.n_tiles - 1 - tile) * 64;
+    const uint64_t j_begin = chunk * P.chunk_reps * 64;
+    const uint64_t j_end = have ? min((chunk + 1) * P.chunk_reps, P.max_reps) * 64 : j_begin;
+    acc_hi[threadIdx.x] = 0.f;
+    acc_lo[threadIdx.x] = 0.f;
+    acc_m2[threadIdx.x] = 0.f;
+
+    Stats<STATS> st;
+#pragma unroll
+    for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
+    double gacc[3] = {0.0, 0.0, 0.0};
+    run_pool<MODE, OUT, STATS, SRC_TILE>(P, c0, j_begin, j_end, nullptr, nullptr, acc_hi + wbase, acc_lo + wbase,
+                                         acc_m2 + wbase, st, gacc);
 
     if (MODE == 0 && OUT == OUT_IMAGE && have) {
         const int64_t cell = c0 + lane;
@@ -651,6 +626,94 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
             if (lane == 0 && v) atomicAdd(P.stats + i, (unsigned long long)v);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent render: many scenes (each with its own medium, table,
+// sensor, bins and path budget) in one launch.  The host cuts every scene's
+// paths into work units; a grid sized to the machine pulls units from a
+// global counter (one vector atomic per unit) until none are left, so scenes
+// with long paths do not hold up the rest.  The last wave to leave rewinds
+// the counters, which makes the launch repeatable (and capturable in a graph)
+// without a clearing step.
+// ---------------------------------------------------------------------------
+struct BItem {
+    KParams P;              // the scene's parameters (output pointers unused)
+    int64_t image_offset;   // first element of the scene's image in the batch output
+};
+
+struct BUnit {
+    uint32_t item;
+    uint32_t pad;
+    int64_t c0;             // SRC_TILE: first tile cell; SRC_IDS: cell of path j_begin
+    uint64_t j_begin, j_end;
+};
+
+struct BParams {
+    const BItem *items;
+    const BUnit *units;
+    uint32_t n_units;
+    uint32_t n_waves;       // waves in the grid
+    unsigned *ctr;          // [0] next unit, [1] waves finished; zero between launches
+    float *hi, *lo;
+};
+
+typedef __attribute__((address_space(4))) const BItem CItem;
+typedef __attribute__((address_space(4))) const BUnit CUnit;
+
+template <int SRC, int BLOCK>
+__global__ __launch_bounds__(BLOCK, DARTS_RENDER_WAVES_PER_SIMD) void batch_kernel(BParams B)
+{
+    __shared__ float acc_hi[BLOCK], acc_lo[BLOCK];
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
+    Stats<false> st;
+    while (true) {
+        uint32_t u = 0;
+        if (lane == 0) u = atomicAdd(&B.ctr[0], 1u);
+        u = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)u, 0));
+        if (u >= B.n_units) break;
+        // unit and scene parameters are read-only and wave-uniform: reading
+        // them through the constant address space lets them live in scalar
+        // registers instead of being loaded per lane
+        const CUnit *units = (const CUnit *)B.units;
+        const CItem *items = (const CItem *)B.items;
+        const uint32_t item = units[u].item;
+        const int64_t c0 = units[u].c0;
+        const uint64_t j_begin = units[u].j_begin, j_end = units[u].j_end;
+        const KParams &P = *(const KParams *)&items[item].P;
+        const int64_t off = items[item].image_offset;
+        float *img_hi = B.hi + off, *img_lo = B.lo + off;
+        if (SRC == SRC_TILE) {
+            acc_hi[threadIdx.x] = 0.f;
+            acc_lo[threadIdx.x] = 0.f;
+        }
+        run_pool<0, OUT_IMAGE, false, SRC>(P, c0, j_begin, j_end, img_hi, img_lo, acc_hi + wbase, acc_lo + wbase,
+                                           nullptr, st, nullptr);
+        if (SRC == SRC_TILE) {
+            const int64_t cell = c0 + lane;
+            const float h = acc_hi[threadIdx.x], l = acc_lo[threadIdx.x];
+            if (cell < P.ncells && (h != 0.f || l != 0.f)) add_compensated(img_hi, img_lo, cell, h, l);
+        }
+    }
+    // every wave has made its last pull once all have counted themselves out
+    if (lane == 0) {
+        const unsigned done = atomicAdd(&B.ctr[1], 1u);
+        if (done == B.n_waves - 1) {
+            atomicExch(&B.ctr[0], 0u);
+            atomicExch(&B.ctr[1], 0u);
+        }
+    }
+}
+
+__global__ void zero2_kernel(float *a, float *b, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n; k += stride) {
+        a[k] = 0.f;
+        b[k] = 0.f;
     }
 }
 
@@ -907,7 +970,6 @@ int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &
 }
 
 int64_t g_target_waves = 1 << 14;
-bool g_use_queue = false;
 
 int make_params(const darts_scene *sc, const darts_params *pr, const darts_table *table, KParams &P,
                 bool per_path_only)
@@ -1017,20 +1079,183 @@ int launch_render(const KParams &P, bool stats, hipStream_t stream)
 {
     const uint64_t blocks = (P.n_waves + kBlock / 64 - 1) / (kBlock / 64);
     if (blocks == 0 || P.n_paths == 0) return ok();
-    // the queue loses the per-path sums that the second moments and the
-    // statistics counters need; those launches evaluate connections in place
-    const bool queue = MODE == 0 && OUT == OUT_IMAGE && P.m2 == nullptr && !stats && g_use_queue;
     const dim3 grid((uint32_t)blocks), block(kBlock);
-    if (queue) {
-        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, true>), grid, block, 0, stream, P);
-        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, true>), grid, block, 0, stream, P);
-    } else {
-        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, false>), grid, block, 0, stream, P);
-        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, false>), grid, block, 0, stream, P);
-    }
+    if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true>), grid, block, 0, stream, P);
+    else hipLaunchKernelGGL((render_kernel<MODE, OUT, false>), grid, block, 0, stream, P);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "render launch failed: %s", hipGetErrorString(e));
     return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Batched render: host side
+// ---------------------------------------------------------------------------
+bool valid_plan(const darts_batch_plan &pl)
+{
+    return (pl.order == DARTS_BATCH_TILES || pl.order == DARTS_BATCH_IDS) &&
+           (pl.block_threads == 64 || pl.block_threads == 256) && pl.waves_per_cu >= 1 && pl.waves_per_cu <= 64 &&
+           pl.unit_paths >= 64 && pl.unit_paths <= ((int64_t)1 << 32);
+}
+
+darts_batch_plan default_plan()
+{
+    darts_batch_plan pl;
+    pl.order = DARTS_BATCH_TILES;
+    pl.block_threads = 256;
+    pl.waves_per_cu = 16;
+    pl.unit_paths = 8192;
+    return pl;
+}
+
+// Rough cost of one path of a scene (vertex steps), used only to start the
+// expensive units first: the walk ends after about sigma_t * length steps or
+// at max_bounces.
+double path_cost(const KParams &P)
+{
+    const double len = std::max(1.0, (double)P.l_hi - (double)P.l_lo);
+    const double steps = 2.0 + (double)P.med.sigma_t * std::min(len, 1.0 / std::max((double)P.med.sigma_a, 1e-6));
+    return std::min(steps, (double)P.max_bounces + 1.0);
+}
+
+// Number of repetitions of cell c in the scene's path range.
+uint64_t reps_of(const KParams &P, uint64_t c)
+{
+    return (P.q1 + (c < P.r1 ? 1 : 0)) - (P.q0 + (c < P.r0 ? 1 : 0));
+}
+
+struct UnitCost {
+    BUnit u;
+    double cost;
+};
+
+void build_units(const std::vector<BItem> &items, const darts_batch_plan &pl, std::vector<BUnit> &out)
+{
+    std::vector<UnitCost> v;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const KParams &P = items[i].P;
+        const double pc = path_cost(P);
+        const uint64_t nc = (uint64_t)P.ncells;
+        if (P.n_paths == 0) continue;
+        if (pl.order == DARTS_BATCH_TILES) {
+            const uint64_t reps_unit = std::max<uint64_t>(1, (uint64_t)pl.unit_paths / 64);
+            for (uint64_t t = 0; t < (uint64_t)P.n_tiles; ++t) {
+                // later bins first inside a scene (long paths start early)
+                const uint64_t c0 = ((uint64_t)P.n_tiles - 1 - t) * 64;
+                const uint64_t c1 = std::min(c0 + 64, nc) - 1;
+                // repetitions per cell change only at r0 and r1
+                uint64_t reps = std::max(reps_of(P, c0), reps_of(P, c1));
+                if (P.r0 > c0 && P.r0 <= c1) reps = std::max(reps, reps_of(P, P.r0));
+                if (P.r1 > c0 && P.r1 <= c1) reps = std::max(reps, reps_of(P, P.r1 - 1));
+                for (uint64_t r = 0; r < reps; r += reps_unit) {
+                    UnitCost uc;
+                    uc.u.item = (uint32_t)i;
+                    uc.u.pad = 0;
+                    uc.u.c0 = (int64_t)c0;
+                    uc.u.j_begin = r * 64;
+                    uc.u.j_end = std::min(r + reps_unit, reps) * 64;
+                    uc.cost = pc * (double)(uc.u.j_end - uc.u.j_begin);
+                    v.push_back(uc);
+                }
+            }
+        } else {
+            const uint64_t step = std::min<uint64_t>((uint64_t)pl.unit_paths, nc);
+            const uint64_t end = P.path_offset + P.n_paths;
+            for (uint64_t j = P.path_offset; j < end; j += std::min(step, end - j)) {
+                UnitCost uc;
+                uc.u.item = (uint32_t)i;
+                uc.u.pad = 0;
+                uc.u.c0 = (int64_t)(j % nc);
+                uc.u.j_begin = j;
+                uc.u.j_end = j + std::min(step, end - j);
+                uc.cost = pc * (double)(uc.u.j_end - uc.u.j_begin);
+                v.push_back(uc);
+            }
+        }
+    }
+    std::stable_sort(v.begin(), v.end(), [](const UnitCost &a, const UnitCost &b) { return a.cost > b.cost; });
+    out.resize(v.size());
+    for (size_t k = 0; k < v.size(); ++k) out[k] = v[k].u;
+}
+
+}  // namespace
+
+struct darts_batch {
+    int device = 0;
+    int n_cu = 0;
+    std::vector<BItem> items;
+    std::vector<int64_t> offsets;
+    darts_batch_plan plan{};
+    BItem *items_dev = nullptr;
+    BUnit *units_dev = nullptr;
+    uint32_t n_units = 0;
+    unsigned *ctr_dev = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float *graph_hi = nullptr, *graph_lo = nullptr;
+};
+
+namespace {
+
+void drop_graph(darts_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->graph_hi = b->graph_lo = nullptr;
+}
+
+int upload_units(darts_batch *b, const darts_batch_plan &pl)
+{
+    std::vector<BUnit> units;
+    build_units(b->items, pl, units);
+    if (units.size() > 0xFFFFFFF0ull) return fail(DARTS_ERR_INVALID_ARG, "too many work units; raise unit_paths");
+    BUnit *dev = nullptr;
+    if (!units.empty()) {
+        if (hipMalloc(&dev, units.size() * sizeof(BUnit)) != hipSuccess)
+            return fail(DARTS_ERR_DEVICE, "allocating %zu work units failed", units.size());
+        if (hipMemcpy(dev, units.data(), units.size() * sizeof(BUnit), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(dev);
+            return fail(DARTS_ERR_DEVICE, "uploading work units failed");
+        }
+    }
+    if (b->units_dev) (void)hipFree(b->units_dev);
+    b->units_dev = dev;
+    b->n_units = (uint32_t)units.size();
+    b->plan = pl;
+    drop_graph(b);
+    return DARTS_OK;
+}
+
+int launch_batch(const darts_batch *b, float *hi, float *lo, hipStream_t stream)
+{
+    if (b->n_units == 0) return ok();
+    const int per_block = b->plan.block_threads / 64;
+    const uint32_t blocks = (uint32_t)std::max(1, b->n_cu * b->plan.waves_per_cu / per_block);
+    BParams B;
+    B.items = b->items_dev;
+    B.units = b->units_dev;
+    B.n_units = b->n_units;
+    B.n_waves = blocks * (uint32_t)per_block;   // exactly the waves launched: the last one rewinds the counter
+    B.ctr = b->ctr_dev;
+    B.hi = hi;
+    B.lo = lo;
+    const dim3 grid(blocks);
+    if (b->plan.block_threads == 64) {
+        if (b->plan.order == DARTS_BATCH_TILES) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 64>), grid, dim3(64), 0, stream, B);
+        else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 64>), grid, dim3(64), 0, stream, B);
+    } else {
+        if (b->plan.order == DARTS_BATCH_TILES) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 256>), grid, dim3(256), 0, stream, B);
+        else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 256>), grid, dim3(256), 0, stream, B);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+int check_batch_device(const darts_batch *b)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return fail(DARTS_ERR_INVALID_ARG, "batch was created on device %d, current device is %d", b->device, dev);
+    return DARTS_OK;
 }
 
 }  // namespace
@@ -1114,6 +1339,194 @@ int darts_render_transient_backward(const darts_scene *scene, const darts_params
     return launch_render<0, OUT_GRAD>(P, false, (hipStream_t)stream);
 }
 
+int darts_batch_default_plan(darts_batch_plan *plan)
+{
+    if (!plan) return fail(DARTS_ERR_INVALID_ARG, "plan is null");
+    *plan = default_plan();
+    return ok();
+}
+
+int darts_batch_create(const darts_batch_item *items, int n_items, const darts_batch_plan *plan, darts_batch **out)
+{
+    if (!out) return fail(DARTS_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (n_items < 1 || !items) return fail(DARTS_ERR_INVALID_ARG, "need at least one item");
+    const darts_batch_plan pl = plan ? *plan : default_plan();
+    if (!valid_plan(pl)) return fail(DARTS_ERR_INVALID_ARG, "invalid batch plan");
+    std::vector<BItem> host((size_t)n_items);
+    std::vector<int64_t> offsets((size_t)n_items + 1, 0);
+    for (int i = 0; i < n_items; ++i) {
+        const darts_batch_item &it = items[i];
+        if (it.params.flags & DARTS_DIRECT_REUSE)
+            return fail(DARTS_ERR_UNSUPPORTED, "item %d: batches render the DARTS family only", i);
+        KParams &P = host[(size_t)i].P;
+        if (int rc = make_params(&it.scene, &it.params, it.table, P, false)) {
+            const std::string msg = g_last_error;
+            return fail(rc, "item %d: %s", i, msg.c_str());
+        }
+        host[(size_t)i].image_offset = offsets[(size_t)i];
+        offsets[(size_t)i + 1] = offsets[(size_t)i] + P.ncells;
+    }
+    if (offsets.back() > ((int64_t)1 << 40)) return fail(DARTS_ERR_INVALID_ARG, "batch image too large");
+
+    auto *b = new darts_batch();
+    b->items = std::move(host);
+    b->offsets = std::move(offsets);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete b;
+        return fail(DARTS_ERR_DEVICE, "no usable HIP device");
+    }
+    b->device = dev;
+    b->n_cu = prop.multiProcessorCount;
+    const size_t ib = b->items.size() * sizeof(BItem);
+    if (hipMalloc(&b->items_dev, ib) != hipSuccess || hipMalloc(&b->ctr_dev, 2 * sizeof(unsigned)) != hipSuccess ||
+        hipMemcpy(b->items_dev, b->items.data(), ib, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(b->ctr_dev, 0, 2 * sizeof(unsigned)) != hipSuccess) {
+        darts_batch_destroy(b);
+        return fail(DARTS_ERR_DEVICE, "allocating the batch failed");
+    }
+    if (int rc = upload_units(b, pl)) {
+        const std::string msg = g_last_error;
+        darts_batch_destroy(b);
+        return fail(rc, "%s", msg.c_str());
+    }
+    *out = b;
+    return ok();
+}
+
+int darts_batch_image_offsets(const darts_batch *batch, int64_t *offsets)
+{
+    if (!batch || !offsets) return fail(DARTS_ERR_INVALID_ARG, "batch or offsets is null");
+    std::memcpy(offsets, batch->offsets.data(), batch->offsets.size() * sizeof(int64_t));
+    return ok();
+}
+
+int darts_batch_set_plan(darts_batch *batch, const darts_batch_plan *plan)
+{
+    if (!batch || !plan) return fail(DARTS_ERR_INVALID_ARG, "batch or plan is null");
+    if (!valid_plan(*plan)) return fail(DARTS_ERR_INVALID_ARG, "invalid batch plan");
+    if (int rc = check_batch_device(batch)) return rc;
+    if (int rc = upload_units(batch, *plan)) return rc;
+    return ok();
+}
+
+int darts_batch_get_plan(const darts_batch *batch, darts_batch_plan *plan)
+{
+    if (!batch || !plan) return fail(DARTS_ERR_INVALID_ARG, "batch or plan is null");
+    *plan = batch->plan;
+    return ok();
+}
+
+int darts_batch_render(darts_batch *batch, float *image_hi_dev, float *image_lo_dev, void *stream)
+{
+    if (!batch) return fail(DARTS_ERR_INVALID_ARG, "batch is null");
+    if (!image_hi_dev || !image_lo_dev) return fail(DARTS_ERR_INVALID_ARG, "image_hi/lo are null");
+    if (int rc = check_batch_device(batch)) return rc;
+    return launch_batch(batch, image_hi_dev, image_lo_dev, (hipStream_t)stream);
+}
+
+int darts_batch_graph_launch(darts_batch *batch, float *image_hi_dev, float *image_lo_dev, void *stream)
+{
+    if (!batch) return fail(DARTS_ERR_INVALID_ARG, "batch is null");
+    if (!image_hi_dev || !image_lo_dev) return fail(DARTS_ERR_INVALID_ARG, "image_hi/lo are null");
+    if (int rc = check_batch_device(batch)) return rc;
+    if (!batch->exec || batch->graph_hi != image_hi_dev || batch->graph_lo != image_lo_dev) {
+        drop_graph(batch);
+        hipStream_t cs = nullptr;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+            return fail(DARTS_ERR_DEVICE, "creating the capture stream failed");
+        hipGraph_t g = nullptr;
+        int rc = DARTS_OK;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = fail(DARTS_ERR_DEVICE, "begin capture failed");
+        } else {
+            const int64_t n = batch->offsets.back();
+            const uint32_t zb = (uint32_t)std::min<int64_t>((n + 255) / 256, 4096);
+            hipLaunchKernelGGL(zero2_kernel, dim3(std::max<uint32_t>(zb, 1)), dim3(256), 0, cs, image_hi_dev,
+                               image_lo_dev, n);
+            rc = launch_batch(batch, image_hi_dev, image_lo_dev, cs);
+            const hipError_t e = hipStreamEndCapture(cs, &g);
+            if (rc == DARTS_OK && e != hipSuccess) rc = fail(DARTS_ERR_DEVICE, "end capture failed");
+        }
+        if (rc == DARTS_OK && hipGraphInstantiate(&batch->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            batch->exec = nullptr;
+            rc = fail(DARTS_ERR_DEVICE, "graph instantiation failed");
+        }
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        if (rc != DARTS_OK) return rc;
+        batch->graph_hi = image_hi_dev;
+        batch->graph_lo = image_lo_dev;
+    }
+    if (hipGraphLaunch(batch->exec, (hipStream_t)stream) != hipSuccess)
+        return fail(DARTS_ERR_DEVICE, "graph launch failed");
+    return ok();
+}
+
+int darts_batch_autotune(darts_batch *batch, float *image_hi_dev, float *image_lo_dev, int reps,
+                         darts_batch_plan *chosen, double *best_ms, void *stream)
+{
+    if (!batch) return fail(DARTS_ERR_INVALID_ARG, "batch is null");
+    if (!image_hi_dev || !image_lo_dev) return fail(DARTS_ERR_INVALID_ARG, "image_hi/lo are null");
+    if (reps < 1) return fail(DARTS_ERR_INVALID_ARG, "reps must be >= 1");
+    if (int rc = check_batch_device(batch)) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(DARTS_ERR_DEVICE, "creating timing events failed");
+    const darts_batch_plan start = batch->plan;
+    darts_batch_plan best = start;
+    double best_t = 1e300;
+    int rc = DARTS_OK;
+    for (int order : {DARTS_BATCH_TILES, DARTS_BATCH_IDS})
+        for (int bt : {64, 256})
+            for (int wpc : {16, 32})
+                for (int64_t up : {(int64_t)2048, (int64_t)8192, (int64_t)32768}) {
+                    if (rc != DARTS_OK) break;
+                    darts_batch_plan pl{order, bt, wpc, up};
+                    if ((rc = upload_units(batch, pl)) != DARTS_OK) break;
+                    if ((rc = launch_batch(batch, image_hi_dev, image_lo_dev, st)) != DARTS_OK) break;
+                    (void)hipEventRecord(e0, st);
+                    for (int r = 0; r < reps && rc == DARTS_OK; ++r)
+                        rc = launch_batch(batch, image_hi_dev, image_lo_dev, st);
+                    (void)hipEventRecord(e1, st);
+                    if (rc != DARTS_OK) break;
+                    float ms = 0.f;
+                    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        rc = fail(DARTS_ERR_DEVICE, "timing a candidate plan failed");
+                        break;
+                    }
+                    if (ms / reps < best_t) {
+                        best_t = ms / reps;
+                        best = pl;
+                    }
+                }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DARTS_OK) {
+        const std::string msg = g_last_error;
+        (void)upload_units(batch, start);
+        return fail(rc, "%s", msg.c_str());
+    }
+    if ((rc = upload_units(batch, best)) != DARTS_OK) return rc;
+    if (chosen) *chosen = best;
+    if (best_ms) *best_ms = best_t;
+    return ok();
+}
+
+int darts_batch_destroy(darts_batch *batch)
+{
+    if (!batch) return ok();
+    drop_graph(batch);
+    if (batch->units_dev) (void)hipFree(batch->units_dev);
+    if (batch->items_dev) (void)hipFree(batch->items_dev);
+    if (batch->ctr_dev) (void)hipFree(batch->ctr_dev);
+    delete batch;
+    return ok();
+}
+
 int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n, const darts_medium *medium,
                           const darts_table *table, void *stream)
 {
@@ -1138,14 +1551,6 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
     hipLaunchKernelGGL(pointwise_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, (hipStream_t)stream, Q);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "pointwise launch failed: %s", hipGetErrorString(e));
-    return ok();
-}
-
-// Tuning knob (not part of the stable ABI): evaluate connections through the
-// wave's LDS queue (1) or in place (0, default) in image mode without m2.
-int darts_set_connection_queue(int on)
-{
-    g_use_queue = on != 0;
     return ok();
 }
 

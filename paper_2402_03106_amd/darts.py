@@ -84,6 +84,15 @@ class _Params(C.Structure):
                 ("max_bounces", C.c_int), ("n_ris", C.c_int), ("alpha", C.c_float), ("flags", C.c_uint)]
 
 
+class _BatchItem(C.Structure):
+    _fields_ = [("scene", _Scene), ("params", _Params), ("table", C.POINTER(_Table))]
+
+
+class _BatchPlan(C.Structure):
+    _fields_ = [("order", C.c_int), ("block_threads", C.c_int), ("waves_per_cu", C.c_int),
+                ("unit_paths", C.c_int64)]
+
+
 _lib = None
 
 
@@ -105,7 +114,16 @@ def lib() -> C.CDLL:
                                                       vp, vp, vp]
         L.darts_debug_pointwise.argtypes = [C.c_int, vp, vp, i64, C.POINTER(_Medium), C.POINTER(_Table), vp]
         L.darts_set_target_waves.argtypes = [i64]
-        L.darts_set_connection_queue.argtypes = [C.c_int]
+        pp = C.POINTER(C.c_void_p)
+        L.darts_batch_default_plan.argtypes = [C.POINTER(_BatchPlan)]
+        L.darts_batch_create.argtypes = [C.POINTER(_BatchItem), C.c_int, C.POINTER(_BatchPlan), pp]
+        L.darts_batch_image_offsets.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.darts_batch_set_plan.argtypes = [vp, C.POINTER(_BatchPlan)]
+        L.darts_batch_get_plan.argtypes = [vp, C.POINTER(_BatchPlan)]
+        L.darts_batch_render.argtypes = [vp, vp, vp, vp]
+        L.darts_batch_graph_launch.argtypes = [vp, vp, vp, vp]
+        L.darts_batch_autotune.argtypes = [vp, vp, vp, C.c_int, C.POINTER(_BatchPlan), C.POINTER(C.c_double), vp]
+        L.darts_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -266,8 +284,105 @@ def debug_pointwise(fn: str, inputs: torch.Tensor, med: dict | None = None, tabl
     return out
 
 
-def set_connection_queue(on: bool):
-    _check(lib().darts_set_connection_queue(1 if on else 0))
+# --------------------------------------------------------------------------
+# Batched persistent render
+# --------------------------------------------------------------------------
+BATCH_ORDERS = {"tiles": 0, "ids": 1}
+
+
+def _plan_dict(pl: _BatchPlan) -> dict:
+    return {"order": {v: k for k, v in BATCH_ORDERS.items()}[pl.order], "block_threads": pl.block_threads,
+            "waves_per_cu": pl.waves_per_cu, "unit_paths": int(pl.unit_paths)}
+
+
+def _plan_struct(plan: dict | None) -> _BatchPlan:
+    pl = _BatchPlan()
+    _check(lib().darts_batch_default_plan(C.byref(pl)))
+    if plan:
+        if "order" in plan:
+            pl.order = BATCH_ORDERS[plan["order"]] if isinstance(plan["order"], str) else int(plan["order"])
+        for k in ("block_threads", "waves_per_cu", "unit_paths"):
+            if k in plan:
+                setattr(pl, k, int(plan[k]))
+    return pl
+
+
+class Batch:
+    """Many scenes rendered by one persistent launch (darts_batch_*).  items:
+    list of (scene dict, params dict, mode, Table or None).  The tables must
+    stay alive as long as the batch; the Batch keeps references to them."""
+
+    def __init__(self, items, plan: dict | None = None):
+        self._h = C.c_void_p()
+        self._holders = [_SceneHolder(sc) for sc, _, _, _ in items]
+        self._tables = [t for _, _, _, t in items]
+        self._tstructs = [t.c_struct() if t is not None else None for t in self._tables]
+        arr = (_BatchItem * len(items))()
+        for i, (sc, p, mode, t) in enumerate(items):
+            arr[i].scene = self._holders[i].c
+            arr[i].params = params(p, mode)
+            arr[i].table = C.pointer(self._tstructs[i]) if t is not None else None
+        self.shapes = [image_shape(sc) for sc, _, _, _ in items]
+        pl = _plan_struct(plan)
+        _check(lib().darts_batch_create(arr, len(items), C.byref(pl), C.byref(self._h)))
+        offs = (C.c_int64 * (len(items) + 1))()
+        _check(lib().darts_batch_image_offsets(self._h, offs))
+        self.offsets = [int(x) for x in offs]
+
+    @property
+    def numel(self) -> int:
+        return self.offsets[-1]
+
+    def images(self, flat: torch.Tensor):
+        """Per-scene views [n_bins, height, width] of a flat batch image."""
+        return [flat[self.offsets[i]:self.offsets[i + 1]].view(self.shapes[i]) for i in range(len(self.shapes))]
+
+    def empty(self, device="cuda"):
+        z = lambda: torch.zeros(self.numel, dtype=torch.float32, device=device)
+        return z(), z()
+
+    def _out(self, hi, lo):
+        for t in (hi, lo):
+            if t is None or t.dtype != torch.float32 or t.numel() != self.numel:
+                raise ValueError(f"batch images must be float32 with {self.numel} elements")
+        return _ptr(hi), _ptr(lo)
+
+    def render(self, hi, lo, stream=None):
+        """One launch accumulating into (hi, lo)."""
+        _check(lib().darts_batch_render(self._h, *self._out(hi, lo), _stream(stream)))
+        return hi, lo
+
+    def graph_launch(self, hi, lo, stream=None):
+        """Clear (hi, lo) and render, as one captured graph."""
+        _check(lib().darts_batch_graph_launch(self._h, *self._out(hi, lo), _stream(stream)))
+        return hi, lo
+
+    def autotune(self, hi, lo, reps: int = 2, stream=None):
+        pl, ms = _BatchPlan(), C.c_double()
+        _check(lib().darts_batch_autotune(self._h, *self._out(hi, lo), int(reps), C.byref(pl), C.byref(ms),
+                                          _stream(stream)))
+        return _plan_dict(pl), float(ms.value)
+
+    @property
+    def plan(self) -> dict:
+        pl = _BatchPlan()
+        _check(lib().darts_batch_get_plan(self._h, C.byref(pl)))
+        return _plan_dict(pl)
+
+    @plan.setter
+    def plan(self, plan: dict):
+        _check(lib().darts_batch_set_plan(self._h, C.byref(_plan_struct(plan))))
+
+    def close(self):
+        if self._h:
+            lib().darts_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def set_target_waves(n: int):

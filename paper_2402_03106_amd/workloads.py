@@ -111,6 +111,34 @@ def box_hg_grad() -> dict:
     return w
 
 
+def batched(n_media: int = 256, seed: int = 0xC3, lo_log2: int = 12, hi_log2: int = 18) -> list:
+    """Batch of independent box media for the many-configuration sweep: the
+    geometry, emitter and camera of ``box_hg`` with sigma_s ~ U[0.5, 20],
+    albedo ~ U[0.8, 0.999] (sigma_a = sigma_s (1/albedo - 1)),
+    g ~ U[-0.3, 0.9], 32x32 sensors, 128 bins over [0, 40), path budgets
+    log-uniform in [2^lo_log2, 2^hi_log2] and one Philox key per medium;
+    64x64x32 direction tables with S_max = 40.  Drawn from numpy's PCG64
+    stream of `seed`; returns a list of workload dictionaries."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_media):
+        sigma_s = float(rng.uniform(0.5, 20.0))
+        albedo = float(rng.uniform(0.8, 0.999))
+        g = float(rng.uniform(-0.3, 0.9))
+        n = int(round(2.0 ** rng.uniform(lo_log2, hi_log2)))
+        w = box_hg()
+        w["name"] = f"batched_{i}"
+        w["scene"]["medium"] = {"sigma_s": sigma_s, "sigma_a": sigma_s * (1.0 / albedo - 1.0), "g": g}
+        w["scene"]["sensor"]["width"] = 32
+        w["scene"]["sensor"]["height"] = 32
+        w["scene"]["bins"] = {"l_lo": 0.0, "l_hi": 40.0, "n_bins": 128}
+        w["params"]["n_paths"] = n
+        w["params"]["seed"] = (seed << 32) | i
+        out.append(w)
+    return out
+
+
 def with_(w: dict, **changes) -> dict:
     """Copy of a workload with params/scene entries replaced, e.g.
     ``with_(w, n_paths=4096, medium={"sigma_s": 2.0, ...})``."""

@@ -114,3 +114,40 @@ def test_paths_per_cell_counts(D):
     ids = torch.arange(5, 12) % 6
     ref = torch.bincount(ids, minlength=6).double()
     assert torch.equal(c, ref)
+
+
+def _batch_item(D, flags, table=None, n_paths=1024):
+    from paper_2402_03106_amd import workloads as W
+    w = W.batched(1, seed=1)[0]
+    h = D._SceneHolder(w["scene"])
+    it = D._BatchItem()
+    it.scene = h.c
+    p = dict(w["params"], n_paths=n_paths)
+    it.params = D.params(p, flags)
+    it.table = table
+    return it, h
+
+
+def test_batch_create_validates_before_the_device(D):
+    """darts_batch_create rejects bad requests before any device call."""
+    import ctypes as C
+    L = D.lib()
+    out = C.c_void_p()
+    arr = (D._BatchItem * 1)()
+    assert L.darts_batch_create(arr, 0, None, C.byref(out)) == D.ERR_INVALID_ARG
+    it, h = _batch_item(D, "vanilla")
+    arr[0] = it
+    assert L.darts_batch_create(arr, 1, None, C.byref(out)) == D.ERR_UNSUPPORTED
+    it, h = _batch_item(D, "darts")          # EDA needs a table
+    arr[0] = it
+    assert L.darts_batch_create(arr, 1, None, C.byref(out)) == D.ERR_INVALID_ARG
+    assert "item 0" in D.last_error()
+    it, h = _batch_item(D, "uniform")
+    arr[0] = it
+    bad = D._plan_struct({"block_threads": 96})
+    assert L.darts_batch_create(arr, 1, C.byref(bad), C.byref(out)) == D.ERR_INVALID_ARG
+    bad = D._plan_struct({"unit_paths": 8})
+    assert L.darts_batch_create(arr, 1, C.byref(bad), C.byref(out)) == D.ERR_INVALID_ARG
+    assert not out.value
+    assert L.darts_batch_render(None, None, None, None) == D.ERR_INVALID_ARG
+    assert L.darts_batch_destroy(None) == D.OK

@@ -123,7 +123,6 @@ def test_compensated_accumulation(D, oracle):
     sc, pr = w["scene"], w["params"]
     vals = D.render_paths(sc, pr, "darts", table).cpu().numpy().astype(np.float64)
     exact = np.bincount(np.arange(pr["n_paths"]) % 64, weights=vals, minlength=64)
-    D.set_connection_queue(False)
     hi, lo, _, _ = D.render_transient(sc, pr, "darts", table)
     torch.cuda.synchronize()
     tot = hi.double().cpu().numpy().ravel() + lo.double().cpu().numpy().ravel()
@@ -134,26 +133,21 @@ def test_compensated_accumulation(D, oracle):
 
 @pytest.mark.parametrize("wname,mode", [("box_hg", "darts"), ("box_hg", "uniform"), ("infinite_point", "darts"),
                                         ("box_hg_small", "eda_only")])
-def test_connection_queue_matches_direct(D, oracle, wname, mode):
-    """The image kernel that defers connections to the wave's LDS queue
-    gives the per-path sums of the direct evaluation (only the order of the
-    floating-point additions differs)."""
+def test_image_is_sum_of_path_values(D, oracle, wname, mode):
+    """The image kernel's cells are the sums of the per-path values of the
+    paths mapped to them (only the order of the floating-point additions
+    differs)."""
     w = WORKLOADS[wname]()
     table, _ = tables(D, oracle, w)
     sc, pr = w["scene"], w["params"]
     vals = D.render_paths(sc, pr, mode, table).cpu().numpy().astype(np.float64)
     nc = oracle.n_cells(sc)
     exact = np.bincount((np.arange(pr["n_paths"]) + pr["path_offset"]) % nc, weights=vals, minlength=nc)
-    out = {}
-    for queue in (True, False):
-        D.set_connection_queue(queue)
-        hi, lo, _, _ = D.render_transient(sc, pr, mode, table)
-        torch.cuda.synchronize()
-        out[queue] = (hi.double() + lo.double()).cpu().numpy().ravel()
-    D.set_connection_queue(False)
+    hi, lo, _, _ = D.render_transient(sc, pr, mode, table)
+    torch.cuda.synchronize()
+    img = (hi.double() + lo.double()).cpu().numpy().ravel()
     scale = max(np.abs(exact).max(), 1e-30)
-    assert np.max(np.abs(out[True] - exact)) <= 1e-6 * scale
-    assert np.max(np.abs(out[False] - exact)) <= 1e-6 * scale
+    assert np.max(np.abs(img - exact)) <= 1e-6 * scale
 
 
 def test_ragged_offset_and_accumulate_into(D, oracle):
