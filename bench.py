@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-mse", action="store_true", help="skip the time-to-MSE measurement")
     ap.add_argument("--no-uniform", action="store_true", help="skip the uniform-baseline throughput")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-media launch")
+    ap.add_argument("--no-response", action="store_true", help="skip the two-peak sensor-response study")
     ap.add_argument("--batched-reps", type=int, default=5, help="timed graph launches of the batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -223,6 +224,9 @@ def main():
             "infinite_point": time_to_mse(darts, torch, np, W.infinite_point(), None, 1 << 24),
         }
         print(f"[bench] time to MSE {out['time_to_mse']}", file=sys.stderr, flush=True)
+    if not a.no_response:
+        out["response"] = response_bench(darts, torch, np, W, w)
+        print(f"[bench] response {out['response']}", file=sys.stderr, flush=True)
     if not a.no_batched:
         out["batched"] = batched_bench(darts, torch, W, a.batched_reps)
         print(f"[bench] batched {out['batched']}", file=sys.stderr, flush=True)
@@ -295,6 +299,55 @@ def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4, k=16):
     for mode in ["uniform", "vanilla"]:
         if "seconds" in rep[mode] and "seconds" in rep["darts"]:
             rep[f"{mode}_over_darts_time"] = rep[mode]["seconds"] / rep["darts"]["seconds"]
+        rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
+    return rep
+
+
+def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 24, k=16, target=1e-4):
+    """Two-peak sensor response W on the box workload (one value per pixel,
+    Eq. (4)): throughput of each strategy, the fraction of full path samples
+    the sensor rejects (W = 0 at their length), and time to MSE `target`
+    (0.95-quantile normalised, variance from k independent batches,
+    extrapolated at the measured throughput)."""
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    resp = W.two_peak_response(sc["bins"])
+    R = darts.build_response(resp)
+    table = darts.build_da_tables(sc["medium"], dm)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rep = {"response": "two Gaussian peaks at L = 3.0 and 5.5 (width 0.4, heights 1 and 0.6), zero below 1e-3",
+           "target": target, "batches": k, "paths_for_variance": n_var}
+    thr, var, means = {}, {}, {}
+    for mode in ["darts", "uniform", "vanilla"]:
+        p = dict(pr, n_paths=n_thr)
+        hi, lo, _, st = darts.render_transient(sc, p, mode, table, want_stats=True, response=R)
+        torch.cuda.synchronize()
+        s = darts.stats_dict(st)
+        e0.record(stream)
+        darts.render_transient(sc, p, mode, table, hi, lo, response=R)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        thr[mode] = n_thr / (e0.elapsed_time(e1) / 1e3)
+        imgs = []
+        nb = n_var // k
+        for i in range(k):
+            pb = dict(pr, n_paths=nb, path_offset=(1 << 40) + i * nb, seed=0xEF)
+            h, l, _, _ = darts.render_transient(sc, pb, mode, table, response=R)
+            n = darts.paths_per_cell(sc, pb, mode, response=R).numpy()
+            imgs.append((h.double() + l.double()).cpu().numpy() / np.maximum(n, 1))
+        imgs = np.stack(imgs)
+        means[mode] = imgs.mean(0)
+        var[mode] = imgs.var(0, ddof=1) * nb
+        rep[mode] = {"paths_per_s": thr[mode], "samples": s["samples"], "rejected": s["rejected"],
+                     "rejected_fraction": s["rejected"] / max(s["samples"], 1)}
+    q95 = float(np.quantile(means["darts"], 0.95))
+    rep["q95"] = q95
+    for mode in var:
+        mse_n = float(np.mean(var[mode])) / q95 ** 2
+        rep[mode]["mse_times_paths"] = mse_n
+        rep[mode]["seconds_to_target"] = mse_n / target / thr[mode]
+    for mode in ["uniform", "vanilla"]:
+        rep[f"{mode}_over_darts_time"] = rep[mode]["seconds_to_target"] / rep["darts"]["seconds_to_target"]
         rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
     return rep
 

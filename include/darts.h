@@ -76,6 +76,14 @@ typedef struct { int kind; float lo[3], hi[3]; } darts_geometry;
  * measured from the sensor and including the emitter's start offset. */
 typedef struct { float l_lo, l_hi; int n_bins; } darts_bins;
 
+/* Sensor response W (Eq. (4)): NULL for a time-resolved image (W the
+ * indicator of each bin), or a device table built by darts_build_response
+ * holding a piecewise-constant W over the scene's bins.  With a response the
+ * image has one value per pixel, [height][width], estimating the integral of
+ * W(path length) times the path contribution; path id p maps to pixel
+ * p mod (height * width) and, in the DARTS family, draws its target bin with
+ * probability proportional to W (Section V-B: sampling the path length where
+ * the sensor responds avoids rejected samples). */
 typedef struct {
     darts_medium medium;
     darts_geometry geom;
@@ -83,6 +91,7 @@ typedef struct {
     int n_emitters;                  /* 1 .. DARTS_MAX_EMITTERS          */
     darts_sensor sensor;
     darts_bins bins;
+    const float *response_dev;       /* NULL or a table of bins.n_bins segments */
 } darts_scene;
 
 /* Elliptical-DA direction table (Section V-A): n_cs cells of C/S over [0,1),
@@ -124,11 +133,16 @@ typedef struct {
  * a non-zero contribution; early exits (nothing reachable inside the gate);
  * walks that left the medium; RIS steps with no valid candidate; EDA-branch
  * direction samples; paths stopped at max_bounces; paths that contributed
- * nothing; early exits already at the path's first vertex. */
+ * nothing; early exits already at the path's first vertex; full path samples
+ * (sensor-to-emitter paths a connection produced) and those the sensor
+ * weights with zero (length outside the bins or W = 0: the rejected samples
+ * of Section V-B; vanilla connects at every vertex whatever the length, the
+ * DARTS family only inside the target bin). */
 enum {
     DARTS_ST_PATHS = 0, DARTS_ST_VERTICES, DARTS_ST_CONNECTIONS, DARTS_ST_EARLY_EXIT,
     DARTS_ST_MEDIUM_EXIT, DARTS_ST_RIS_ALL_INVALID, DARTS_ST_EDA_BRANCH,
-    DARTS_ST_TRUNCATED, DARTS_ST_ZERO_PATHS, DARTS_ST_SETUP_EXIT, DARTS_ST_COUNT = 16
+    DARTS_ST_TRUNCATED, DARTS_ST_ZERO_PATHS, DARTS_ST_SETUP_EXIT, DARTS_ST_SAMPLES,
+    DARTS_ST_REJECTED, DARTS_ST_COUNT = 16
 };
 
 /* Size in bytes of the cdf array of a table of these dimensions.
@@ -148,13 +162,25 @@ int darts_table_bytes(const darts_table_dims *dims, size_t *bytes);
 int darts_build_da_tables(const darts_medium *medium, const darts_table_dims *dims,
                           float *cdf_dev, void *stream);
 
+/* Size in bytes of a sensor-response table for n_bins segments
+ * ((2 n_bins + 1) floats).  INVALID_ARG for n_bins < 1. */
+int darts_response_bytes(int n_bins, size_t *bytes);
+
+/* Build a sensor-response table from W (host float[n_bins], W >= 0, finite,
+ * not all zero): float cdf[n_bins + 1] (cdf[0] = 0, cdf[k+1] the running sum
+ * of W_j / sum W accumulated in double and rounded to float, cdf[n_bins] = 1)
+ * followed by float W[n_bins].  response_dev: device memory of
+ * darts_response_bytes; the copy completes before the call returns. */
+int darts_build_response(const float *w_host, int n_bins, float *response_dev, void *stream);
+
 /* Render: accumulate raw path contributions into the time-resolved image.
  *   Path id p = path_offset + i (i < n_paths) belongs to cell
  *   c = p mod (n_bins * height * width); its pixel is c mod (height*width) and,
  *   except in vanilla mode, its target interval is bin c / (height*width).
  *   DARTS family: each path adds its estimate to its own cell; vanilla: each
  *   path adds to every bin of its pixel its length reaches.
- *   image_hi_dev, image_lo_dev: device float[n_bins][height][width],
+ *   image_hi_dev, image_lo_dev: device float[n_bins][height][width]
+ *     ([height][width] with a sensor response),
  *     accumulate-into; hi + lo is a compensated (two-float) sum.
  *   image_m2_dev (nullable): accumulate-into sums of squared per-path (DARTS
  *     family) or per-path-per-bin (vanilla) contributions.
@@ -295,7 +321,7 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
 const char *darts_last_error(void);
 
 /* ABI version of this header (incremented on incompatible change). */
-#define DARTS_ABI_VERSION 1
+#define DARTS_ABI_VERSION 2
 int darts_abi_version(void);
 
 #ifdef __cplusplus

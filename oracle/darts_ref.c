@@ -480,19 +480,51 @@ typedef struct {
     int alive;
 } path_state;
 
+/* Segment k of a piecewise-constant sensor response drawn by inverse
+ * transform from its float CDF (cdf[0] = 0, cdf[k+1] = running double sum of
+ * W_j / sum W rounded to float, cdf[n] = 1): the largest k with cdf[k] <= u.
+ * *weight = W_k / (cdf[k+1] - cdf[k]), the response over the probability. */
+static int64_t response_segment(int n, const double *W, double u, double *weight)
+{
+    double tot = 0.0;
+    for (int k = 0; k < n; ++k) tot += W[k];
+    double run = 0.0;
+    float lo = 0.0f;
+    for (int k = 0; k < n; ++k) {
+        run += W[k];
+        float hi = (k == n - 1) ? 1.0f : (float)(run / tot);
+        if (u < (double)hi && (double)lo <= u) {
+            *weight = W[k] / ((double)hi - (double)lo);
+            return k;
+        }
+        lo = hi;
+    }
+    *weight = 0.0;   /* not reached: u < 1 = cdf[n] */
+    return n - 1;
+}
+
 /* Path set-up (Section III and Section V-A): stratified target interval,
  * camera ray, emitter choice, entry into the medium. */
 static void setup_path(const ref_scene *sc, const ref_params *pr, uint64_t p, path_state *ps, int vanilla)
 {
     const ref_sensor *sn = &sc->sensor;
+    const int response = (pr->flags & REF_RESPONSE) != 0;
     int64_t npix = (int64_t)sn->width * sn->height;
-    int64_t ncells = npix * sc->bins.n_bins;
+    int64_t ncells = response ? npix : npix * sc->bins.n_bins;
     ps->cell = (int64_t)(p % (uint64_t)ncells);
     ps->pixel = ps->cell % npix;
     int64_t b = ps->cell / npix;
     uint32_t r[4];
     draw(pr->seed, p, 0u, 0, r);
     double u0 = ref_u01(r[0]), u1 = ref_u01(r[1]), u2 = ref_u01(r[2]);
+    double resp_weight = 1.0;
+    if (response && !vanilla) {
+        /* target segment drawn with probability proportional to W (Eq. (4):
+         * the estimator of the W-weighted integral picks the interval to
+         * sample and divides by its probability) */
+        b = response_segment(sc->bins.n_bins, pr->response, ref_u01(r[3]), &resp_weight);
+        if (pr->mutation == REF_MUT_RESPONSE_UNWEIGHTED) resp_weight = 1.0;
+    }
     double pos[3], w[3];
     if (sn->kind == 1) {
         int px = (int)(ps->pixel % sn->width), py = (int)(ps->pixel / sn->width);
@@ -511,7 +543,7 @@ static void setup_path(const ref_scene *sc, const ref_params *pr, uint64_t p, pa
     int j = (int)floor(u2 * sc->n_emitters);
     if (j > sc->n_emitters - 1) j = sc->n_emitters - 1;
     ps->em = &sc->emitters[j];
-    ps->J = (double)sc->n_emitters;
+    ps->J = (double)sc->n_emitters * resp_weight;
     double delta = (sc->bins.l_hi - sc->bins.l_lo) / sc->bins.n_bins;
     if (vanilla) {
         ps->G_lo = sc->bins.l_lo - ps->em->start;
@@ -536,9 +568,10 @@ typedef struct {
 /* Generalised shadow connection through a control vertex on the current
  * ray (Section V-B, case I; Eq. (21)-(22)).  Returns the contribution. */
 static double connect_elliptical(const ref_scene *sc, const ref_params *pr, const path_state *ps,
-                                 double dm, double u4, double *t_out, double *rin_out, double *mu_c_out)
+                                 double dm, double u4, double *t_out, double *rin_out, double *mu_c_out,
+                                 int *reached)
 {
-    *t_out = 0.0; *rin_out = 0.0; *mu_c_out = 0.0;
+    *t_out = 0.0; *rin_out = 0.0; *mu_c_out = 0.0; *reached = 0;
     const ref_medium *m = &sc->medium;
     double st = m->sigma_s + m->sigma_a;
     double de[3];
@@ -557,6 +590,7 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
     }
     double S_lo = fmax(R_lo, C), S_hi = fmin(R_hi, S_exit);
     if (!(S_lo < S_hi)) return 0.0;
+    *reached = 1;
     double width = S_hi - S_lo, S, pS;
     if (pr->flags & REF_ELL_TEXP) {
         S = S_lo + ref_texp_sample(u4, st, width);
@@ -624,7 +658,11 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
         uint32_t r1[4];
         draw(pr->seed, p, (uint32_t)k, 1, r1);
         double tc, rin, muc;
-        double c = connect_elliptical(sc, pr, &ps, dm, ref_u01(r1[0]), &tc, &rin, &muc);
+        int reached;
+        double c = connect_elliptical(sc, pr, &ps, dm, ref_u01(r1[0]), &tc, &rin, &muc, &reached);
+        /* a full path sample exists when a control vertex can close the
+         * path; its length lies in the target segment, where W > 0 */
+        if (reached) S->st[REF_ST_SAMPLES]++;
         if (c != 0.0) {
             S->st[REF_ST_CONNECTIONS]++;
             if (grad) {
@@ -689,6 +727,7 @@ static void trace_vanilla(const ref_scene *sc, const ref_params *pr, uint64_t p,
     double Ie = ps.em->power / (4.0 * PI);
     double dm = ps.dm0;
     int any = 0;
+    const int response = (pr->flags & REF_RESPONSE) != 0;
     for (int k = 0; k <= pr->max_bounces; ++k) {
         S->st[REF_ST_VERTICES]++;
         if (k >= 1) {
@@ -699,11 +738,20 @@ static void trace_vanilla(const ref_scene *sc, const ref_params *pr, uint64_t p,
             double r_in = fmin(r, ref_box_exit(&sc->geom, ps.x, wc));
             double L = ps.Le + r + ps.em->start;       /* arrival time */
             int bin = (int)floor((L - sc->bins.l_lo) / delta);
+            S->st[REF_ST_SAMPLES]++;
             if (L >= sc->bins.l_lo && bin >= 0 && bin < sc->bins.n_bins) {
-                double v = ps.beta * ps.J * ref_hg_pdf(dot3(ps.w, wc), m->g) * exp(-st * r_in) * Ie / (r * r);
-                scratch_add(bs, bin, v);
-                S->st[REF_ST_CONNECTIONS]++;
-                any = 1;
+                /* sensor weight: the bin indicator, or W of the length */
+                double wsens = response ? pr->response[bin] : 1.0;
+                double v = wsens * ps.beta * ps.J * ref_hg_pdf(dot3(ps.w, wc), m->g) * exp(-st * r_in) * Ie / (r * r);
+                if (wsens > 0.0) {
+                    scratch_add(bs, response ? 0 : bin, v);
+                    S->st[REF_ST_CONNECTIONS]++;
+                    any = 1;
+                } else {
+                    S->st[REF_ST_REJECTED]++;
+                }
+            } else {
+                S->st[REF_ST_REJECTED]++;
             }
         }
         if (k == pr->max_bounces) { S->st[REF_ST_TRUNCATED]++; break; }
@@ -801,6 +849,16 @@ static int check_args(const ref_scene *sc, const ref_params *pr)
     if (sc->sensor.width <= 0 || sc->sensor.height <= 0) return -1;
     if (pr->max_bounces <= 0 || pr->n_ris < 1 || pr->n_ris > 8) return -1;
     unsigned f = pr->flags;
+    if (f & REF_RESPONSE) {
+        if (!pr->response || (f & REF_FORWARD)) return -1;
+        double tot = 0.0;
+        for (int k = 0; k < sc->bins.n_bins; ++k) {
+            if (!(pr->response[k] >= 0.0) || isinf(pr->response[k])) return -1;
+            tot += pr->response[k];
+        }
+        if (!(tot > 0.0)) return -1;
+        f &= ~REF_RESPONSE;
+    }
     if (f & REF_FORWARD) { if (sc->sensor.kind != 0) return -1; return 0; }
     if (f & REF_DIRECT_REUSE) return 0;
     if (((f & REF_ELL_TEXP) != 0) == ((f & REF_ELL_UNIFORM) != 0)) return -1;
@@ -892,7 +950,7 @@ int ref_render_transient(const ref_scene *sc, const ref_params *pr,
     int nt = nthreads_eff(n_threads);
     int64_t npix = (int64_t)sc->sensor.width * sc->sensor.height;
     int B = sc->bins.n_bins;
-    int64_t ncells = npix * B;
+    int64_t ncells = (pr->flags & REF_RESPONSE) ? npix : npix * B;   /* response: one value per pixel */
     int64_t n = (int64_t)pr->n_paths;
     memset(image, 0, sizeof(double) * (size_t)ncells);
     if (m2) memset(m2, 0, sizeof(double) * (size_t)ncells);

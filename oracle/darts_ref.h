@@ -69,6 +69,8 @@ typedef struct { int n_cs, n_s, n_cos; double s_max; } ref_table_dims;
 #define REF_ELL_UNIFORM   0x8u  /* uniform S (temporally uniform baseline)    */
 #define REF_DIRECT_REUSE  0x10u /* vanilla: shadow connection + length reuse  */
 #define REF_FORWARD       0x20u /* analog walk from the emitter (oracle only) */
+#define REF_RESPONSE      0x40u /* general sensor response W (Eq. (4)); the
+                                   image is per pixel, see `response`        */
 
 typedef struct {
     uint64_t n_paths, path_offset, seed;
@@ -76,6 +78,14 @@ typedef struct {
     double alpha;
     unsigned flags;
     int mutation; /* 0 in normal use; see REF_MUT_* (planted mistakes for tests) */
+    /* With REF_RESPONSE: W(L) piecewise constant on the n_bins segments of the
+     * scene's bins, response[k] >= 0, not all zero.  The DARTS family draws
+     * each path's target segment with probability proportional to W (from
+     * a float CDF: cdf[0] = 0, cdf[k+1] = sum_{j<=k} W_j / sum W accumulated
+     * in double and rounded, cdf[n_bins] = 1) and weights it by W_k / (cdf[k+1]
+     * - cdf[k]); vanilla weights every connection by W of its length.  Paths
+     * map to pixels (id mod pixels) and the image is [height][width]. */
+    const double *response;
 } ref_params;
 
 /* Planted mistakes. They exist so the test-suite can show that its pins
@@ -87,12 +97,18 @@ typedef struct {
 #define REF_MUT_NO_EMITTER_TRANS  4 /* drop transmittance control->emitter    */
 #define REF_MUT_HG_SAMPLE_FLIP    5 /* HG sample mirrored (cos -> -cos)       */
 #define REF_MUT_GRAD_NO_COUNT     6 /* gradient: drop n / sigma_s              */
+#define REF_MUT_RESPONSE_UNWEIGHTED 7 /* response: drop W_k / P(segment k)     */
 
 /* Statistics, uint64 counters. */
 enum {
     REF_ST_PATHS = 0, REF_ST_VERTICES, REF_ST_CONNECTIONS, REF_ST_EARLY_EXIT,
     REF_ST_MEDIUM_EXIT, REF_ST_RIS_ALL_INVALID, REF_ST_EDA_BRANCH,
     REF_ST_TRUNCATED, REF_ST_ZERO_PATHS, REF_ST_RIS_INVALID_CANDS,
+    /* full path samples (sensor-to-emitter paths produced by a connection)
+     * and those the sensor weights with zero (length outside the bins, or
+     * W = 0): vanilla connects at every vertex whatever its length; the
+     * DARTS family only produces samples inside the target segment */
+    REF_ST_SAMPLES, REF_ST_REJECTED,
     REF_ST_COUNT = 16
 };
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libdarts_ref.so")
 
 # Strategy bits (same numeric values as the GPU library; declared separately).
 RIS_DIST, EDA_DIR, ELL_TEXP, ELL_UNIFORM, DIRECT_REUSE, FORWARD = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+RESPONSE = 0x40
 MODES = {
     "darts": RIS_DIST | EDA_DIR | ELL_TEXP,
     "uniform": ELL_UNIFORM,
@@ -30,9 +31,9 @@ MODES = {
     "forward": FORWARD,
 }
 MUT = {"none": 0, "printed_jacobian": 1, "ris_no_mean": 2, "eda_pdf_unscaled": 3,
-       "no_emitter_trans": 4, "hg_sample_flip": 5, "grad_no_count": 6}
+       "no_emitter_trans": 4, "hg_sample_flip": 5, "grad_no_count": 6, "response_unweighted": 7}
 STATS = ["paths", "vertices", "connections", "early_exit", "medium_exit", "ris_all_invalid",
-         "eda_branch", "truncated", "zero_paths", "ris_invalid_cands"]
+         "eda_branch", "truncated", "zero_paths", "ris_invalid_cands", "samples", "rejected"]
 
 
 def build(force: bool = True) -> str:
@@ -78,7 +79,7 @@ class _Dims(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("n_paths", C.c_uint64), ("path_offset", C.c_uint64), ("seed", C.c_uint64),
                 ("max_bounces", C.c_int), ("n_ris", C.c_int), ("alpha", C.c_double),
-                ("flags", C.c_uint), ("mutation", C.c_int)]
+                ("flags", C.c_uint), ("mutation", C.c_int), ("response", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -184,11 +185,17 @@ class _SceneHolder:
                         _Bins(float(b["l_lo"]), float(b["l_hi"]), int(b["n_bins"])))
 
 
-def params(p: dict, mode: str | None = None, mutation: str = "none") -> _Params:
+def params(p: dict, mode: str | None = None, mutation: str = "none", response=None) -> _Params:
     flags = MODES[mode] if mode is not None else int(p["flags"])
-    return _Params(int(p["n_paths"]), int(p.get("path_offset", 0)), int(p["seed"]),
-                   int(p["max_bounces"]), int(p.get("n_ris", 8)), float(p.get("alpha", 0.5)),
-                   flags, MUT[mutation])
+    pr = _Params(int(p["n_paths"]), int(p.get("path_offset", 0)), int(p["seed"]),
+                 int(p["max_bounces"]), int(p.get("n_ris", 8)), float(p.get("alpha", 0.5)),
+                 flags, MUT[mutation], None)
+    if response is not None:
+        arr = np.ascontiguousarray(response, np.float64)
+        pr.flags |= RESPONSE
+        pr.response = arr.ctypes.data_as(C.POINTER(C.c_double))
+        pr._keep = arr
+    return pr
 
 
 def n_cells(sc: dict) -> int:
@@ -319,6 +326,60 @@ def render_gradient(sc: dict, p: dict, mode: str, grad_image, table=None, dims_=
     if rc:
         raise ValueError(f"ref_render_gradient failed: {rc}")
     return out
+
+
+def render_response(sc: dict, p: dict, mode: str, response, table=None, dims_: dict | None = None,
+                    n_threads: int = 0, mutation: str = "none"):
+    """Sensor-response render (Eq. (4) with a piecewise-constant W over the
+    scene's bins): raw per-pixel sums (image, m2) of shape [H, W] and stats."""
+    holder = _SceneHolder(sc)
+    pr = params(p, mode, mutation, response)
+    s = sc["sensor"]
+    shape = (int(s.get("height", 1)), int(s.get("width", 1)))
+    img = np.zeros(shape, np.float64)
+    m2 = np.zeros(shape, np.float64)
+    st = np.zeros(16, np.uint64)
+    cdf = None if table is None else np.ascontiguousarray(table, np.float32)
+    dptr = C.byref(dims(dims_)) if (cdf is not None) else None
+    cptr = cdf.ctypes.data_as(C.POINTER(C.c_float)) if cdf is not None else None
+    rc = lib().ref_render_transient(C.byref(holder.c), C.byref(pr), dptr, cptr,
+                                    img.ctypes.data_as(C.POINTER(C.c_double)),
+                                    m2.ctypes.data_as(C.POINTER(C.c_double)),
+                                    st.ctypes.data_as(C.POINTER(C.c_uint64)), int(n_threads))
+    if rc:
+        raise ValueError(f"ref_render_transient (response) failed: {rc}")
+    return img, m2, {k: int(st[i]) for i, k in enumerate(STATS)}
+
+
+def render_response_paths(sc: dict, p: dict, mode: str, response, table=None, dims_: dict | None = None,
+                          n_threads: int = 0):
+    """Per-path values and pixels of a sensor-response render (DARTS family)."""
+    holder = _SceneHolder(sc)
+    pr = params(p, mode, "none", response)
+    n = int(p["n_paths"])
+    val = np.zeros(n, np.float64)
+    cell = np.zeros(n, np.int64)
+    cdf = None if table is None else np.ascontiguousarray(table, np.float32)
+    dptr = C.byref(dims(dims_)) if (cdf is not None) else None
+    cptr = cdf.ctypes.data_as(C.POINTER(C.c_float)) if cdf is not None else None
+    rc = lib().ref_render_paths(C.byref(holder.c), C.byref(pr), dptr, cptr,
+                                val.ctypes.data_as(C.POINTER(C.c_double)),
+                                cell.ctypes.data_as(C.POINTER(C.c_int64)), int(n_threads))
+    if rc:
+        raise ValueError(f"ref_render_paths (response) failed: {rc}")
+    return val, cell
+
+
+def paths_per_pixel(sc: dict, p: dict) -> np.ndarray:
+    """Paths per pixel of a sensor-response render (path id i -> pixel
+    i mod pixels), shape [H, W]."""
+    s = sc["sensor"]
+    h, w = int(s.get("height", 1)), int(s.get("width", 1))
+    npix = h * w
+    n, off = int(p["n_paths"]), int(p.get("path_offset", 0))
+    first = (np.arange(npix) - off) % npix
+    cnt = np.where(first < n, (n - 1 - first) // npix + 1, 0).astype(np.float64)
+    return cnt.reshape(h, w)
 
 
 def paths_per_cell(sc: dict, p: dict, mode: str) -> np.ndarray:

@@ -68,6 +68,8 @@ struct KParams {
     float alpha;
     unsigned flags;
     int64_t npix, ncells;
+    // sensor response (null: time-resolved image): cdf[n_bins + 1], W[n_bins]
+    const float *resp_cdf, *resp_w;
     // work decomposition: the launch covers path ids [q0*ncells + r0, q1*ncells + r1);
     // cell c holds repetitions m in [q0 + (c < r0), q1 + (c < r1)); waves own
     // tiles of 64 cells and chunks of chunk_reps repetitions
@@ -174,6 +176,20 @@ __device__ bool setup_path(const KParams &P, U4 r, int bin, int px, int py, Path
     s.acc = 0.f;
     s.L_med = 0.f;
     s.dlog_g = 0.f;
+    if (P.resp_cdf && !vanilla) {
+        // target segment drawn with probability proportional to W, the path
+        // weighted by W_k over that probability (Eq. (4))
+        const float u3 = u01(r.w);
+        int lo = 0, hi = P.n_bins;
+        float c_lo = 0.f, c_hi = 1.f;
+        while (hi - lo > 1) {   // largest k with cdf[k] <= u3
+            const int mid = (lo + hi) >> 1;
+            const float v = P.resp_cdf[mid];
+            if (v <= u3) { lo = mid; c_lo = v; } else { hi = mid; c_hi = v; }
+        }
+        bin = lo;
+        s.em_scale *= P.resp_w[lo] / (c_hi - c_lo);
+    }
     if (vanilla) {
         s.G_lo = P.l_lo - start;
         s.G_hi = P.l_hi - start;
@@ -270,10 +286,12 @@ __device__ __forceinline__ float connect_eval(const KParams &P, const Conn &q, f
 
 // Direct connection (range + contribution); dlog (if not null) receives the
 // derivative of the log path throughput w.r.t. (sigma_s, sigma_a, g).
-__device__ float connect(const KParams &P, const PathState &s, float u4, float *dlog)
+template <class ST>
+__device__ float connect(const KParams &P, const PathState &s, float u4, float *dlog, ST &st)
 {
     Conn q;
     if (!connect_range(P, s, q.S_lo, q.S_hi)) return 0.f;
+    st.inc(DARTS_ST_SAMPLES);   // a full path sample, its length inside the target bin
     q.x = s.x; q.w = s.w; q.xe = s.xe; q.C = s.C; q.scale = s.beta * s.em_scale; q.u = u4;
     float mu_c, t, r_in;
     const float c = connect_eval(P, q, mu_c, t, r_in);
@@ -316,7 +334,7 @@ __device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &
     const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
     {
         float dl[3];
-        const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD ? dl : nullptr);
+        const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD ? dl : nullptr, st);
         if (c != 0.f) {
             st.inc(DARTS_ST_CONNECTIONS);
             s.acc += c;
@@ -396,13 +414,20 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
         // total length with the emitter's start offset: G_lo = l_lo - start
         const float L = s.Le + r + (P.l_lo - s.G_lo);
         const int bin = (int)floorf((L - P.l_lo) / P.delta);
-        if (L >= P.l_lo && bin >= 0 && bin < P.n_bins) {
-            const float v = s.beta * s.em_scale * hg_pdf(dot(s.w, wc), m.g) * fast_exp(-m.sigma_t * r_in) * ir * ir;
-            const int64_t cell = (int64_t)bin * P.npix + pixel;
+        st.inc(DARTS_ST_SAMPLES);
+        // sensor weight: the indicator of the bin, or W of the length
+        const bool in_range = L >= P.l_lo && bin >= 0 && bin < P.n_bins;
+        const float wsens = !in_range ? 0.f : (P.resp_w ? P.resp_w[bin] : 1.f);
+        if (wsens > 0.f) {
+            const float v = wsens * s.beta * s.em_scale * hg_pdf(dot(s.w, wc), m.g) *
+                            fast_exp(-m.sigma_t * r_in) * ir * ir;
+            const int64_t cell = P.resp_w ? pixel : (int64_t)bin * P.npix + pixel;
             add_compensated(P.hi, P.lo, cell, v, 0.f);
             if (P.m2) unsafeAtomicAdd(P.m2 + cell, v * v);
             st.inc(DARTS_ST_CONNECTIONS);
             s.acc += v;
+        } else {
+            st.inc(DARTS_ST_REJECTED);
         }
     }
     if (s.k == P.max_bounces) { st.inc(DARTS_ST_TRUNCATED); return false; }
@@ -621,7 +646,7 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
     }
     if (STATS) {
 #pragma unroll
-        for (int i = 0; i < DARTS_ST_SETUP_EXIT + 1; ++i) {
+        for (int i = 0; i < DARTS_ST_REJECTED + 1; ++i) {
             uint32_t v = st.v[i];
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
             if (lane == 0 && v) atomicAdd(P.stats + i, (unsigned long long)v);
@@ -1045,6 +1070,13 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     P.flags = f;
     P.npix = (int64_t)sn.width * sn.height;
     P.ncells = P.npix * sc->bins.n_bins;
+    P.resp_cdf = P.resp_w = nullptr;
+    if (sc->response_dev) {
+        // one value per pixel; table = cdf[n_bins + 1] then W[n_bins]
+        P.ncells = P.npix;
+        P.resp_cdf = sc->response_dev;
+        P.resp_w = sc->response_dev + sc->bins.n_bins + 1;
+    }
     if (P.ncells > ((int64_t)1 << 40)) return fail(DARTS_ERR_INVALID_ARG, "image too large");
     const uint64_t nc = (uint64_t)P.ncells;
     if (pr->path_offset > UINT64_MAX - pr->n_paths) return fail(DARTS_ERR_INVALID_ARG, "path id range overflows");
@@ -1274,6 +1306,39 @@ int darts_table_bytes(const darts_table_dims *dims, size_t *bytes)
     if (int rc = check_dims(dims)) return rc;
     if (!bytes) return fail(DARTS_ERR_INVALID_ARG, "bytes is null");
     *bytes = (size_t)dims->n_cs * dims->n_s * (dims->n_cos + 1) * sizeof(float);
+    return ok();
+}
+
+int darts_response_bytes(int n_bins, size_t *bytes)
+{
+    if (n_bins < 1) return fail(DARTS_ERR_INVALID_ARG, "n_bins must be >= 1");
+    if (!bytes) return fail(DARTS_ERR_INVALID_ARG, "bytes is null");
+    *bytes = (size_t)(2 * (int64_t)n_bins + 1) * sizeof(float);
+    return ok();
+}
+
+int darts_build_response(const float *w_host, int n_bins, float *response_dev, void *stream)
+{
+    if (n_bins < 1 || !w_host || !response_dev) return fail(DARTS_ERR_INVALID_ARG, "bad response arguments");
+    double tot = 0.0;
+    for (int k = 0; k < n_bins; ++k) {
+        if (!(w_host[k] >= 0.f) || !std::isfinite(w_host[k]))
+            return fail(DARTS_ERR_INVALID_ARG, "response W[%d] must be finite and >= 0", k);
+        tot += w_host[k];
+    }
+    if (!(tot > 0.0)) return fail(DARTS_ERR_INVALID_ARG, "response W is all zero");
+    std::vector<float> h((size_t)(2 * n_bins + 1));
+    double run = 0.0;
+    h[0] = 0.f;
+    for (int k = 0; k < n_bins; ++k) {
+        run += w_host[k];
+        h[(size_t)k + 1] = k == n_bins - 1 ? 1.f : (float)(run / tot);
+        h[(size_t)n_bins + 1 + k] = w_host[k];
+    }
+    if (hipMemcpyAsync(response_dev, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice,
+                       (hipStream_t)stream) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return fail(DARTS_ERR_DEVICE, "copying the response table failed");
     return ok();
 }
 

@@ -31,7 +31,7 @@ MODES = {
 }
 MAX_EMITTERS = 8
 ST_NAMES = ["paths", "vertices", "connections", "early_exit", "medium_exit", "ris_all_invalid",
-            "eda_branch", "truncated", "zero_paths", "setup_exit"]
+            "eda_branch", "truncated", "zero_paths", "setup_exit", "samples", "rejected"]
 ST_COUNT = 16
 PW_IN, PW_OUT = 16, 8
 PW = {name: i for i, name in enumerate(
@@ -68,7 +68,7 @@ class _Bins(C.Structure):
 
 class _Scene(C.Structure):
     _fields_ = [("medium", _Medium), ("geom", _Geometry), ("emitters", C.POINTER(_Emitter)),
-                ("n_emitters", C.c_int), ("sensor", _Sensor), ("bins", _Bins)]
+                ("n_emitters", C.c_int), ("sensor", _Sensor), ("bins", _Bins), ("response_dev", C.c_void_p)]
 
 
 class _Dims(C.Structure):
@@ -114,6 +114,8 @@ def lib() -> C.CDLL:
                                                       vp, vp, vp]
         L.darts_debug_pointwise.argtypes = [C.c_int, vp, vp, i64, C.POINTER(_Medium), C.POINTER(_Table), vp]
         L.darts_set_target_waves.argtypes = [i64]
+        L.darts_response_bytes.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
+        L.darts_build_response.argtypes = [C.POINTER(C.c_float), C.c_int, vp, vp]
         pp = C.POINTER(C.c_void_p)
         L.darts_batch_default_plan.argtypes = [C.POINTER(_BatchPlan)]
         L.darts_batch_create.argtypes = [C.POINTER(_BatchItem), C.c_int, C.POINTER(_BatchPlan), pp]
@@ -166,7 +168,7 @@ def dims(d: dict) -> _Dims:
 
 
 class _SceneHolder:
-    def __init__(self, sc: dict):
+    def __init__(self, sc: dict, response=None):
         ems = sc["emitters"]
         self.em = (_Emitter * len(ems))(*[_Emitter(_f3(e["pos"]), float(e.get("start", 0.0)),
                                                    float(e.get("power", 1.0))) for e in ems])
@@ -177,7 +179,10 @@ class _SceneHolder:
                         _Sensor(int(s["kind"]), _f3(s["origin"]), _f3(s.get("dir", (0, 0, -1))),
                                 _f3(s.get("du", (0, 0, 0))), _f3(s.get("dv", (0, 0, 0))),
                                 int(s.get("width", 1)), int(s.get("height", 1))),
-                        _Bins(float(b["l_lo"]), float(b["l_hi"]), int(b["n_bins"])))
+                        _Bins(float(b["l_lo"]), float(b["l_hi"]), int(b["n_bins"])),
+                        C.c_void_p(response.table.data_ptr()) if response is not None else None)
+        if response is not None and response.n_bins != int(b["n_bins"]):
+            raise ValueError("the response table has a different number of segments than the scene's bins")
 
 
 def params(p: dict, mode) -> _Params:
@@ -186,9 +191,37 @@ def params(p: dict, mode) -> _Params:
                    int(p.get("n_ris", 8)), float(p.get("alpha", 0.5)), flags)
 
 
-def image_shape(sc: dict):
+def image_shape(sc: dict, response=None):
+    """[n_bins, H, W], or [H, W] with a sensor response."""
     s = sc["sensor"]
+    if response is not None:
+        return (int(s.get("height", 1)), int(s.get("width", 1)))
     return (int(sc["bins"]["n_bins"]), int(s.get("height", 1)), int(s.get("width", 1)))
+
+
+@dataclass
+class Response:
+    """A built sensor-response table (device float[2 n_bins + 1]) and the W
+    values it holds."""
+    table: torch.Tensor
+    w: tuple
+
+    @property
+    def n_bins(self) -> int:
+        return len(self.w)
+
+
+def build_response(w, stream=None, device="cuda") -> Response:
+    """Device table of a piecewise-constant sensor response W over the
+    scene's bins (darts_build_response)."""
+    wf = [float(x) for x in w]
+    n = len(wf)
+    nbytes = C.c_size_t()
+    _check(lib().darts_response_bytes(n, C.byref(nbytes)))
+    out = torch.empty(int(nbytes.value) // 4, dtype=torch.float32, device=device)
+    arr = (C.c_float * n)(*wf)
+    _check(lib().darts_build_response(arr, n, _ptr(out), _stream(stream)))
+    return Response(out, tuple(C.c_float(x).value for x in wf))
 
 
 # --------------------------------------------------------------------------
@@ -229,10 +262,11 @@ def build_da_tables(med: dict, d: dict, out: torch.Tensor | None = None, stream=
 # --------------------------------------------------------------------------
 def render_transient(sc: dict, p: dict, mode, table: Table | None = None, image_hi=None, image_lo=None,
                      image_m2=None, stats=None, want_m2: bool = False, want_stats: bool = False,
-                     stream=None, device="cuda"):
+                     stream=None, device="cuda", response: Response | None = None):
     """Accumulate raw sums into (image_hi, image_lo[, image_m2]); allocates
-    zeroed outputs when none are given.  Returns (hi, lo, m2, stats)."""
-    shape = image_shape(sc)
+    zeroed outputs when none are given.  Returns (hi, lo, m2, stats).  With a
+    sensor response the images are per pixel [H, W]."""
+    shape = image_shape(sc, response)
     if image_hi is None:
         image_hi = torch.zeros(shape, dtype=torch.float32, device=device)
     if image_lo is None:
@@ -244,28 +278,29 @@ def render_transient(sc: dict, p: dict, mode, table: Table | None = None, image_
     for t in (image_hi, image_lo, image_m2):
         if t is not None and (tuple(t.shape) != shape or t.dtype != torch.float32):
             raise ValueError(f"image tensors must be float32 {shape}")
-    h = _SceneHolder(sc)
+    h = _SceneHolder(sc, response)
     tb = C.byref(table.c_struct()) if table is not None else None
     _check(lib().darts_render_transient(C.byref(h.c), C.byref(params(p, mode)), tb, _ptr(image_hi),
                                         _ptr(image_lo), _ptr(image_m2), _ptr(stats), _stream(stream)))
     return image_hi, image_lo, image_m2, stats
 
 
-def render_paths(sc: dict, p: dict, mode, table: Table | None = None, out=None, stream=None, device="cuda"):
+def render_paths(sc: dict, p: dict, mode, table: Table | None = None, out=None, stream=None, device="cuda",
+                 response: Response | None = None):
     n = int(p["n_paths"])
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=device)
-    h = _SceneHolder(sc)
+    h = _SceneHolder(sc, response)
     tb = C.byref(table.c_struct()) if table is not None else None
     _check(lib().darts_render_paths(C.byref(h.c), C.byref(params(p, mode)), tb, _ptr(out), _stream(stream)))
     return out
 
 
 def render_transient_backward(sc: dict, p: dict, mode, table: Table | None, grad_image: torch.Tensor,
-                              grad_out=None, stream=None):
+                              grad_out=None, stream=None, response: Response | None = None):
     if grad_out is None:
         grad_out = torch.zeros(3, dtype=torch.float64, device=grad_image.device)
-    h = _SceneHolder(sc)
+    h = _SceneHolder(sc, response)
     tb = C.byref(table.c_struct()) if table is not None else None
     _check(lib().darts_render_transient_backward(C.byref(h.c), C.byref(params(p, mode)), tb,
                                                  _ptr(grad_image.contiguous()), _ptr(grad_out), _stream(stream)))
@@ -314,15 +349,17 @@ class Batch:
 
     def __init__(self, items, plan: dict | None = None):
         self._h = C.c_void_p()
-        self._holders = [_SceneHolder(sc) for sc, _, _, _ in items]
-        self._tables = [t for _, _, _, t in items]
+        items = [tuple(it) + (None,) * (5 - len(it)) for it in items]   # (scene, params, mode, table[, response])
+        self._holders = [_SceneHolder(it[0], it[4]) for it in items]
+        self._tables = [it[3] for it in items]
+        self._responses = [it[4] for it in items]
         self._tstructs = [t.c_struct() if t is not None else None for t in self._tables]
         arr = (_BatchItem * len(items))()
-        for i, (sc, p, mode, t) in enumerate(items):
+        for i, (sc, p, mode, t, _) in enumerate(items):
             arr[i].scene = self._holders[i].c
             arr[i].params = params(p, mode)
             arr[i].table = C.pointer(self._tstructs[i]) if t is not None else None
-        self.shapes = [image_shape(sc) for sc, _, _, _ in items]
+        self.shapes = [image_shape(it[0], it[4]) for it in items]
         pl = _plan_struct(plan)
         _check(lib().darts_batch_create(arr, len(items), C.byref(pl), C.byref(self._h)))
         offs = (C.c_int64 * (len(items) + 1))()
@@ -394,10 +431,18 @@ def stats_dict(stats: torch.Tensor) -> dict:
     return {k: int(s[i]) for i, k in enumerate(ST_NAMES)}
 
 
-def paths_per_cell(sc: dict, p: dict, mode) -> torch.Tensor:
+def paths_per_cell(sc: dict, p: dict, mode, response: Response | None = None) -> torch.Tensor:
     """Paths mapped to each cell by the stratified map (path id i lands in
-    cell i mod n_cells); vanilla reuses a path for all bins of its pixel."""
-    shape = image_shape(sc)
+    cell i mod n_cells); vanilla reuses a path for all bins of its pixel.
+    With a sensor response the cells are the pixels."""
+    shape = image_shape(sc, response)
+    if response is not None:
+        npix = shape[0] * shape[1]
+        n, off = int(p["n_paths"]), int(p.get("path_offset", 0))
+        ids = torch.arange(npix, dtype=torch.int64)
+        first = (ids - off) % npix
+        cnt = torch.where(first < n, (n - 1 - first) // npix + 1, torch.zeros_like(first)).to(torch.float64)
+        return cnt.reshape(shape)
     nc = shape[0] * shape[1] * shape[2]
     n, off = int(p["n_paths"]), int(p.get("path_offset", 0))
     ids = torch.arange(nc, dtype=torch.int64)

@@ -139,6 +139,20 @@ def batched(n_media: int = 256, seed: int = 0xC3, lo_log2: int = 12, hi_log2: in
     return out
 
 
+def two_peak_response(bins: dict, peaks=((3.0, 0.4, 1.0), (5.5, 0.4, 0.6)), cutoff: float = 1e-3) -> list:
+    """A sensor response W with two Gaussian peaks over the bins' path-length
+    range, sampled at the bin centres and set to zero below `cutoff` (the
+    two-peak response of the paper's W study, Section V-B); each peak is
+    (centre, width, height).  Values are rounded to float32 so both sides read
+    identical numbers."""
+    import numpy as np
+    n, lo, hi = int(bins["n_bins"]), float(bins["l_lo"]), float(bins["l_hi"])
+    c = lo + (np.arange(n) + 0.5) * (hi - lo) / n
+    w = sum(h * np.exp(-0.5 * ((c - m) / s) ** 2) for m, s, h in peaks)
+    w = np.where(w < cutoff, 0.0, w)
+    return [float(x) for x in w.astype(np.float32)]
+
+
 def with_(w: dict, **changes) -> dict:
     """Copy of a workload with params/scene entries replaced, e.g.
     ``with_(w, n_paths=4096, medium={"sigma_s": 2.0, ...})``."""

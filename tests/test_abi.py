@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(D):
     L = D.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert L.darts_abi_version() == 1
+    assert L.darts_abi_version() == 2
 
 
 def test_library_has_no_torch_dependency(D):
@@ -151,3 +151,15 @@ def test_batch_create_validates_before_the_device(D):
     assert not out.value
     assert L.darts_batch_render(None, None, None, None) == D.ERR_INVALID_ARG
     assert L.darts_batch_destroy(None) == D.OK
+
+
+def test_response_table_validation(D):
+    import ctypes as C
+    L = D.lib()
+    n = C.c_size_t()
+    assert L.darts_response_bytes(0, C.byref(n)) == D.ERR_INVALID_ARG
+    assert L.darts_response_bytes(32, C.byref(n)) == D.OK and n.value == 65 * 4
+    dummy = C.c_void_p(16)   # never dereferenced: validation fails first
+    for bad in ([0.0, 0.0], [1.0, -1.0], [1.0, float("nan")], [float("inf"), 1.0]):
+        arr = (C.c_float * len(bad))(*bad)
+        assert L.darts_build_response(arr, len(bad), dummy, None) == D.ERR_INVALID_ARG
