@@ -217,6 +217,43 @@ double ref_box_exit(const ref_geometry *g, const double x[3], const double w[3])
     return t > 0.0 ? t : 0.0;
 }
 
+int ref_exits_through_floor(const ref_geometry *g, const double x[3], const double w[3])
+{
+    if (g->kind != 2 || !(w[2] < 0.0)) return 0;
+    double tz = (g->lo[2] - x[2]) / w[2];
+    for (int a = 0; a < 2; ++a) {
+        if (w[a] > 0.0 && (g->hi[a] - x[a]) / w[a] < tz) return 0;
+        if (w[a] < 0.0 && (g->lo[a] - x[a]) / w[a] < tz) return 0;
+    }
+    return 1;
+}
+
+/* Lambertian floor (normal +z), reached from x along w at distance t_s:
+ * the contribution of the path that ends x -> floor point -> emitter
+ * (Section V-B, case II: the control vertex is the surface point), with
+ * transmittance along both segments, BRDF albedo/pi and the cosine at the
+ * floor toward the emitter.  *L_out is the length x -> floor -> emitter and
+ * *rin_out the in-medium part of the last segment. */
+static double floor_connection(const ref_geometry *g, const double x[3], const double w[3], double t_s,
+                               const double xe[3], double sigma_t, int mutation, double *L_out, double *rin_out)
+{
+    double xs[3], de[3], wc[3];
+    axpy3(x, w, t_s, xs);
+    xs[2] = g->lo[2];
+    sub3(xe, xs, de);
+    double r = len3(de);
+    *L_out = t_s + r;
+    *rin_out = 0.0;
+    if (!(r > 0.0)) return 0.0;
+    double cos_s = de[2] / r;
+    if (!(cos_s > 0.0)) return 0.0;
+    for (int i = 0; i < 3; ++i) wc[i] = de[i] / r;
+    double r_in = fmin(r, ref_box_exit(g, xs, wc));
+    *rin_out = r_in;
+    double cosf = mutation == REF_MUT_FLOOR_NO_COSINE ? 1.0 : cos_s;
+    return exp(-sigma_t * (t_s + r_in)) * (g->floor_albedo / PI) * cosf / (r * r);
+}
+
 int ref_box_entry(const ref_geometry *g, const double x[3], const double w[3],
                   double *t_in, double *t_out)
 {
@@ -612,6 +649,14 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
     return ps->beta * ps->J * m->sigma_s * ref_hg_pdf(dot3(ps->w, wc), m->g) * trans * Ie / (r * r * pt);
 }
 
+/* Direction leaving the Lambertian floor: cosine-weighted about +z
+ * (cos theta = sqrt(u1), phi = 2 pi u2); the BRDF-to-pdf ratio is the albedo. */
+static void floor_direction(double u1, double u2, double w[3])
+{
+    double ct = sqrt(u1), sn = sqrt(fmax(0.0, 1.0 - u1)), phi = 2.0 * PI * u2;
+    w[0] = sn * cos(phi); w[1] = sn * sin(phi); w[2] = ct;
+}
+
 /* DARTS family (DARTS, uniform-S baseline and the ablation arms): one path,
  * following the recursive residual-time estimator (Eq. (6)-(7)): at every
  * vertex a control-vertex connection, then a free flight. */
@@ -634,6 +679,9 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
     double acc = 0.0;
     if (!ps.alive) { S->st[REF_ST_ZERO_PATHS]++; return 0.0; }
     double dm = ps.dm0;
+    const ref_geometry *geo = &sc->geom;
+    int on_floor = 0, n_surf = 0;   /* current vertex on the floor; floor vertices so far */
+    double Ie = ps.em->power / (4.0 * PI);
     for (int k = 0; k < pr->max_bounces; ++k) {
         S->st[REF_ST_VERTICES]++;
         double C = dist3(ps.em->pos, ps.x);
@@ -646,11 +694,17 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
             draw(pr->seed, p, (uint32_t)k, 0, r0);
             double u[4] = { ref_u01(r0[0]), ref_u01(r0[1]), ref_u01(r0[2]), ref_u01(r0[3]) };
             double wn[3], weight;
-            int eb;
-            ref_sample_direction(m, dm_t, cdf, pr->alpha, (pr->flags & REF_EDA_DIR) != 0,
-                                 ps.x, ps.em->pos, ps.w, R_hi, u, wn, &weight, &eb, pr->mutation);
-            S->st[REF_ST_EDA_BRANCH] += (uint64_t)eb;
-            dlg += dlog_hg_dg(dot3(ps.w, wn), m->g);
+            if (on_floor) {
+                floor_direction(u[1], u[2], wn);
+                weight = geo->floor_albedo;
+                on_floor = 0;
+            } else {
+                int eb;
+                ref_sample_direction(m, dm_t, cdf, pr->alpha, (pr->flags & REF_EDA_DIR) != 0,
+                                     ps.x, ps.em->pos, ps.w, R_hi, u, wn, &weight, &eb, pr->mutation);
+                S->st[REF_ST_EDA_BRANCH] += (uint64_t)eb;
+                dlg += dlog_hg_dg(dot3(ps.w, wn), m->g);
+            }
             for (int i = 0; i < 3; ++i) ps.w[i] = wn[i];
             ps.beta *= weight;
             dm = ref_box_exit(&sc->geom, ps.x, ps.w);
@@ -667,18 +721,56 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
             S->st[REF_ST_CONNECTIONS]++;
             if (grad) {
                 double Lm = L_med + tc + rin;
-                double n_sc = pr->mutation == REF_MUT_GRAD_NO_COUNT ? 0.0 : (double)(k + 1);
+                /* medium scattering vertices: the walk's (floor vertices
+                 * excluded) plus the control vertex */
+                double n_sc = pr->mutation == REF_MUT_GRAD_NO_COUNT ? 0.0 : (double)(k + 1 - n_surf);
                 grad[0] += c * (n_sc / m->sigma_s - Lm);
                 grad[1] += c * (-Lm);
                 grad[2] += c * (dlg + dlog_hg_dg(muc, m->g));
             }
         }
         acc += c;
+        if (ref_exits_through_floor(geo, ps.x, ps.w)) {
+            /* case II: the ray meets the floor at t_s = dm; the floor point
+             * closes a path of fixed length, which counts if it falls in
+             * the target interval */
+            double Lp, rin_s;
+            double fc = floor_connection(geo, ps.x, ps.w, dm, ps.em->pos, st, pr->mutation, &Lp, &rin_s);
+            double L = ps.Le + Lp;
+            S->st[REF_ST_SAMPLES]++;
+            if (L >= ps.G_lo && L < ps.G_hi) {
+                double cs = ps.beta * ps.J * Ie * fc;
+                if (cs != 0.0) {
+                    S->st[REF_ST_CONNECTIONS]++;
+                    if (grad) {
+                        double Lm = L_med + dm + rin_s;
+                        double n_sc = pr->mutation == REF_MUT_GRAD_NO_COUNT ? 0.0 : (double)(k - n_surf);
+                        grad[0] += cs * (n_sc / m->sigma_s - Lm);
+                        grad[1] += cs * (-Lm);
+                        grad[2] += cs * dlg;
+                    }
+                }
+                acc += cs;
+            } else {
+                S->st[REF_ST_REJECTED]++;
+            }
+        }
         if (k == pr->max_bounces - 1) { S->st[REF_ST_TRUNCATED]++; break; }
         /* free flight: medium-event Bernoulli (Eq. (12)) */
         double pc = isinf(dm) ? 1.0 : -expm1(-st * dm);
         double u5 = ref_u01(r1[1]);
-        if (!(u5 < pc)) { S->st[REF_ST_MEDIUM_EXIT]++; break; }
+        if (!(u5 < pc)) {
+            if (!ref_exits_through_floor(geo, ps.x, ps.w)) { S->st[REF_ST_MEDIUM_EXIT]++; break; }
+            /* surface event (probability e^{-sigma_t d_m}, equal to the
+             * transmittance: the throughput is unchanged) */
+            axpy3(ps.x, ps.w, dm, ps.x);
+            ps.x[2] = geo->lo[2];
+            ps.Le += dm;
+            L_med += dm;
+            on_floor = 1;
+            ++n_surf;
+            continue;
+        }
         double d, factor;
         if (pr->flags & REF_RIS_DIST) {
             if (!ref_ris_step(m, pr->n_ris, ps.x, ps.w, ps.em->pos, R_hi, dm,
@@ -728,6 +820,8 @@ static void trace_vanilla(const ref_scene *sc, const ref_params *pr, uint64_t p,
     double dm = ps.dm0;
     int any = 0;
     const int response = (pr->flags & REF_RESPONSE) != 0;
+    const ref_geometry *geo = &sc->geom;
+    int on_floor = 0;   /* current vertex on the Lambertian floor */
     for (int k = 0; k <= pr->max_bounces; ++k) {
         S->st[REF_ST_VERTICES]++;
         if (k >= 1) {
@@ -736,13 +830,18 @@ static void trace_vanilla(const ref_scene *sc, const ref_params *pr, uint64_t p,
             double r = len3(de), wc[3];
             for (int i = 0; i < 3; ++i) wc[i] = de[i] / r;
             double r_in = fmin(r, ref_box_exit(&sc->geom, ps.x, wc));
+            /* local scattering toward the emitter: phase function in the
+             * medium, BRDF times cosine on the floor */
+            double fl = on_floor ? (wc[2] > 0.0 ? geo->floor_albedo / PI *
+                                    (pr->mutation == REF_MUT_FLOOR_NO_COSINE ? 1.0 : wc[2]) : 0.0)
+                                 : ref_hg_pdf(dot3(ps.w, wc), m->g);
             double L = ps.Le + r + ps.em->start;       /* arrival time */
             int bin = (int)floor((L - sc->bins.l_lo) / delta);
             S->st[REF_ST_SAMPLES]++;
             if (L >= sc->bins.l_lo && bin >= 0 && bin < sc->bins.n_bins) {
                 /* sensor weight: the bin indicator, or W of the length */
                 double wsens = response ? pr->response[bin] : 1.0;
-                double v = wsens * ps.beta * ps.J * ref_hg_pdf(dot3(ps.w, wc), m->g) * exp(-st * r_in) * Ie / (r * r);
+                double v = wsens * ps.beta * ps.J * fl * exp(-st * r_in) * Ie / (r * r);
                 if (wsens > 0.0) {
                     scratch_add(bs, response ? 0 : bin, v);
                     S->st[REF_ST_CONNECTIONS]++;
@@ -761,16 +860,29 @@ static void trace_vanilla(const ref_scene *sc, const ref_params *pr, uint64_t p,
         if (k >= 1) {
             uint32_t r0[4];
             draw(pr->seed, p, (uint32_t)k, 0, r0);
-            double mu = ref_hg_sample_mu(ref_u01(r0[1]), m->g);
             double wn[3];
-            from_frame(ps.w, mu, 2.0 * PI * ref_u01(r0[2]), wn);
+            if (on_floor) {
+                floor_direction(ref_u01(r0[1]), ref_u01(r0[2]), wn);
+                ps.beta *= geo->floor_albedo;
+                on_floor = 0;
+            } else {
+                double mu = ref_hg_sample_mu(ref_u01(r0[1]), m->g);
+                from_frame(ps.w, mu, 2.0 * PI * ref_u01(r0[2]), wn);
+            }
             for (int i = 0; i < 3; ++i) ps.w[i] = wn[i];
             dm = ref_box_exit(&sc->geom, ps.x, ps.w);
         }
         draw(pr->seed, p, (uint32_t)k, 1, r1);
         double pc = isinf(dm) ? 1.0 : -expm1(-st * dm);
         double u5 = ref_u01(r1[1]);
-        if (!(u5 < pc)) { S->st[REF_ST_MEDIUM_EXIT]++; break; }
+        if (!(u5 < pc)) {
+            if (!ref_exits_through_floor(geo, ps.x, ps.w)) { S->st[REF_ST_MEDIUM_EXIT]++; break; }
+            axpy3(ps.x, ps.w, dm, ps.x);     /* surface event on the floor */
+            ps.x[2] = geo->lo[2];
+            ps.Le += dm;
+            on_floor = 1;
+            continue;
+        }
         double d = -log1p(-u5) / st;
         axpy3(ps.x, ps.w, d, ps.x);
         ps.Le += d;
@@ -848,7 +960,10 @@ static int check_args(const ref_scene *sc, const ref_params *pr)
     if (sc->bins.n_bins <= 0 || !(sc->bins.l_hi > sc->bins.l_lo)) return -1;
     if (sc->sensor.width <= 0 || sc->sensor.height <= 0) return -1;
     if (pr->max_bounces <= 0 || pr->n_ris < 1 || pr->n_ris > 8) return -1;
+    if (sc->geom.kind < 0 || sc->geom.kind > 2) return -1;
+    if (sc->geom.kind == 2 && !(sc->geom.floor_albedo >= 0.0 && sc->geom.floor_albedo <= 1.0)) return -1;
     unsigned f = pr->flags;
+    if ((f & REF_FORWARD) && sc->geom.kind == 2) return -1;   /* the analog walk has no floor */
     if (f & REF_RESPONSE) {
         if (!pr->response || (f & REF_FORWARD)) return -1;
         double tot = 0.0;

@@ -43,8 +43,10 @@ typedef struct {
 } ref_sensor;
 
 /* kind 0: infinite medium; kind 1: medium fills the box [lo, hi] with an
- * index-matched boundary (vacuum outside, no refraction). */
-typedef struct { int kind; double lo[3], hi[3]; } ref_geometry;
+ * index-matched boundary (vacuum outside, no refraction); kind 2: the box of
+ * kind 1 whose face z = lo[2] is an opaque Lambertian floor of albedo
+ * floor_albedo (a fog layer over a diffuse ground; Section V-B, case II). */
+typedef struct { int kind; double lo[3], hi[3]; double floor_albedo; } ref_geometry;
 
 /* n_bins half-open path-length bins of equal width over [l_lo, l_hi). */
 typedef struct { double l_lo, l_hi; int n_bins; } ref_bins;
@@ -98,6 +100,7 @@ typedef struct {
 #define REF_MUT_HG_SAMPLE_FLIP    5 /* HG sample mirrored (cos -> -cos)       */
 #define REF_MUT_GRAD_NO_COUNT     6 /* gradient: drop n / sigma_s              */
 #define REF_MUT_RESPONSE_UNWEIGHTED 7 /* response: drop W_k / P(segment k)     */
+#define REF_MUT_FLOOR_NO_COSINE   8 /* floor connection without its cosine      */
 
 /* Statistics, uint64 counters. */
 enum {
@@ -127,6 +130,8 @@ double ref_ell_t(double S, double C, double mu);
 double ref_ell_pdf_t(double pS, double S, double C, double mu, double t, int printed);
 double ref_gamma(double kappa, double alpha);
 double ref_box_exit(const ref_geometry *g, const double x[3], const double w[3]);
+/* 1 if the ray (x, w) leaves the medium through the Lambertian floor. */
+int    ref_exits_through_floor(const ref_geometry *g, const double x[3], const double w[3]);
 int    ref_box_entry(const ref_geometry *g, const double x[3], const double w[3],
                      double *t_in, double *t_out);
 double ref_sobol_u(uint32_t row, uint32_t col, uint32_t eps_bits);

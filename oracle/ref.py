@@ -31,7 +31,8 @@ MODES = {
     "forward": FORWARD,
 }
 MUT = {"none": 0, "printed_jacobian": 1, "ris_no_mean": 2, "eda_pdf_unscaled": 3,
-       "no_emitter_trans": 4, "hg_sample_flip": 5, "grad_no_count": 6, "response_unweighted": 7}
+       "no_emitter_trans": 4, "hg_sample_flip": 5, "grad_no_count": 6, "response_unweighted": 7,
+       "floor_no_cosine": 8}
 STATS = ["paths", "vertices", "connections", "early_exit", "medium_exit", "ris_all_invalid",
          "eda_branch", "truncated", "zero_paths", "ris_invalid_cands", "samples", "rejected"]
 
@@ -60,7 +61,7 @@ class _Sensor(C.Structure):
 
 
 class _Geometry(C.Structure):
-    _fields_ = [("kind", C.c_int), ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+    _fields_ = [("kind", C.c_int), ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("floor_albedo", C.c_double)]
 
 
 class _Bins(C.Structure):
@@ -161,7 +162,8 @@ def medium(m: dict) -> _Medium:
 
 
 def geometry(g: dict) -> _Geometry:
-    return _Geometry(int(g["kind"]), _v3(g.get("lo", (0, 0, 0))), _v3(g.get("hi", (0, 0, 0))))
+    return _Geometry(int(g["kind"]), _v3(g.get("lo", (0, 0, 0))), _v3(g.get("hi", (0, 0, 0))),
+                     float(g.get("floor_albedo", 0.0)))
 
 
 def dims(d: dict) -> _Dims:

@@ -94,6 +94,18 @@ def box_point() -> dict:
     }
 
 
+def box_floor_point() -> dict:
+    """The medium of ``box_point`` as a layer z in [0, 1] over [-1, 1]^2
+    whose bottom face is an opaque Lambertian floor of albedo 0.5; pulse at
+    (0, 0, 1.5) and point fluence detector at (0.8, 0, 1.5), both above the
+    layer, so every estimator has bounded weights; 32 bins over [0, 16)."""
+    w = box_point()
+    w["name"] = "box_floor_point"
+    w["scene"]["geometry"] = {"kind": 2, "lo": (-1.0, -1.0, 0.0), "hi": (1.0, 1.0, 1.0), "floor_albedo": 0.5}
+    w["scene"]["sensor"]["origin"] = (0.8, 0.0, 1.5)
+    return w
+
+
 def box_hg_grad() -> dict:
     """Differentiable rendering workload: the box geometry of ``box_hg`` at
     sigma_s = 8, sigma_a = 0.2, g = 0.5 with a 128x128 sensor and 512 bins
@@ -137,6 +149,45 @@ def batched(n_media: int = 256, seed: int = 0xC3, lo_log2: int = 12, hi_log2: in
         w["params"]["seed"] = (seed << 32) | i
         out.append(w)
     return out
+
+
+def fog_slab() -> dict:
+    """Fog layer over a diffuse ground (the set-up of the paper's Fig. 1):
+    a slab 10 mean free paths thick (sigma_s = 2, sigma_a = 0.02, g = 0.85,
+    so thickness 10 / 2.02) over an opaque Lambertian floor of albedo 0.5 at
+    z = 0, laterally 100 units wide (effectively infinite); two pulsed point
+    emitters inside the fog, 1 unit above the floor at x = -1 and x = +1, the
+    second starting 3 length units later; a 256x256 orthographic sensor on the
+    slab's top face over [-4, 4]^2 looking down; 1024 bins over [0, 40); 2^28
+    paths, at most 256 bounces; 64x64x32 direction table, S_max = 40."""
+    h = 10.0 / 2.02
+    return {
+        "name": "fog_slab",
+        "scene": {
+            "medium": {"sigma_s": 2.0, "sigma_a": 0.02, "g": 0.85},
+            "geometry": {"kind": 2, "lo": (-50.0, -50.0, 0.0), "hi": (50.0, 50.0, h), "floor_albedo": 0.5},
+            "emitters": [{"pos": (-1.0, 0.0, 1.0), "start": 0.0, "power": 1.0},
+                         {"pos": (1.0, 0.0, 1.0), "start": 3.0, "power": 1.0}],
+            "sensor": {"kind": 1, "origin": (-4.0, -4.0, h), "dir": (0.0, 0.0, -1.0),
+                       "du": (8.0, 0.0, 0.0), "dv": (0.0, 8.0, 0.0), "width": 256, "height": 256},
+            "bins": {"l_lo": 0.0, "l_hi": 40.0, "n_bins": 1024},
+        },
+        "params": {"n_paths": 1 << 28, "path_offset": 0, "seed": 0xC5, "max_bounces": 256,
+                   "n_ris": 8, "alpha": 0.5},
+        "dims": {"n_cs": 64, "n_s": 64, "n_cos": 32, "s_max": 40.0},
+    }
+
+
+def fog_slab_small() -> dict:
+    """``fog_slab`` at oracle scale: 16x16 pixels, 64 bins over [0, 20),
+    2^16 paths, 32x32x32 table with S_max = 20."""
+    w = fog_slab()
+    w["name"] = "fog_slab_small"
+    w["scene"]["sensor"]["width"] = w["scene"]["sensor"]["height"] = 16
+    w["scene"]["bins"] = {"l_lo": 0.0, "l_hi": 20.0, "n_bins": 64}
+    w["params"]["n_paths"] = 1 << 16
+    w["dims"] = {"n_cs": 32, "n_s": 32, "n_cos": 32, "s_max": 20.0}
+    return w
 
 
 def two_peak_response(bins: dict, peaks=((3.0, 0.4, 1.0), (5.5, 0.4, 0.6)), cutoff: float = 1e-3) -> list:

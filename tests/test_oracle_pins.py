@@ -588,8 +588,8 @@ def test_planted_mistakes_are_caught(oracle):
 # --------------------------------------------------------------------------
 # Gradient of a transient loss (detached sampling, path replay)
 # --------------------------------------------------------------------------
-def _gradient_vs_fd(oracle, mode, mutation="none", seeds=6, n=1 << 19, hrel=0.03):
-    w = W.box_point()
+def _gradient_vs_fd(oracle, mode, mutation="none", seeds=6, n=1 << 19, hrel=0.03, floor=False):
+    w = W.box_floor_point() if floor else W.box_point()
     sc, dm = w["scene"], w["dims"]
     med = sc["medium"]
     gimg = np.random.default_rng(0).random(oracle.image_shape(sc))
@@ -633,3 +633,11 @@ def test_gradient_matches_finite_differences(oracle, mode):
 def test_gradient_planted_mistake_is_caught(oracle):
     z, g, fd = _gradient_vs_fd(oracle, "darts", mutation="grad_no_count", seeds=4)
     assert abs(z[0]) > 6.0, (z, g, fd)
+
+
+def test_gradient_with_floor_matches_finite_differences(oracle):
+    """The same check in a medium over a Lambertian floor: floor vertices
+    carry no sigma_s and no phase function, the floor's case II
+    contributions no control vertex."""
+    z, g, fd = _gradient_vs_fd(oracle, "darts", floor=True)
+    assert np.max(np.abs(z)) < 4.0, (z, g, fd)
