@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "transient paths/s and time-to-MSE 1e-4, DARTS vs uniform sampling, 1×MI355X"
+FIT_SETTINGS = {"steps": 200, "mode": "da_only", "lr": 0.05, "lr_final": 0.01, "n_paths": 1 << 24}
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
 HBM_PEAK_GBS = 8000.0
 
@@ -84,6 +85,7 @@ def parse():
     ap.add_argument("--no-uniform", action="store_true", help="skip the uniform-baseline throughput")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-media launch")
     ap.add_argument("--no-response", action="store_true", help="skip the two-peak sensor-response study")
+    ap.add_argument("--no-fog", action="store_true", help="skip the fog-layer render and the Adam fit")
     ap.add_argument("--batched-reps", type=int, default=5, help="timed graph launches of the batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -227,6 +229,9 @@ def main():
     if not a.no_response:
         out["response"] = response_bench(darts, torch, np, W, w)
         print(f"[bench] response {out['response']}", file=sys.stderr, flush=True)
+    if not a.no_fog:
+        out["fog_slab"] = fog_bench(darts, torch, W)
+        print(f"[bench] fog_slab {out['fog_slab']}", file=sys.stderr, flush=True)
     if not a.no_batched:
         out["batched"] = batched_bench(darts, torch, W, a.batched_reps)
         print(f"[bench] batched {out['batched']}", file=sys.stderr, flush=True)
@@ -350,6 +355,43 @@ def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 24, k=16, t
         rep[f"{mode}_over_darts_time"] = rep[mode]["seconds_to_target"] / rep["darts"]["seconds_to_target"]
         rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
     return rep
+
+
+def fog_bench(darts, torch, W, reps=2):
+    """Fog layer over a Lambertian floor, two emitters 3 length units apart:
+    the full 256x256 x 1024-bin DARTS render at 2^28 paths (HIP-event timed),
+    then 200 Adam steps recovering (sigma_s, g) from a synthetic target with
+    the adjoint kernel (on the 16x16 x 128-bin version of the scene)."""
+    from paper_2402_03106_amd import inverse
+    w = W.fog_slab()
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    table = darts.build_da_tables(sc["medium"], dm)
+    hi, lo, _, _ = darts.render_transient(sc, pr, "darts", table)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        darts.render_transient(sc, pr, "darts", table, hi, lo)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = int(pr["n_paths"])
+    del hi, lo
+    torch.cuda.empty_cache()
+    fw = W.fog_slab_fit()
+    fit = inverse.fit_medium(fw, fw["target_medium"], fw["init_medium"], **FIT_SETTINGS)
+    tm, im = fw["target_medium"], fw["init_medium"]
+    return {
+        "render": {"paths": n, "cells": 256 * 256 * 1024, "render_ms": ms, "paths_per_s": n / ms * 1e3},
+        "fit": {"target": {"sigma_s": tm["sigma_s"], "g": tm["g"]}, "init": {"sigma_s": im["sigma_s"], "g": im["g"]},
+                "estimate": {"sigma_s": fit["sigma_s"], "g": fit["g"]},
+                "rel_error": {"sigma_s": fit["sigma_s"] / tm["sigma_s"] - 1, "g": fit["g"] / tm["g"] - 1,
+                              "reduced_sigma_s": fit["sigma_s"] * (1 - fit["g"]) / (tm["sigma_s"] * (1 - tm["g"])) - 1},
+                "steps": fit["steps"], "seconds": fit["seconds"], "ms_per_step": fit["seconds"] / fit["steps"] * 1e3,
+                "paths_per_render": fit["paths_per_render"], "mode": fit["mode"],
+                "image": "16x16 x 128 bins over [0,40)"},
+    }
 
 
 def batched_bench(darts, torch, W, reps):

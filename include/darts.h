@@ -69,8 +69,12 @@ typedef struct {
 } darts_sensor;
 
 /* kind 0: infinite medium.  kind 1: the medium fills the axis-aligned box
- * [lo, hi] with an index-matched boundary (vacuum outside, no refraction). */
-typedef struct { int kind; float lo[3], hi[3]; } darts_geometry;
+ * [lo, hi] with an index-matched boundary (vacuum outside, no refraction).
+ * kind 2: the box of kind 1 whose bottom face z = lo[2] is an opaque
+ * Lambertian floor of albedo floor_albedo in [0, 1] (a fog layer over diffuse
+ * ground; surface events and case II surface connections of Section V-B).
+ * floor_albedo is ignored for kinds 0 and 1. */
+typedef struct { int kind; float lo[3], hi[3]; float floor_albedo; } darts_geometry;
 
 /* n_bins half-open bins of equal width over total path length [l_lo, l_hi),
  * measured from the sensor and including the emitter's start offset. */

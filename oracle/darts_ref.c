@@ -639,9 +639,11 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
     double t = ref_ell_t(S, C, mu);
     double r = S - t;
     double pt = ref_ell_pdf_t(pS, S, C, mu, t, pr->mutation == REF_MUT_PRINTED_JACOBIAN);
-    double xc[3], wc[3];
+    double xc[3], wc[3], dv[3];
     axpy3(ps->x, ps->w, t, xc);
-    for (int i = 0; i < 3; ++i) wc[i] = (ps->em->pos[i] - xc[i]) / r;
+    sub3(ps->em->pos, xc, dv);
+    double rv = len3(dv);                      /* equals r = S - t up to rounding */
+    for (int i = 0; i < 3; ++i) wc[i] = dv[i] / rv;
     double r_in = fmin(r, ref_box_exit(&sc->geom, xc, wc));
     double Ie = ps->em->power / (4.0 * PI);
     double trans = exp(-st * t) * (pr->mutation == REF_MUT_NO_EMITTER_TRANS ? 1.0 : exp(-st * r_in));

@@ -49,7 +49,7 @@ int ok()
 // ---------------------------------------------------------------------------
 struct KParams {
     Medium med;
-    int box;                    // 0 infinite, 1 box
+    int box;                    // 0 infinite, 1 box (also with a floor)
     Box bx;
     int n_em;
     float em_pos[DARTS_MAX_EMITTERS][3];
@@ -81,6 +81,8 @@ struct KParams {
     float *path_out;
     const float *grad_image;
     double *grad_out;
+    int floor;                  // the box's bottom face is an opaque Lambertian floor
+    float floor_albedo;
 };
 
 constexpr int kBlock = 256;
@@ -117,25 +119,20 @@ struct PathState {
     // derivative bookkeeping for the backward pass (detached sampling)
     float L_med;      // in-medium length walked so far
     float dlog_g;     // sum of d log f_HG / dg over walk vertices so far
+    int n_surf;       // floor vertices among vertices 1..k
+    bool on_floor;    // the current vertex lies on the floor
 };
 
-// Emitter j's position, start and scale by an unrolled select over the
-// kernel-argument arrays (a dynamic index into the by-value parameter block
-// would force a copy of the block to scratch memory).
+// Emitter j's position, start and scale.  The kernels reach the parameter
+// block through a pointer into constant memory (the kernel-argument segment,
+// or the batch's scene array), so a per-lane index becomes a vector load
+// rather than keeping every emitter's fields live in scalar registers.
 __device__ __forceinline__ void emitter(const KParams &P, int j, V3 &pos, float &start, float &scale)
 {
-    pos = V3{P.em_pos[0][0], P.em_pos[0][1], P.em_pos[0][2]};
-    start = P.em_start[0];
-    scale = P.em_scale[0];
-    if (P.n_em == 1) return;
-#pragma unroll
-    for (int i = 1; i < DARTS_MAX_EMITTERS; ++i) {
-        if (i < P.n_em && i == j) {
-            pos = V3{P.em_pos[i][0], P.em_pos[i][1], P.em_pos[i][2]};
-            start = P.em_start[i];
-            scale = P.em_scale[i];
-        }
-    }
+    if (P.n_em == 1) j = 0;
+    pos = V3{P.em_pos[j][0], P.em_pos[j][1], P.em_pos[j][2]};
+    start = P.em_start[j];
+    scale = P.em_scale[j];
 }
 
 __device__ __forceinline__ float dlog_hg_dg(float mu, float g)
@@ -173,6 +170,8 @@ __device__ bool setup_path(const KParams &P, U4 r, int bin, int px, int py, Path
     emitter(P, j, s.xe, start, s.em_scale);
     s.beta = P.beta0;
     s.k = 0;
+    s.n_surf = 0;
+    s.on_floor = false;
     s.acc = 0.f;
     s.L_med = 0.f;
     s.dlog_g = 0.f;
@@ -270,9 +269,14 @@ __device__ __forceinline__ float connect_eval(const KParams &P, const Conn &q, f
     if (!(den > 0.f) || !(r > 0.f)) return 0.f;
     const V3 xc = fma3(q.x, q.w, t);
     const float ir = rcp(r);
-    const V3 wc = (q.xe - xc) * ir;
+    // unit direction from the control vertex to the emitter, normalised from
+    // the vector itself: when the ray points almost at the emitter and the S
+    // range is a few ulps wide, r from the ellipse formula is far below the
+    // rounding of xe - xc, and dividing by it would leave |wc| > 1
+    const V3 dv = q.xe - xc;
+    const V3 wc = dv * rsq(dot(dv, dv));
     const float r_in = P.box ? fminf(r, box_exit(P.bx, xc, wc)) : r;
-    mu_c = dot(q.w, wc);
+    mu_c = fminf(fmaxf(dot(q.w, wc), -1.f), 1.f);
     t_out = t;
     r_in_out = r_in;
     const float f = hg_pdf(mu_c, m.g);
@@ -298,7 +302,7 @@ __device__ float connect(const KParams &P, const PathState &s, float u4, float *
     if (dlog) {
         const Medium &m = P.med;
         const float Lm = s.L_med + t + r_in;               // in-medium length
-        const float n = (float)(s.k + 1);                  // scattering vertices
+        const float n = (float)(s.k + 1 - s.n_surf);       // medium scattering vertices
         dlog[0] = n / m.sigma_s - Lm;
         dlog[1] = -Lm;
         dlog[2] = s.dlog_g + dlog_hg_dg(mu_c, m.g);
@@ -307,10 +311,17 @@ __device__ float connect(const KParams &P, const PathState &s, float u4, float *
 }
 
 // Direction at vertex k >= 1 (DARTS family), from stream 0 of vertex k.
-template <int OUT, class ST>
+template <int OUT, bool FLOOR, class ST>
 __device__ __forceinline__ void direction_darts(const KParams &P, PathState &s, U4 r0, ST &st)
 {
     const Medium &m = P.med;
+    if (FLOOR && s.on_floor) {
+        s.w = floor_direction(u01(r0.y), u01(r0.z));
+        s.beta *= P.floor_albedo;
+        s.on_floor = false;
+        s.dm = box_exit(P.bx, s.x, s.w);
+        return;
+    }
     const V3 de = s.xe - s.x;
     float weight;
     bool eb;
@@ -323,11 +334,45 @@ __device__ __forceinline__ void direction_darts(const KParams &P, PathState &s, 
     s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
 }
 
+// Floor point as the connection vertex (Section V-B, case II): the ray meets
+// the floor at t_s = s.dm; the path x -> floor point -> emitter has a fixed
+// length and counts when it falls in the target interval.  Contribution:
+// throughput x transmittance of both segments x albedo/pi x cosine at the
+// floor x emitter intensity / r^2.  dlog as for connect().
+template <class ST>
+__device__ float floor_connect(const KParams &P, const PathState &s, float *dlog, ST &st)
+{
+    const float t_s = s.dm;
+    V3 xs = fma3(s.x, s.w, t_s);
+    xs.z = P.bx.lo[2];
+    const V3 de = s.xe - xs;
+    const float r = length(de);
+    if (!(r > 0.f) || !(de.z > 0.f)) return 0.f;
+    const float L = s.Le + t_s + r;
+    st.inc(DARTS_ST_SAMPLES);
+    if (!(L >= s.G_lo && L < s.G_hi)) {
+        st.inc(DARTS_ST_REJECTED);
+        return 0.f;
+    }
+    const float ir = rcp(r);
+    const float r_in = fminf(r, box_exit(P.bx, xs, de * ir));
+    const Medium &m = P.med;
+    if (dlog) {
+        const float Lm = s.L_med + t_s + r_in;
+        dlog[0] = (float)(s.k - s.n_surf) / m.sigma_s - Lm;
+        dlog[1] = -Lm;
+        dlog[2] = s.dlog_g;
+    }
+    const float cos_s = de.z * ir;
+    return s.beta * s.em_scale * fast_exp(-m.sigma_t * (t_s + r_in)) * (P.floor_albedo * (1.f / kPi)) * cos_s *
+           ir * ir;
+}
+
 // Connection at vertex k and free flight from it (DARTS family, stream 1 of
 // vertex k): medium-event Bernoulli (Eq. (12)), DA-RIS or exponential
 // distance, then the early-exit test at the new vertex.  Returns false when
 // the path has ended.
-template <int OUT, class ST>
+template <int OUT, bool FLOOR, class ST>
 __device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &st, float grad_w, double *gacc)
 {
     const Medium &m = P.med;
@@ -344,11 +389,39 @@ __device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &
             }
         }
     }
+    const bool to_floor = FLOOR && exits_floor(P.bx, s.x, s.w);
+    if (to_floor) {
+        float dl[3];
+        const float c = floor_connect(P, s, OUT == OUT_GRAD ? dl : nullptr, st);
+        if (c != 0.f) {
+            st.inc(DARTS_ST_CONNECTIONS);
+            s.acc += c;
+            if (OUT == OUT_GRAD) {
+                const double cw = (double)c * (double)grad_w;
+                gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
+            }
+        }
+    }
     if (s.k == P.max_bounces - 1) { st.inc(DARTS_ST_TRUNCATED); return false; }
     float epc = 0.f;
     const float pc = P.box ? one_minus_exp_neg(m.sigma_t * s.dm, epc) : 1.f;
     const float u5 = u01(r1.y);
-    if (!(u5 < pc)) { st.inc(DARTS_ST_MEDIUM_EXIT); return false; }
+    if (!(u5 < pc)) {
+        if (!to_floor) { st.inc(DARTS_ST_MEDIUM_EXIT); return false; }
+        // surface event: probability e^{-sigma_t d_m}, equal to the
+        // transmittance, so the throughput is unchanged
+        s.x = fma3(s.x, s.w, s.dm);
+        s.x.z = P.bx.lo[2];
+        s.Le += s.dm;
+        s.L_med += s.dm;
+        s.k += 1;
+        s.n_surf += 1;
+        s.on_floor = true;
+        s.C = length(s.xe - s.x);
+        st.inc(DARTS_ST_VERTICES);
+        if (s.G_hi - s.Le <= s.C) { st.inc(DARTS_ST_EARLY_EXIT); return false; }
+        return true;
+    }
     float d, factor;
     if (P.flags & DARTS_RIS_DIST) {
         const V3 de = s.xe - s.x;
@@ -383,26 +456,41 @@ __device__ __forceinline__ void add_compensated(float *hi, float *lo, int64_t i,
 // Vanilla transient path tracing (the paper's baseline): exponential free
 // flight, phase sampling, a shadow connection at every medium vertex, each
 // connection binned by its total length.
+template <bool FLOOR>
 __device__ __forceinline__ void direction_vanilla(const KParams &P, PathState &s, U4 r0)
 {
-    float mu, sn;
-    hg_sample(u01(r0.y), P.med.g, mu, sn);
-    s.w = from_frame(s.w, mu, sn, u01(r0.z));
+    if (FLOOR && s.on_floor) {
+        s.w = floor_direction(u01(r0.y), u01(r0.z));
+        s.beta *= P.floor_albedo;
+        s.on_floor = false;
+    } else {
+        float mu, sn;
+        hg_sample(u01(r0.y), P.med.g, mu, sn);
+        s.w = from_frame(s.w, mu, sn, u01(r0.z));
+    }
     s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
 }
 
-template <class ST>
+template <bool FLOOR, class ST>
 __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathState &s, ST &st)
 {
     const Medium &m = P.med;
     const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
     const float pc = P.box ? texp_mass(m.sigma_t, s.dm) : 1.f;
     const float u5 = u01(r1.y);
-    if (!(u5 < pc)) { st.inc(DARTS_ST_MEDIUM_EXIT); return false; }
-    const float d = texp_sample(u5, m.ln2_over_sigma_t, 1.f, 0.f);
-    s.x = fma3(s.x, s.w, d);
-    s.Le += d;
-    s.beta *= m.albedo;
+    if (!(u5 < pc)) {
+        if (!(FLOOR && exits_floor(P.bx, s.x, s.w))) { st.inc(DARTS_ST_MEDIUM_EXIT); return false; }
+        // surface event on the floor (probability = transmittance)
+        s.x = fma3(s.x, s.w, s.dm);
+        s.x.z = P.bx.lo[2];
+        s.Le += s.dm;
+        s.on_floor = true;
+    } else {
+        const float d = texp_sample(u5, m.ln2_over_sigma_t, 1.f, 0.f);
+        s.x = fma3(s.x, s.w, d);
+        s.Le += d;
+        s.beta *= m.albedo;
+    }
     s.k += 1;
     const V3 de = s.xe - s.x;
     const float r = length(de);
@@ -410,6 +498,10 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
     {
         const float ir = rcp(r);
         const V3 wc = de * ir;
+        // local scattering toward the emitter: phase function in the medium,
+        // BRDF times cosine on the floor
+        const float f_loc = FLOOR && s.on_floor ? (wc.z > 0.f ? P.floor_albedo * (1.f / kPi) * wc.z : 0.f)
+                                       : hg_pdf(dot(s.w, wc), m.g);
         const float r_in = P.box ? fminf(r, box_exit(P.bx, s.x, wc)) : r;
         // total length with the emitter's start offset: G_lo = l_lo - start
         const float L = s.Le + r + (P.l_lo - s.G_lo);
@@ -419,8 +511,7 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
         const bool in_range = L >= P.l_lo && bin >= 0 && bin < P.n_bins;
         const float wsens = !in_range ? 0.f : (P.resp_w ? P.resp_w[bin] : 1.f);
         if (wsens > 0.f) {
-            const float v = wsens * s.beta * s.em_scale * hg_pdf(dot(s.w, wc), m.g) *
-                            fast_exp(-m.sigma_t * r_in) * ir * ir;
+            const float v = wsens * s.beta * s.em_scale * f_loc * fast_exp(-m.sigma_t * r_in) * ir * ir;
             const int64_t cell = P.resp_w ? pixel : (int64_t)bin * P.npix + pixel;
             add_compensated(P.hi, P.lo, cell, v, 0.f);
             if (P.m2) unsafeAtomicAdd(P.m2 + cell, v * v);
@@ -464,7 +555,7 @@ __device__ __forceinline__ void compensated_lds_add(float *hi, float *lo, int i,
     if (e != 0.f) atomicAdd(&lo[i], e);
 }
 
-template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, int SRC>
+template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, int SRC, bool FLOOR>
 __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end,
                                          float *img_hi, float *img_lo, float *acc_hi, float *acc_lo,
                                          float *acc_m2, Stats<STATS> &st, double *gacc)
@@ -569,13 +660,13 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
                 alive = setup_path(P, r0, bin, px, py, s, st, MODE == 1);
                 if (!alive) s.acc = 0.f;
             } else if (MODE == 1) {
-                direction_vanilla(P, s, r0);
+                direction_vanilla<FLOOR>(P, s, r0);
             } else {
-                direction_darts<OUT>(P, s, r0, st);
+                direction_darts<OUT, FLOOR>(P, s, r0, st);
             }
             if (alive) {
-                if (MODE == 1) alive = fly_vanilla(P, p, pixel, s, st);
-                else alive = connect_and_fly<OUT>(P, p, s, st, grad_w, gacc);
+                if (MODE == 1) alive = fly_vanilla<FLOOR>(P, p, pixel, s, st);
+                else alive = connect_and_fly<OUT, FLOOR>(P, p, s, st, grad_w, gacc);
             }
             if (alive) {
                 state = LANE_ACTIVE;
@@ -604,9 +695,14 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
 // (later time bins first, so the long paths start first) and a chunk of
 // repetitions, runs its pool with LDS accumulators and flushes one
 // compensated global atomic pair per cell.
-template <int MODE, int OUT, bool STATS>
-__global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_kernel(KParams P)
+typedef __attribute__((address_space(4))) const KParams CKParams;
+
+template <int MODE, int OUT, bool STATS, bool FLOOR>
+__global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_kernel(KParams P_arg)
 {
+    // the parameter block, read in place in the kernel-argument segment
+    (void)P_arg;
+    const KParams &P = *(const KParams *)(CKParams *)__builtin_amdgcn_kernarg_segment_ptr();
     __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
@@ -625,7 +721,7 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
 #pragma unroll
     for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     double gacc[3] = {0.0, 0.0, 0.0};
-    run_pool<MODE, OUT, STATS, SRC_TILE>(P, c0, j_begin, j_end, nullptr, nullptr, acc_hi + wbase, acc_lo + wbase,
+    run_pool<MODE, OUT, STATS, SRC_TILE, FLOOR>(P, c0, j_begin, j_end, nullptr, nullptr, acc_hi + wbase, acc_lo + wbase,
                                          acc_m2 + wbase, st, gacc);
 
     if (MODE == 0 && OUT == OUT_IMAGE && have) {
@@ -687,7 +783,7 @@ struct BParams {
 typedef __attribute__((address_space(4))) const BItem CItem;
 typedef __attribute__((address_space(4))) const BUnit CUnit;
 
-template <int SRC, int BLOCK>
+template <int SRC, int BLOCK, bool FLOOR>
 __global__ __launch_bounds__(BLOCK, DARTS_RENDER_WAVES_PER_SIMD) void batch_kernel(BParams B)
 {
     __shared__ float acc_hi[BLOCK], acc_lo[BLOCK];
@@ -714,7 +810,7 @@ __global__ __launch_bounds__(BLOCK, DARTS_RENDER_WAVES_PER_SIMD) void batch_kern
             acc_hi[threadIdx.x] = 0.f;
             acc_lo[threadIdx.x] = 0.f;
         }
-        run_pool<0, OUT_IMAGE, false, SRC>(P, c0, j_begin, j_end, img_hi, img_lo, acc_hi + wbase, acc_lo + wbase,
+        run_pool<0, OUT_IMAGE, false, SRC, FLOOR>(P, c0, j_begin, j_end, img_hi, img_lo, acc_hi + wbase, acc_lo + wbase,
                                            nullptr, st, nullptr);
         if (SRC == SRC_TILE) {
             const int64_t cell = c0 + lane;
@@ -1011,8 +1107,10 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     if (sn.width <= 0 || sn.height <= 0) return fail(DARTS_ERR_INVALID_ARG, "sensor size must be positive");
     if (sn.kind == 0 && (sn.width != 1 || sn.height != 1))
         return fail(DARTS_ERR_INVALID_ARG, "point detector has width = height = 1");
-    if (sc->geom.kind != 0 && sc->geom.kind != 1) return fail(DARTS_ERR_INVALID_ARG, "geometry kind must be 0 or 1");
-    if (sc->geom.kind == 1)
+    if (sc->geom.kind < 0 || sc->geom.kind > 2) return fail(DARTS_ERR_INVALID_ARG, "geometry kind must be 0, 1 or 2");
+    if (sc->geom.kind == 2 && !(sc->geom.floor_albedo >= 0.f && sc->geom.floor_albedo <= 1.f))
+        return fail(DARTS_ERR_INVALID_ARG, "floor albedo must be in [0, 1]");
+    if (sc->geom.kind >= 1)
         for (int a = 0; a < 3; ++a)
             if (!(sc->geom.hi[a] > sc->geom.lo[a])) return fail(DARTS_ERR_INVALID_ARG, "box needs hi > lo");
     if (pr->max_bounces < 1) return fail(DARTS_ERR_INVALID_ARG, "max_bounces must be >= 1");
@@ -1031,7 +1129,9 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
 
     std::memset(&P.em_pos, 0, sizeof P.em_pos);
     P.med = make_medium(sc->medium);
-    P.box = sc->geom.kind;
+    P.box = sc->geom.kind >= 1 ? 1 : 0;
+    P.floor = sc->geom.kind == 2 ? 1 : 0;
+    P.floor_albedo = sc->geom.kind == 2 ? sc->geom.floor_albedo : 0.f;
     for (int a = 0; a < 3; ++a) { P.bx.lo[a] = sc->geom.lo[a]; P.bx.hi[a] = sc->geom.hi[a]; }
     P.n_em = sc->n_emitters;
     for (int j = 0; j < P.n_em; ++j) {
@@ -1112,8 +1212,14 @@ int launch_render(const KParams &P, bool stats, hipStream_t stream)
     const uint64_t blocks = (P.n_waves + kBlock / 64 - 1) / (kBlock / 64);
     if (blocks == 0 || P.n_paths == 0) return ok();
     const dim3 grid((uint32_t)blocks), block(kBlock);
-    if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true>), grid, block, 0, stream, P);
-    else hipLaunchKernelGGL((render_kernel<MODE, OUT, false>), grid, block, 0, stream, P);
+    // scenes without a floor run kernels compiled without its branches
+    if (P.floor) {
+        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, true>), grid, block, 0, stream, P);
+        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, true>), grid, block, 0, stream, P);
+    } else {
+        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, false>), grid, block, 0, stream, P);
+        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, false>), grid, block, 0, stream, P);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "render launch failed: %s", hipGetErrorString(e));
     return ok();
@@ -1223,6 +1329,7 @@ struct darts_batch {
     unsigned *ctr_dev = nullptr;
     hipGraphExec_t exec = nullptr;
     float *graph_hi = nullptr, *graph_lo = nullptr;
+    bool any_floor = false;   // some scene has a floor: the batch runs the floor kernels
 };
 
 namespace {
@@ -1270,12 +1377,23 @@ int launch_batch(const darts_batch *b, float *hi, float *lo, hipStream_t stream)
     B.hi = hi;
     B.lo = lo;
     const dim3 grid(blocks);
-    if (b->plan.block_threads == 64) {
-        if (b->plan.order == DARTS_BATCH_TILES) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 64>), grid, dim3(64), 0, stream, B);
-        else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 64>), grid, dim3(64), 0, stream, B);
+    const bool tiles = b->plan.order == DARTS_BATCH_TILES;
+    if (b->any_floor) {
+        if (b->plan.block_threads == 64) {
+            if (tiles) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 64, true>), grid, dim3(64), 0, stream, B);
+            else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 64, true>), grid, dim3(64), 0, stream, B);
+        } else {
+            if (tiles) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 256, true>), grid, dim3(256), 0, stream, B);
+            else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 256, true>), grid, dim3(256), 0, stream, B);
+        }
     } else {
-        if (b->plan.order == DARTS_BATCH_TILES) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 256>), grid, dim3(256), 0, stream, B);
-        else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 256>), grid, dim3(256), 0, stream, B);
+        if (b->plan.block_threads == 64) {
+            if (tiles) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 64, false>), grid, dim3(64), 0, stream, B);
+            else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 64, false>), grid, dim3(64), 0, stream, B);
+        } else {
+            if (tiles) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 256, false>), grid, dim3(256), 0, stream, B);
+            else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 256, false>), grid, dim3(256), 0, stream, B);
+        }
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
@@ -1437,6 +1555,7 @@ int darts_batch_create(const darts_batch_item *items, int n_items, const darts_b
     auto *b = new darts_batch();
     b->items = std::move(host);
     b->offsets = std::move(offsets);
+    for (const BItem &it : b->items) b->any_floor = b->any_floor || it.P.floor != 0;
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {

@@ -177,6 +177,27 @@ __device__ __forceinline__ float box_exit(const Box &b, V3 x, V3 w)
     return box_exit_inv(b, x, w, V3{rcp(w.x), rcp(w.y), rcp(w.z)});
 }
 
+// True if the ray from x (inside) along w leaves the box through its bottom
+// face z = lo[2] (the opaque floor, when the geometry has one).
+__device__ __forceinline__ bool exits_floor(const Box &b, V3 x, V3 w)
+{
+    if (!(w.z < 0.f)) return false;
+    const float tz = (b.lo[2] - x.z) / w.z;
+    const float tx = w.x > 0.f ? (b.hi[0] - x.x) / w.x : (w.x < 0.f ? (b.lo[0] - x.x) / w.x : kInf);
+    const float ty = w.y > 0.f ? (b.hi[1] - x.y) / w.y : (w.y < 0.f ? (b.lo[1] - x.y) / w.y : kInf);
+    return !(tx < tz) && !(ty < tz);
+}
+
+// Direction leaving a Lambertian floor (normal +z), cosine-weighted:
+// cos theta = sqrt(u1), phi = 2 pi u2.  The BRDF-to-pdf ratio is the albedo.
+__device__ __forceinline__ V3 floor_direction(float u1, float u2)
+{
+    const float ct = hw_sqrt(u1), sn = hw_sqrt(fmaxf(1.f - u1, 0.f));
+    float sp, cp;
+    sincos_rev(u2, sp, cp);
+    return V3{sn * cp, sn * sp, ct};
+}
+
 // Slab test for a ray from x along w; returns false on a miss.
 __device__ __forceinline__ bool box_entry(const Box &b, V3 x, V3 w, float &t_in, float &t_out)
 {

@@ -59,7 +59,7 @@ class _Sensor(C.Structure):
 
 
 class _Geometry(C.Structure):
-    _fields_ = [("kind", C.c_int), ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+    _fields_ = [("kind", C.c_int), ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("floor_albedo", C.c_float)]
 
 
 class _Bins(C.Structure):
@@ -174,7 +174,8 @@ class _SceneHolder:
                                                    float(e.get("power", 1.0))) for e in ems])
         s, g, b = sc["sensor"], sc["geometry"], sc["bins"]
         self.c = _Scene(medium(sc["medium"]),
-                        _Geometry(int(g["kind"]), _f3(g.get("lo", (0, 0, 0))), _f3(g.get("hi", (0, 0, 0)))),
+                        _Geometry(int(g["kind"]), _f3(g.get("lo", (0, 0, 0))), _f3(g.get("hi", (0, 0, 0))),
+                                  float(g.get("floor_albedo", 0.0))),
                         C.cast(self.em, C.POINTER(_Emitter)), len(ems),
                         _Sensor(int(s["kind"]), _f3(s["origin"]), _f3(s.get("dir", (0, 0, -1))),
                                 _f3(s.get("du", (0, 0, 0))), _f3(s.get("dv", (0, 0, 0))),

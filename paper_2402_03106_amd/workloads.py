@@ -156,18 +156,19 @@ def fog_slab() -> dict:
     a slab 10 mean free paths thick (sigma_s = 2, sigma_a = 0.02, g = 0.85,
     so thickness 10 / 2.02) over an opaque Lambertian floor of albedo 0.5 at
     z = 0, laterally 100 units wide (effectively infinite); two pulsed point
-    emitters inside the fog, 1 unit above the floor at x = -1 and x = +1, the
-    second starting 3 length units later; a 256x256 orthographic sensor on the
-    slab's top face over [-4, 4]^2 looking down; 1024 bins over [0, 40); 2^28
-    paths, at most 256 bounces; 64x64x32 direction table, S_max = 40."""
+    emitters 1 unit above the fog at x = -1.5 and x = +1.5, the second starting
+    3 length units later; a 256x256 orthographic sensor on the slab's top face
+    over [-4, 4]^2 looking down; 1024 bins over [0, 40); 2^28 paths, at most
+    256 bounces; 64x64x32 direction table, S_max = 40.  (Emitters outside the
+    medium keep every estimator's variance finite.)"""
     h = 10.0 / 2.02
     return {
         "name": "fog_slab",
         "scene": {
             "medium": {"sigma_s": 2.0, "sigma_a": 0.02, "g": 0.85},
             "geometry": {"kind": 2, "lo": (-50.0, -50.0, 0.0), "hi": (50.0, 50.0, h), "floor_albedo": 0.5},
-            "emitters": [{"pos": (-1.0, 0.0, 1.0), "start": 0.0, "power": 1.0},
-                         {"pos": (1.0, 0.0, 1.0), "start": 3.0, "power": 1.0}],
+            "emitters": [{"pos": (-1.5, 0.0, h + 1.0), "start": 0.0, "power": 1.0},
+                         {"pos": (1.5, 0.0, h + 1.0), "start": 3.0, "power": 1.0}],
             "sensor": {"kind": 1, "origin": (-4.0, -4.0, h), "dir": (0.0, 0.0, -1.0),
                        "du": (8.0, 0.0, 0.0), "dv": (0.0, 8.0, 0.0), "width": 256, "height": 256},
             "bins": {"l_lo": 0.0, "l_hi": 40.0, "n_bins": 1024},
@@ -187,6 +188,24 @@ def fog_slab_small() -> dict:
     w["scene"]["bins"] = {"l_lo": 0.0, "l_hi": 20.0, "n_bins": 64}
     w["params"]["n_paths"] = 1 << 16
     w["dims"] = {"n_cs": 32, "n_s": 32, "n_cos": 32, "s_max": 20.0}
+    return w
+
+
+def fog_slab_fit() -> dict:
+    """The inverse problem on the fog layer: the scene of ``fog_slab`` seen by
+    a 16x16 sensor (0.5-unit pixels) with 128 bins over [0, 40) (512 paths
+    per cell at 2^24 paths per render: the gradient of an L2 loss multiplies
+    two independent per-cell estimates, so its noise falls fast with the
+    paths per cell); the target is rendered at the true medium
+    (sigma_s = 2, g = 0.85) and the fit starts from sigma_s = 1, g = 0.6 with
+    sigma_a = 0.02 known."""
+    w = fog_slab()
+    w["name"] = "fog_slab_fit"
+    w["scene"]["sensor"]["width"] = w["scene"]["sensor"]["height"] = 16
+    w["scene"]["bins"] = {"l_lo": 0.0, "l_hi": 40.0, "n_bins": 128}
+    w["params"]["n_paths"] = 1 << 24
+    w["init_medium"] = {"sigma_s": 1.0, "sigma_a": 0.02, "g": 0.6}
+    w["target_medium"] = dict(w["scene"]["medium"])
     return w
 
 
