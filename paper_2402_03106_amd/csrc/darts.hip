@@ -83,13 +83,21 @@ struct KParams {
     double *grad_out;
     int floor;                  // the box's bottom face is an opaque Lambertian floor
     float floor_albedo;
+    // id-range decomposition (few paths per cell): wave w takes path ids
+    // path_offset + [w unit_paths, (w + 1) unit_paths)
+    uint64_t unit_paths;
 };
 
 constexpr int kBlock = 256;
 // Minimum resident waves per SIMD the render kernel is compiled for (caps its
 // VGPR budget at 512 / waves).
 #ifndef DARTS_RENDER_WAVES_PER_SIMD
-#define DARTS_RENDER_WAVES_PER_SIMD 4
+#define DARTS_RENDER_WAVES_PER_SIMD 6
+#endif
+// The batched kernel keeps more registers (it runs the whole pool per work
+// unit from parameters in constant memory) and is faster at 4.
+#ifndef DARTS_BATCH_WAVES_PER_SIMD
+#define DARTS_BATCH_WAVES_PER_SIMD 4
 #endif
 
 enum { OUT_IMAGE = 0, OUT_PATHS = 1, OUT_GRAD = 2 };
@@ -697,8 +705,16 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
 // compensated global atomic pair per cell.
 typedef __attribute__((address_space(4))) const KParams CKParams;
 
-template <int MODE, int OUT, bool STATS, bool FLOOR>
-__global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_kernel(KParams P_arg)
+// The adjoint keeps three FP64 accumulators per lane: at the image kernels'
+// occupancy it would spill, so it is compiled for 4 waves per SIMD.
+template <int OUT>
+constexpr int render_waves_per_simd()
+{
+    return OUT == OUT_GRAD ? 4 : DARTS_RENDER_WAVES_PER_SIMD;
+}
+
+template <int MODE, int OUT, bool STATS, bool FLOOR, int SRC>
+__global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_kernel(KParams P_arg)
 {
     // the parameter block, read in place in the kernel-argument segment
     (void)P_arg;
@@ -708,11 +724,20 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
     const int wbase = threadIdx.x & ~63;
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const bool have = wave < P.n_waves;
-    const uint64_t tile = have ? wave % P.n_tiles : 0;
-    const uint64_t chunk = have ? wave / P.n_tiles : 0;
-    const int64_t c0 = (int64_t)(P.n_tiles - 1 - tile) * 64;
-    const uint64_t j_begin = chunk * P.chunk_reps * 64;
-    const uint64_t j_end = have ? min((chunk + 1) * P.chunk_reps, P.max_reps) * 64 : j_begin;
+    int64_t c0;
+    uint64_t j_begin, j_end;
+    if (SRC == SRC_TILE) {
+        const uint64_t tile = have ? wave % P.n_tiles : 0;
+        const uint64_t chunk = have ? wave / P.n_tiles : 0;
+        c0 = (int64_t)(P.n_tiles - 1 - tile) * 64;
+        j_begin = chunk * P.chunk_reps * 64;
+        j_end = have ? min((chunk + 1) * P.chunk_reps, P.max_reps) * 64 : j_begin;
+    } else {
+        const uint64_t end = P.path_offset + P.n_paths;
+        j_begin = P.path_offset + (have ? wave : 0) * P.unit_paths;
+        j_end = have ? min(j_begin + P.unit_paths, end) : j_begin;
+        c0 = (int64_t)(j_begin % (uint64_t)P.ncells);
+    }
     acc_hi[threadIdx.x] = 0.f;
     acc_lo[threadIdx.x] = 0.f;
     acc_m2[threadIdx.x] = 0.f;
@@ -721,10 +746,10 @@ __global__ __launch_bounds__(kBlock, DARTS_RENDER_WAVES_PER_SIMD) void render_ke
 #pragma unroll
     for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     double gacc[3] = {0.0, 0.0, 0.0};
-    run_pool<MODE, OUT, STATS, SRC_TILE, FLOOR>(P, c0, j_begin, j_end, nullptr, nullptr, acc_hi + wbase, acc_lo + wbase,
-                                         acc_m2 + wbase, st, gacc);
+    run_pool<MODE, OUT, STATS, SRC, FLOOR>(P, c0, j_begin, j_end, P.hi, P.lo, acc_hi + wbase, acc_lo + wbase,
+                                           acc_m2 + wbase, st, gacc);
 
-    if (MODE == 0 && OUT == OUT_IMAGE && have) {
+    if (SRC == SRC_TILE && MODE == 0 && OUT == OUT_IMAGE && have) {
         const int64_t cell = c0 + lane;
         const float h = acc_hi[threadIdx.x], l = acc_lo[threadIdx.x];
         if (cell < P.ncells) {
@@ -784,7 +809,7 @@ typedef __attribute__((address_space(4))) const BItem CItem;
 typedef __attribute__((address_space(4))) const BUnit CUnit;
 
 template <int SRC, int BLOCK, bool FLOOR>
-__global__ __launch_bounds__(BLOCK, DARTS_RENDER_WAVES_PER_SIMD) void batch_kernel(BParams B)
+__global__ __launch_bounds__(BLOCK, DARTS_BATCH_WAVES_PER_SIMD) void batch_kernel(BParams B)
 {
     __shared__ float acc_hi[BLOCK], acc_lo[BLOCK];
     const int lane = threadIdx.x & 63;
@@ -1090,6 +1115,8 @@ int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &
     return DARTS_OK;
 }
 
+int64_t g_ids_max_reps = 16;         // id ranges when no cell has more repetitions
+constexpr uint64_t kIdsUnit = 2048;   // paths per wave in the id-range decomposition
 int64_t g_target_waves = 1 << 16;   // measured: 4 chunks per tile balance the 2^28-path box frame best
 
 int make_params(const darts_scene *sc, const darts_params *pr, const darts_table *table, KParams &P,
@@ -1197,6 +1224,14 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     if (P.chunk_reps == 0) P.chunk_reps = 1;
     n_chunks = (P.max_reps + P.chunk_reps - 1) / P.chunk_reps;
     P.n_waves = P.n_tiles * n_chunks;
+    // few repetitions per cell: a tile's wave would run a handful of paths per
+    // lane and idle while its longest path finishes, so waves take ranges of
+    // consecutive ids instead (each finished path adds to the image directly)
+    P.unit_paths = 0;
+    if ((int64_t)P.max_reps <= g_ids_max_reps) {
+        P.unit_paths = std::min<uint64_t>(kIdsUnit, nc);
+        P.n_waves = (pr->n_paths + P.unit_paths - 1) / P.unit_paths;
+    }
     if (P.n_waves / (kBlock / 64) > 0x7FFFFFFFull) return fail(DARTS_ERR_INVALID_ARG, "launch too large");
     P.hi = P.lo = P.m2 = nullptr;
     P.stats = nullptr;
@@ -1213,12 +1248,20 @@ int launch_render(const KParams &P, bool stats, hipStream_t stream)
     if (blocks == 0 || P.n_paths == 0) return ok();
     const dim3 grid((uint32_t)blocks), block(kBlock);
     // scenes without a floor run kernels compiled without its branches
-    if (P.floor) {
-        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, true>), grid, block, 0, stream, P);
-        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, true>), grid, block, 0, stream, P);
+    if (P.unit_paths) {
+        if (P.floor) {
+            if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, true, SRC_IDS>), grid, block, 0, stream, P);
+            else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, true, SRC_IDS>), grid, block, 0, stream, P);
+        } else {
+            if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, false, SRC_IDS>), grid, block, 0, stream, P);
+            else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, false, SRC_IDS>), grid, block, 0, stream, P);
+        }
+    } else if (P.floor) {
+        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, true, SRC_TILE>), grid, block, 0, stream, P);
+        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, true, SRC_TILE>), grid, block, 0, stream, P);
     } else {
-        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, false>), grid, block, 0, stream, P);
-        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, false>), grid, block, 0, stream, P);
+        if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, false, SRC_TILE>), grid, block, 0, stream, P);
+        else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, false, SRC_TILE>), grid, block, 0, stream, P);
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "render launch failed: %s", hipGetErrorString(e));
@@ -1735,6 +1778,14 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
     hipLaunchKernelGGL(pointwise_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, (hipStream_t)stream, Q);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "pointwise launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+// Tuning knob (not part of the stable ABI): renders whose cells hold at most
+// this many repetitions use the id-range decomposition (negative: never).
+int darts_set_ids_max_reps(int64_t reps)
+{
+    g_ids_max_reps = reps;
     return ok();
 }
 

@@ -238,3 +238,28 @@ def test_full_size_sampled_cells(D, oracle):
         d = abs(img[c] / 256 - v.mean())
         ok += (d <= 4 * sig + 1e-6 * abs(v.mean())) or (img[c] == 0 and v.sum() == 0)
     assert ok >= len(cells) - 1, (ok, len(cells))
+
+
+@pytest.mark.parametrize("wname,mode,n", [("box_hg_small", "darts", 1 << 16), ("box_hg", "uniform", 1 << 21),
+                                          ("infinite_point", "darts", 1 << 16)])
+def test_tile_and_id_range_decompositions_agree(D, oracle, wname, mode, n):
+    """The two work decompositions of the render kernel (tiles of cells with
+    LDS sums; ranges of path ids with direct atomics) trace the same paths:
+    images agree up to the order of the additions, statistics exactly."""
+    w = W.with_(WORKLOADS[wname](), n_paths=n, path_offset=1234)
+    table, _ = tables(D, oracle, w)
+    sc, pr = w["scene"], w["params"]
+    out = {}
+    try:
+        for name, reps in [("tiles", -1), ("ids", 1 << 40)]:
+            D.set_ids_max_reps(reps)
+            hi, lo, m2, st = D.render_transient(sc, pr, mode, table, want_m2=True, want_stats=True)
+            torch.cuda.synchronize()
+            out[name] = ((hi.double() + lo.double()).cpu().numpy(), m2.double().cpu().numpy(), D.stats_dict(st))
+    finally:
+        D.set_ids_max_reps(16)
+    (a, ma, sa), (b, mb, sb) = out["tiles"], out["ids"]
+    scale = max(np.abs(a).max(), 1e-30)
+    assert np.abs(a - b).max() <= 1e-6 * scale
+    assert np.abs(ma - mb).max() <= 1e-5 * max(np.abs(ma).max(), 1e-30)
+    assert sa == sb
