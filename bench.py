@@ -220,7 +220,9 @@ def main():
 
     if not a.no_mse:
         wall_v, _ = timed("vanilla", 2, 1)
-        thr = {"darts": value, "uniform": out.get("uniform", {}).get("paths_per_s"), "vanilla": 2 * n / wall_v}
+        wall_d, _ = timed("da_only", 2, 1)
+        thr = {"darts": value, "uniform": out.get("uniform", {}).get("paths_per_s"), "vanilla": 2 * n / wall_v,
+               "da_only": 2 * n / wall_d}
         out["time_to_mse"] = {
             "box_hg": time_to_mse(darts, torch, np, w, thr, 1 << 26),
             "infinite_point": time_to_mse(darts, torch, np, W.infinite_point(), None, 1 << 24),
@@ -266,7 +268,7 @@ def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4, k=16):
     nb = n0 // k
     table = darts.build_da_tables(sc["medium"], dm)
     var, m2v, means = {}, {}, {}
-    for mode in ["darts", "uniform", "vanilla"]:
+    for mode in ["darts", "da_only", "uniform", "vanilla"]:
         imgs = []
         for i in range(k):
             pb = dict(pr, n_paths=nb, path_offset=(1 << 40) + i * nb, seed=0xEF)
@@ -301,7 +303,7 @@ def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4, k=16):
             r["paths_per_s"] = thr[mode]
             r["seconds"] = r["paths_needed"] / thr[mode] + t_table
         rep[mode] = r
-    for mode in ["uniform", "vanilla"]:
+    for mode in ["da_only", "uniform", "vanilla"]:
         if "seconds" in rep[mode] and "seconds" in rep["darts"]:
             rep[f"{mode}_over_darts_time"] = rep[mode]["seconds"] / rep["darts"]["seconds"]
         rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
@@ -323,7 +325,7 @@ def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 24, k=16, t
     rep = {"response": "two Gaussian peaks at L = 3.0 and 5.5 (width 0.4, heights 1 and 0.6), zero below 1e-3",
            "target": target, "batches": k, "paths_for_variance": n_var}
     thr, var, means = {}, {}, {}
-    for mode in ["darts", "uniform", "vanilla"]:
+    for mode in ["darts", "da_only", "uniform", "vanilla"]:
         p = dict(pr, n_paths=n_thr)
         hi, lo, _, st = darts.render_transient(sc, p, mode, table, want_stats=True, response=R)
         torch.cuda.synchronize()
@@ -351,7 +353,7 @@ def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 24, k=16, t
         mse_n = float(np.mean(var[mode])) / q95 ** 2
         rep[mode]["mse_times_paths"] = mse_n
         rep[mode]["seconds_to_target"] = mse_n / target / thr[mode]
-    for mode in ["uniform", "vanilla"]:
+    for mode in ["da_only", "uniform", "vanilla"]:
         rep[f"{mode}_over_darts_time"] = rep[mode]["seconds_to_target"] / rep["darts"]["seconds_to_target"]
         rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
     return rep

@@ -1116,7 +1116,8 @@ int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &
 }
 
 int64_t g_ids_max_reps = 16;         // id ranges when no cell has more repetitions
-constexpr uint64_t kIdsUnit = 2048;   // paths per wave in the id-range decomposition
+constexpr uint64_t kIdsUnit = 2048;   // most paths per wave in the id-range decomposition
+constexpr uint64_t kIdsWaves = 16384; // waves the id-range decomposition aims for
 int64_t g_target_waves = 1 << 16;   // measured: 4 chunks per tile balance the 2^28-path box frame best
 
 int make_params(const darts_scene *sc, const darts_params *pr, const darts_table *table, KParams &P,
@@ -1227,9 +1228,12 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     // few repetitions per cell: a tile's wave would run a handful of paths per
     // lane and idle while its longest path finishes, so waves take ranges of
     // consecutive ids instead (each finished path adds to the image directly)
+    // (units of up to kIdsUnit paths, smaller when that would leave fewer
+    // than about kIdsWaves waves to spread over the device)
     P.unit_paths = 0;
     if ((int64_t)P.max_reps <= g_ids_max_reps) {
-        P.unit_paths = std::min<uint64_t>(kIdsUnit, nc);
+        const uint64_t want = (pr->n_paths + kIdsWaves - 1) / kIdsWaves;
+        P.unit_paths = std::min<uint64_t>(nc, std::max<uint64_t>(64, std::min<uint64_t>(kIdsUnit, want)));
         P.n_waves = (pr->n_paths + P.unit_paths - 1) / P.unit_paths;
     }
     if (P.n_waves / (kBlock / 64) > 0x7FFFFFFFull) return fail(DARTS_ERR_INVALID_ARG, "launch too large");
