@@ -61,7 +61,8 @@ typedef struct { float pos[3]; float start; float power; } darts_emitter;
  *           sphere, weight 4 pi); width = height = 1.
  *   kind 1: orthographic radiance sensor; pixel (px, py) covers
  *           origin + [px/width, (px+1)/width) du + [py/height, (py+1)/height) dv;
- *           rays travel along `dir` (need not be normalised). */
+ *           rays travel along `dir` (need not be normalised).
+ * width and height are at most 65535. */
 typedef struct {
     int kind;
     float origin[3], dir[3], du[3], dv[3];
@@ -77,7 +78,8 @@ typedef struct {
 typedef struct { int kind; float lo[3], hi[3]; float floor_albedo; } darts_geometry;
 
 /* n_bins half-open bins of equal width over total path length [l_lo, l_hi),
- * measured from the sensor and including the emitter's start offset. */
+ * measured from the sensor and including the emitter's start offset;
+ * 1 <= n_bins < 2^29. */
 typedef struct { float l_lo, l_hi; int n_bins; } darts_bins;
 
 /* Sensor response W (Eq. (4)): NULL for a time-resolved image (W the

@@ -575,18 +575,20 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
     // bounds); a lane starting a path of cell c0 + sl reads lane sl's
     // description with a cross-lane permute instead of dividing 64-bit
     // indices per path.
-    int my_bin = 0, my_px = 0, my_py = 0;
-    int my_flags = 0;   // bit 0: the cell exists, bit 1: cell < r0, bit 2: cell < r1
+    // packed in two registers: my_bf = bin | flags << 29 (bit 29: the cell
+    // exists, bit 30: cell < r0, bit 31: cell < r1), my_xy = px | py << 16
+    uint32_t my_bf = 0, my_xy = 0;
     float my_gw = 0.f;
     if (SRC == SRC_TILE) {
         const int64_t my_cell = c0 + lane;
         if (j_begin < j_end && my_cell < P.ncells) {
             const int64_t b = my_cell / P.npix;
             const int64_t pix = my_cell - b * P.npix;
-            my_bin = (int)b;
-            my_py = (int)(pix / P.width);
-            my_px = (int)(pix - (int64_t)my_py * P.width);
-            my_flags = 1 | ((uint64_t)my_cell < P.r0 ? 2 : 0) | ((uint64_t)my_cell < P.r1 ? 4 : 0);
+            const uint32_t y = (uint32_t)(pix / P.width);
+            const uint32_t x = (uint32_t)(pix - (int64_t)y * P.width);
+            my_bf = (uint32_t)b | (1u << 29) | ((uint64_t)my_cell < P.r0 ? 1u << 30 : 0u) |
+                    ((uint64_t)my_cell < P.r1 ? 1u << 31 : 0u);
+            my_xy = x | (y << 16);
             if (OUT == OUT_GRAD) my_gw = P.grad_image[my_cell];
         }
     }
@@ -596,36 +598,37 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
     int state = j_begin < j_end ? LANE_NEED : LANE_DONE;
     uint64_t p = 0;
     int slot = 0;
-    int bin = 0, px = 0, py = 0;
     int64_t pixel = 0, cell = 0;
     float grad_w = 0.f;
 
     while (true) {
         const bool want = state == LANE_NEED;
         const uint64_t need = __ballot(want);
+        // the new path's bin and pixel are set and used in the same iteration
+        // (declared here, they are not carried around the loop in registers)
+        int bin = 0, px = 0, py = 0;
         if (need) {
             const uint64_t j = next + (uint64_t)__popcll(need & lanes_below);
             if (SRC == SRC_TILE) {
                 // whole wave active here: the permutes read every lane's description
                 const int sl = (int)(j & 63);
-                const int fl = __shfl(my_flags, sl);
-                const int c_bin = __shfl(my_bin, sl), c_px = __shfl(my_px, sl), c_py = __shfl(my_py, sl);
+                const uint32_t bf = (uint32_t)__shfl((int)my_bf, sl), xy = (uint32_t)__shfl((int)my_xy, sl);
                 const float c_gw = OUT == OUT_GRAD ? __shfl(my_gw, sl) : 0.f;
                 if (want) {
                     if (j >= j_end) {
                         state = LANE_DONE;
                     } else {
                         const uint64_t rep = j >> 6;
-                        const uint64_t m = P.q0 + (uint64_t)((fl >> 1) & 1) + rep;
-                        const uint64_t m_hi = P.q1 + (uint64_t)((fl >> 2) & 1);
-                        if ((fl & 1) && m < m_hi) {
+                        const uint64_t m = P.q0 + (uint64_t)((bf >> 30) & 1u) + rep;
+                        const uint64_t m_hi = P.q1 + (uint64_t)(bf >> 31);
+                        if (((bf >> 29) & 1u) && m < m_hi) {
                             cell = c0 + sl;
                             p = (uint64_t)cell + m * (uint64_t)P.ncells;
                             slot = sl;
-                            bin = c_bin;
-                            px = c_px;
-                            py = c_py;
-                            pixel = (int64_t)c_py * P.width + c_px;
+                            bin = (int)(bf & ((1u << 29) - 1u));
+                            px = (int)(xy & 0xFFFFu);
+                            py = (int)(xy >> 16);
+                            pixel = (int64_t)py * P.width + px;
                             if (OUT == OUT_GRAD) grad_w = c_gw;
                             state = LANE_FRESH;
                         }   // else: an empty slot of a ragged range; pull again next iteration
@@ -1133,6 +1136,9 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     const darts_sensor &sn = sc->sensor;
     if (sn.kind != 0 && sn.kind != 1) return fail(DARTS_ERR_INVALID_ARG, "sensor kind must be 0 or 1");
     if (sn.width <= 0 || sn.height <= 0) return fail(DARTS_ERR_INVALID_ARG, "sensor size must be positive");
+    if (sn.width > 65535 || sn.height > 65535)
+        return fail(DARTS_ERR_INVALID_ARG, "sensor sides are limited to 65535 pixels");
+    if (sc->bins.n_bins >= (1 << 29)) return fail(DARTS_ERR_INVALID_ARG, "n_bins must be below 2^29");
     if (sn.kind == 0 && (sn.width != 1 || sn.height != 1))
         return fail(DARTS_ERR_INVALID_ARG, "point detector has width = height = 1");
     if (sc->geom.kind < 0 || sc->geom.kind > 2) return fail(DARTS_ERR_INVALID_ARG, "geometry kind must be 0, 1 or 2");
