@@ -176,3 +176,19 @@ def test_batch_vs_oracle(D, oracle):
         print(f"{sc['medium']}: rel L2 {rel:.2e}, within 4 sigma {frac:.5f}")
         assert rel <= 0.01, rel
         assert frac >= 0.999, frac
+
+
+def test_batch_with_floor_scenes(D):
+    """Media over a Lambertian floor and plain boxes in one batch (the batch
+    then runs the floor kernel for every scene) equal their separate renders."""
+    ws = W.batched(6, seed=0xF1, lo_log2=10, hi_log2=14)
+    fl = W.fog_slab_small()
+    fl["params"]["n_paths"] = 1 << 14
+    fl2 = W.box_floor_point()
+    fl2["params"]["n_paths"] = 1 << 13
+    items = items_of(D, ws) + items_of(D, [fl, fl2])
+    for plan in PLANS[:3]:
+        b = D.Batch(items, plan)
+        hi, lo = b.empty()
+        b.render(hi, lo)
+        assert_same(batch_images(D, b, hi, lo), separate(D, items))
