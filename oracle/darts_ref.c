@@ -951,7 +951,7 @@ static void trace_forward(const ref_scene *sc, const ref_params *pr, uint64_t p,
 }
 
 /* ------------------------------------------------------------------------- */
-/* Drivers                                                                    */
+/* Entry points                                                               */
 /* ------------------------------------------------------------------------- */
 static int check_args(const ref_scene *sc, const ref_params *pr)
 {
