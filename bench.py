@@ -13,9 +13,10 @@ HBM.  The line also carries
   - `uniform`: the temporally uniform baseline (uniform length-sum
     connection, exponential distance, phase sampling) on the same frame;
   - `time_to_mse`: time to reach MSE <= 1e-4 (cells normalised by the 0.95
-    quantile, as in the paper's parameter study) for DARTS and uniform,
-    from per-cell second moments (both estimators are unbiased, so MSE is
-    their variance, which falls as 1/N).
+    quantile, as in the paper's parameter study) for DARTS at three values
+    of the EDA preference alpha, DA-only, uniform and vanilla, from per-cell
+    variances (all estimators are unbiased, so MSE is their variance, which
+    falls as 1/N).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -143,22 +144,22 @@ def main():
     lo = torch.zeros(shape, dtype=torch.float32, device=dev)
     cdf = torch.empty((dm["n_cs"], dm["n_s"], dm["n_cos"] + 1), dtype=torch.float32, device=dev)
 
-    def step(mode, ev=None):
+    def step(mode, ev=None, params=pr):
         table = darts.build_da_tables(sc["medium"], dm, out=cdf)
         if ev is not None:
             ev[0].record(stream)
-        darts.render_transient(sc, pr, mode, table, hi, lo)
+        darts.render_transient(sc, params, mode, table, hi, lo)
         if ev is not None:
             ev[1].record(stream)
 
-    def timed(mode, steps, warmup):
+    def timed(mode, steps, warmup, params=pr):
         for _ in range(warmup):
-            step(mode)
+            step(mode, None, params)
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t0 = time.perf_counter()
         for i in range(steps):
-            step(mode, evs[i])
+            step(mode, evs[i], params)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kern_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
@@ -219,12 +220,13 @@ def main():
         print(f"[bench] uniform {out['uniform']['paths_per_s']:.4g} paths/s", file=sys.stderr, flush=True)
 
     if not a.no_mse:
-        wall_v, _ = timed("vanilla", 2, 1)
-        wall_d, _ = timed("da_only", 2, 1)
-        thr = {"darts": value, "uniform": out.get("uniform", {}).get("paths_per_s"), "vanilla": 2 * n / wall_v,
-               "da_only": 2 * n / wall_d}
+        thr = {"darts": value, "uniform": out.get("uniform", {}).get("paths_per_s")}
+        for arm, mode, alpha in MSE_ARMS:
+            if not thr.get(arm):
+                wall_x, _ = timed(mode, 2, 1, dict(pr, alpha=alpha))
+                thr[arm] = 2 * n / wall_x
         out["time_to_mse"] = {
-            "box_hg": time_to_mse(darts, torch, np, w, thr, 1 << 26),
+            "box_hg": time_to_mse(darts, torch, np, w, thr, 1 << 28, k=64),
             "infinite_point": time_to_mse(darts, torch, np, W.infinite_point(), None, 1 << 24),
         }
         print(f"[bench] time to MSE {out['time_to_mse']}", file=sys.stderr, flush=True)
@@ -251,15 +253,25 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# Arms of the time-to-MSE study: (name, mode, alpha).  alpha sets the EDA
+# probability gamma = kappa / (kappa + alpha) of Eq. (19); 0.5 is the paper's
+# usual value, the larger ones bound the one-sample MIS weight
+# phase / mixture <= 1 / (1 - gamma) <= 1 + 1/alpha more tightly.
+MSE_ARMS = [("darts", "darts", 0.5), ("darts_alpha2", "darts", 2.0), ("darts_alpha4", "darts", 4.0),
+            ("da_only", "da_only", 0.5), ("uniform", "uniform", 0.5), ("vanilla", "vanilla", 0.5)]
+
+
 def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4, k=16):
     """MSE(N) = mean over cells of Var(cell estimate) / q95^2 (q95: 0.95
-    quantile of the DARTS image, the paper's normalisation before MSE).  All
-    modes are unbiased, so MSE is their variance, which scales as 1/N.  It is
-    estimated from k independent batches of n0/k paths (seed 0xEF, ids disjoint
-    from the timed frames): the per-cell sample variance of the batch images
-    times n0/k is the variance of one path's worth of estimate.  For DARTS and
-    uniform, where a path feeds one cell, the per-path second moments of one
-    n0-path render give a second estimate (`mse_times_paths_m2`); vanilla
+    quantile of the uniform-sampling image, the paper's normalisation before
+    MSE).  All arms are unbiased, so MSE is their variance, which scales as
+    1/N.  It is estimated from k independent batches of n0/k paths (seed 0xEF,
+    ids disjoint from the timed frames): the per-cell sample variance of the
+    batch images times n0/k is the variance of one path's worth of estimate.
+    `max_cell_share` (the largest cell's share of the summed variance) flags
+    a heavy-tailed arm, whose variance estimate is dominated by a few paths.
+    For the arms where a path feeds one cell, the per-path second moments of
+    one n0-path render give a second estimate (`mse_times_paths_m2`); vanilla
     feeds one path into many bins, so only the batch estimate applies.  Wall
     time to the target = N* / measured paths/s + one table build, for the
     workload's throughput `thr` (None: the MSE-per-path products only).  The
@@ -268,54 +280,61 @@ def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4, k=16):
     nb = n0 // k
     table = darts.build_da_tables(sc["medium"], dm)
     var, m2v, means = {}, {}, {}
-    for mode in ["darts", "da_only", "uniform", "vanilla"]:
-        imgs = []
+    for arm, mode, alpha in MSE_ARMS:
+        s1 = s2 = None
         for i in range(k):
-            pb = dict(pr, n_paths=nb, path_offset=(1 << 40) + i * nb, seed=0xEF)
+            pb = dict(pr, n_paths=nb, path_offset=(1 << 40) + i * nb, seed=0xEF, alpha=alpha)
             hi, lo, _, _ = darts.render_transient(sc, pb, mode, table)
             n = darts.paths_per_cell(sc, pb, mode).numpy()
-            imgs.append((hi.double() + lo.double()).cpu().numpy() / np.maximum(n, 1))
-        imgs = np.stack(imgs)
-        means[mode] = imgs.mean(0)
-        var[mode] = imgs.var(0, ddof=1) * nb          # variance of one batch image x paths per batch
+            x = (hi.double() + lo.double()).cpu().numpy() / np.maximum(n, 1)
+            s1 = x if s1 is None else s1 + x
+            s2 = x * x if s2 is None else s2 + x * x
+        means[arm] = s1 / k
+        # variance of one batch image x paths per batch
+        var[arm] = np.maximum(s2 - k * means[arm] ** 2, 0) / (k - 1) * nb
         if mode != "vanilla":
-            p0 = dict(pr, n_paths=n0, path_offset=1 << 40, seed=0xEF)
+            p0 = dict(pr, n_paths=n0, path_offset=1 << 40, seed=0xEF, alpha=alpha)
             hi, lo, m2, _ = darts.render_transient(sc, p0, mode, table, want_m2=True)
             n = darts.paths_per_cell(sc, p0, mode).numpy()
             mean = (hi.double() + lo.double()).cpu().numpy() / np.maximum(n, 1)
             pv = np.maximum(m2.double().cpu().numpy() / np.maximum(n, 1) - mean ** 2, 0)
-            m2v[mode] = pv / np.maximum(n / n0, 1e-300)  # per-path variance / (paths per cell per path)
+            m2v[arm] = pv / np.maximum(n / n0, 1e-300)  # per-path variance / (paths per cell per path)
     torch.cuda.synchronize()
-    q95 = float(np.quantile(means["darts"], 0.95))
+    q95 = float(np.quantile(means["uniform"], 0.95))
     t0 = time.perf_counter()
     darts.build_da_tables(sc["medium"], dm)
     torch.cuda.synchronize()
     t_table = time.perf_counter() - t0
     rep = {"target": target, "q95": q95, "paths_for_variance": n0, "batches": k,
            "note": "extrapolated from measured variance and throughput; vanilla reuses each path for "
-                   "every bin of its pixel (temporal reuse), DARTS and uniform dedicate each path to one bin"}
-    for mode in var:
-        mse_times_n = float(np.mean(var[mode])) / q95 ** 2   # MSE x total paths
-        r = {"mse_times_paths": mse_times_n, "paths_needed": mse_times_n / target}
-        if mode in m2v:
-            r["mse_times_paths_m2"] = float(np.mean(m2v[mode])) / q95 ** 2
-        if thr and thr.get(mode):
-            r["paths_per_s"] = thr[mode]
-            r["seconds"] = r["paths_needed"] / thr[mode] + t_table
-        rep[mode] = r
-    for mode in ["da_only", "uniform", "vanilla"]:
-        if "seconds" in rep[mode] and "seconds" in rep["darts"]:
-            rep[f"{mode}_over_darts_time"] = rep[mode]["seconds"] / rep["darts"]["seconds"]
-        rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
+                   "every bin of its pixel (temporal reuse), the other arms dedicate each path to one bin"}
+    for arm in var:
+        mse_times_n = float(np.mean(var[arm])) / q95 ** 2   # MSE x total paths
+        r = {"alpha": dict((a, al) for a, _, al in MSE_ARMS)[arm], "mse_times_paths": mse_times_n,
+             "paths_needed": mse_times_n / target,
+             "max_cell_share": float(var[arm].max() / max(float(var[arm].sum()), 1e-300))}
+        if arm in m2v:
+            r["mse_times_paths_m2"] = float(np.mean(m2v[arm])) / q95 ** 2
+        if thr and thr.get(arm):
+            r["paths_per_s"] = thr[arm]
+            r["seconds"] = r["paths_needed"] / thr[arm] + t_table
+        rep[arm] = r
+    for arm in var:
+        if arm == "uniform":
+            continue
+        if "seconds" in rep[arm] and "seconds" in rep["uniform"]:
+            rep[f"uniform_over_{arm}_time"] = rep["uniform"]["seconds"] / rep[arm]["seconds"]
+        rep[f"uniform_over_{arm}_mse_per_path"] = rep["uniform"]["mse_times_paths"] / rep[arm]["mse_times_paths"]
     return rep
 
 
-def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 24, k=16, target=1e-4):
+def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 26, k=64, target=1e-4):
     """Two-peak sensor response W on the box workload (one value per pixel,
-    Eq. (4)): throughput of each strategy, the fraction of full path samples
-    the sensor rejects (W = 0 at their length), and time to MSE `target`
-    (0.95-quantile normalised, variance from k independent batches,
-    extrapolated at the measured throughput)."""
+    Eq. (4)): throughput of each arm of the time-to-MSE study, the fraction
+    of full path samples the sensor rejects (W = 0 at their length), and time
+    to MSE `target` (normalised by the 0.95 quantile of the uniform-sampling
+    image, variance from k independent batches, extrapolated at the measured
+    throughput; `max_cell_share` as in time_to_mse)."""
     sc, pr, dm = w["scene"], w["params"], w["dims"]
     resp = W.two_peak_response(sc["bins"])
     R = darts.build_response(resp)
@@ -325,8 +344,8 @@ def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 24, k=16, t
     rep = {"response": "two Gaussian peaks at L = 3.0 and 5.5 (width 0.4, heights 1 and 0.6), zero below 1e-3",
            "target": target, "batches": k, "paths_for_variance": n_var}
     thr, var, means = {}, {}, {}
-    for mode in ["darts", "da_only", "uniform", "vanilla"]:
-        p = dict(pr, n_paths=n_thr)
+    for arm, mode, alpha in MSE_ARMS:
+        p = dict(pr, n_paths=n_thr, alpha=alpha)
         hi, lo, _, st = darts.render_transient(sc, p, mode, table, want_stats=True, response=R)
         torch.cuda.synchronize()
         s = darts.stats_dict(st)
@@ -334,28 +353,31 @@ def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 24, k=16, t
         darts.render_transient(sc, p, mode, table, hi, lo, response=R)
         e1.record(stream)
         torch.cuda.synchronize()
-        thr[mode] = n_thr / (e0.elapsed_time(e1) / 1e3)
-        imgs = []
+        thr[arm] = n_thr / (e0.elapsed_time(e1) / 1e3)
+        s1 = s2 = None
         nb = n_var // k
         for i in range(k):
-            pb = dict(pr, n_paths=nb, path_offset=(1 << 40) + i * nb, seed=0xEF)
+            pb = dict(pr, n_paths=nb, path_offset=(1 << 40) + i * nb, seed=0xEF, alpha=alpha)
             h, l, _, _ = darts.render_transient(sc, pb, mode, table, response=R)
             n = darts.paths_per_cell(sc, pb, mode, response=R).numpy()
-            imgs.append((h.double() + l.double()).cpu().numpy() / np.maximum(n, 1))
-        imgs = np.stack(imgs)
-        means[mode] = imgs.mean(0)
-        var[mode] = imgs.var(0, ddof=1) * nb
-        rep[mode] = {"paths_per_s": thr[mode], "samples": s["samples"], "rejected": s["rejected"],
-                     "rejected_fraction": s["rejected"] / max(s["samples"], 1)}
-    q95 = float(np.quantile(means["darts"], 0.95))
+            x = (h.double() + l.double()).cpu().numpy() / np.maximum(n, 1)
+            s1 = x if s1 is None else s1 + x
+            s2 = x * x if s2 is None else s2 + x * x
+        means[arm] = s1 / k
+        var[arm] = np.maximum(s2 - k * means[arm] ** 2, 0) / (k - 1) * nb
+        rep[arm] = {"alpha": alpha, "paths_per_s": thr[arm], "samples": s["samples"], "rejected": s["rejected"],
+                    "rejected_fraction": s["rejected"] / max(s["samples"], 1),
+                    "max_cell_share": float(var[arm].max() / max(float(var[arm].sum()), 1e-300))}
+    q95 = float(np.quantile(means["uniform"], 0.95))
     rep["q95"] = q95
-    for mode in var:
-        mse_n = float(np.mean(var[mode])) / q95 ** 2
-        rep[mode]["mse_times_paths"] = mse_n
-        rep[mode]["seconds_to_target"] = mse_n / target / thr[mode]
-    for mode in ["da_only", "uniform", "vanilla"]:
-        rep[f"{mode}_over_darts_time"] = rep[mode]["seconds_to_target"] / rep["darts"]["seconds_to_target"]
-        rep[f"{mode}_over_darts_mse_per_path"] = rep[mode]["mse_times_paths"] / rep["darts"]["mse_times_paths"]
+    for arm in var:
+        mse_n = float(np.mean(var[arm])) / q95 ** 2
+        rep[arm]["mse_times_paths"] = mse_n
+        rep[arm]["seconds_to_target"] = mse_n / target / thr[arm]
+    for arm in var:
+        if arm != "uniform":
+            rep[f"uniform_over_{arm}_time"] = rep["uniform"]["seconds_to_target"] / rep[arm]["seconds_to_target"]
+            rep[f"uniform_over_{arm}_mse_per_path"] = rep["uniform"]["mse_times_paths"] / rep[arm]["mse_times_paths"]
     return rep
 
 

@@ -1094,6 +1094,8 @@ Medium make_medium(const darts_medium &m)
     const double D = 1.0 / (3.0 * (m.sigma_a + m.sigma_s * (1.0 - m.g)));
     o.inv4D = (float)(1.0 / (4.0 * D));
     o.ln2_over_sigma_t = (float)(0.69314718055994530942 / (m.sigma_s + m.sigma_a));
+    o.inv4D_log2e = (float)(1.4426950408889634074 / (4.0 * D));
+    o.sigma_a_log2e = (float)(1.4426950408889634074 * m.sigma_a);
     return o;
 }
 

@@ -11,6 +11,7 @@ namespace darts {
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kInv4Pi = 0.0795774715459476679f;   // 1 / (4 pi)
 constexpr float kInf = __builtin_huge_valf();
+constexpr float kLog2e = 1.44269504088896341f;
 
 // Hardware transcendental helpers (gfx950 VALU transcendental unit):
 // v_rcp_f32, v_rsq_f32 and v_sqrt_f32 (1 ulp), v_log_f32 / v_exp_f32 (base 2), and
@@ -46,6 +47,13 @@ __device__ __forceinline__ V3 fma3(V3 x, V3 w, float t) { return V3{fmaf(w.x, t,
 // ---------------------------------------------------------------------------
 struct U4 { uint32_t x, y, z, w; };
 
+// a ^ b ^ c in one gfx950 three-input bit operation (truth table 0x96: the
+// parity of the three input bits)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                      uint32_t k0, uint32_t k1)
 {
@@ -53,7 +61,7 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;   // one 32x32->64 multiply each
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0), n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
     }
@@ -145,16 +153,17 @@ __device__ __forceinline__ float texp_mass(float sigma, float width)   // 1 - e^
 
 // x = -log(1 - mass u) / sigma with mass = 1 - emass, emass = e^{-sigma width},
 // without cancellation: for y = mass u < 1/100 the series
-// y + y^2/2 + y^3/3 + y^4/4 (relative error < y^4/5); for 1/100 <= y < 1/2
-// the logarithm of the rounded 1 - y (relative error < 6e-6); otherwise
-// 1 - mass u = (1 - u) + u emass, a sum of non-negative terms with 1 - u
-// exact (u >= 1/2).  ln2_over_sigma = ln 2 / sigma (log2 hardware result).
+// y + y^2/2 + y^3/3 (relative error < y^3/4 < 2.5e-7), taken in base 2; for
+// 1/100 <= y < 1/2 the logarithm of the rounded 1 - y (relative error
+// < 6e-6); otherwise 1 - mass u = (1 - u) + u emass, a sum of non-negative
+// terms with 1 - u exact (u >= 1/2).  ln2_over_sigma = ln 2 / sigma (the
+// hardware logarithm is base 2).
 __device__ __forceinline__ float texp_sample(float u, float ln2_over_sigma, float mass, float emass)
 {
     const float y = mass * u;
     const float v = y < 0.5f ? 1.f - y : fmaf(u, emass, 1.f - u);
     const float L = log2_hw(v);
-    const float series = y * fmaf(y, fmaf(y, fmaf(y, 0.25f, 0.333333343f), 0.5f), 1.f) * 1.44269504088896341f;
+    const float series = y * fmaf(y, fmaf(y, kLog2e / 3.f, kLog2e / 2.f), kLog2e);
     const float nl = y < 0.01f ? series : -L;
     return nl * ln2_over_sigma;
 }
@@ -227,6 +236,7 @@ struct Medium {
     float sigma_s, sigma_a, sigma_t, inv_sigma_t, albedo, g;
     float inv4D;      // 1 / (4 D), D = 1 / (3 (sigma_a + sigma_s (1 - g)))  (Eq. (9))
     float ln2_over_sigma_t;
+    float inv4D_log2e, sigma_a_log2e;   // the exponent of Eq. (9) in base 2
 };
 
 // log of the DA fluence without its constant -1.5 log(4 pi D) (Eq. (9));
@@ -267,20 +277,30 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
                                              float &d_out, float &factor)
 {
     // Phi_i = (4 pi D s_i)^{-3/2} exp(E_i),  E_i = -r_i^2 / (4 D s_i) - sigma_a s_i:
-    // the weights s_i^{-3/2} exp(E_i - E_max) share one rsq per candidate and
-    // cannot underflow for the candidate with the largest exponent.
+    // the weights s_i^{-3/2} 2^{(E_i - E_max) log2 e} share one rsq per
+    // candidate and cannot underflow for the candidate with the largest
+    // exponent.  The exponents are formed in base 2 (E_i log2 e).
+    //
+    // Candidate uniforms: the radical inverse of 8 row + i is the radical
+    // inverse of 8 row plus that of i (the low three bits of 8 row are zero,
+    // so the bit-reversed parts do not overlap), which leaves one add per
+    // candidate on top of the row's offset.
+    constexpr uint32_t kRev3[8] = {0x00000000u, 0x80000000u, 0x40000000u, 0xC0000000u,
+                                   0x20000000u, 0xA0000000u, 0x60000000u, 0xE0000000u};
+    const uint32_t base = __builtin_bitreverse32(8u * row) + eps;
     float dc[8], q[8], E[8];
     float emax = -kInf;
     const float two_b = 2.f * b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const float ui = sobol_u(row, (uint32_t)i, eps);
+        const float ui = u01(base + kRev3[i]);
         const float di = texp_sample(ui, m.ln2_over_sigma_t, pc, epc);
         const float si = R_hi - di;
         const float r2 = fmaf(di, di - two_b, C2);
+        // s_i > 0 and r_i < s_i in one compare: s_i |s_i| <= 0 <= r_i^2 when s_i <= 0
         const bool valid = (si > 0.f) && (r2 < si * si);
         const float rq = rsq(si);
-        const float e = -fmaf(r2 * m.inv4D, rq * rq, m.sigma_a * si);
+        const float e = -fmaf(r2 * m.inv4D_log2e, rq * rq, m.sigma_a_log2e * si);
         dc[i] = di;
         q[i] = valid ? rq * rq * rq : 0.f;
         E[i] = valid ? e : -kInf;
@@ -290,7 +310,7 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
     float wv[8];
     double wsum = 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { wv[i] = q[i] * fast_exp(E[i] - emax); wsum += (double)wv[i]; }
+    for (int i = 0; i < 8; ++i) { wv[i] = q[i] * exp2_hw(E[i] - emax); wsum += (double)wv[i]; }
     const double target = (double)u_sel * wsum;
     double cum = 0.0;
     float dsel = dc[7], wsel = wv[7];
