@@ -287,7 +287,7 @@ __device__ __forceinline__ float connect_eval(const KParams &P, const Conn &q, f
     mu_c = fminf(fmaxf(dot(q.w, wc), -1.f), 1.f);
     t_out = t;
     r_in_out = r_in;
-    const float f = hg_pdf(mu_c, m.g);
+    const float f = hg_pdf(m.hg, mu_c);
     const float scale = q.scale * f * ir * rcp(den);
     if (texp) {
         // e^{-sigma_t (t + r_in)} / p(S) = (mass / sigma_t) e^{-sigma_t (S_lo - (r - r_in))}
@@ -473,7 +473,7 @@ __device__ __forceinline__ void direction_vanilla(const KParams &P, PathState &s
         s.on_floor = false;
     } else {
         float mu, sn;
-        hg_sample(u01(r0.y), P.med.g, mu, sn);
+        hg_sample(P.med.hg, u01(r0.y), mu, sn);
         s.w = from_frame(s.w, mu, sn, u01(r0.z));
     }
     s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
@@ -509,7 +509,7 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
         // local scattering toward the emitter: phase function in the medium,
         // BRDF times cosine on the floor
         const float f_loc = FLOOR && s.on_floor ? (wc.z > 0.f ? P.floor_albedo * (1.f / kPi) * wc.z : 0.f)
-                                       : hg_pdf(dot(s.w, wc), m.g);
+                                       : hg_pdf(m.hg, dot(s.w, wc));
         const float r_in = P.box ? fminf(r, box_exit(P.bx, s.x, wc)) : r;
         // total length with the emitter's start offset: G_lo = l_lo - start
         const float L = s.Le + r + (P.l_lo - s.G_lo);
@@ -1096,6 +1096,7 @@ Medium make_medium(const darts_medium &m)
     o.ln2_over_sigma_t = (float)(0.69314718055994530942 / (m.sigma_s + m.sigma_a));
     o.inv4D_log2e = (float)(1.4426950408889634074 / (4.0 * D));
     o.sigma_a_log2e = (float)(1.4426950408889634074 * m.sigma_a);
+    o.hg = hg_consts(o.g);
     return o;
 }
 

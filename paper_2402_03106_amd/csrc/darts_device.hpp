@@ -82,31 +82,57 @@ __device__ __forceinline__ float sobol_u(uint32_t row, uint32_t col, uint32_t ep
 // ---------------------------------------------------------------------------
 // Henyey-Greenstein phase function.
 // ---------------------------------------------------------------------------
+// Constants of the phase function for one g, formed once per medium (on the
+// host for a render, so the path loop reads them as scalars).
+struct HG {
+    float g, c0, c1, s;   // den = c0 + c1 (1 - s mu): c0 = (1 - |g|)^2, c1 = 2 |g|, s = sign g
+    float omg, opg;       // 1 - g, 1 + g
+    float two_g, norm;    // 2 g, (1 - g)(1 + g) / (4 pi)
+};
+__host__ __device__ inline HG hg_consts(float g)
+{
+    HG h;
+    const float ag = g >= 0.f ? g : -g;
+    h.g = g;
+    h.c0 = (1.f - ag) * (1.f - ag);
+    h.c1 = 2.f * ag;
+    h.s = g >= 0.f ? 1.f : -1.f;
+    h.omg = 1.f - g;
+    h.opg = 1.f + g;
+    h.two_g = 2.f * g;
+    h.norm = h.omg * h.opg * kInv4Pi;
+    return h;
+}
+
 // 1 + g^2 - 2 g mu is evaluated as a sum of non-negative terms,
 // (1 - g)^2 + 2 g (1 - mu) for g >= 0 and (1 + g)^2 + 2 |g| (1 + mu) for g < 0,
 // so the forward peak keeps full relative precision.
-__device__ __forceinline__ float hg_pdf(float mu, float g)
+__device__ __forceinline__ float hg_pdf(const HG &h, float mu)
 {
-    const float den = g >= 0.f ? fmaf(2.f * g, 1.f - mu, (1.f - g) * (1.f - g))
-                               : fmaf(-2.f * g, 1.f + mu, (1.f + g) * (1.f + g));
+    const float den = fmaf(h.c1, fmaf(-h.s, mu, 1.f), h.c0);
     const float r = rsq(den);
-    return (1.f - g) * (1.f + g) * kInv4Pi * (r * r * r);
+    return h.norm * (r * r * r);
 }
+__device__ __forceinline__ float hg_pdf(float mu, float g) { return hg_pdf(hg_consts(g), mu); }
 
 // Inverse CDF of HG in mu, rewritten without cancellation: with
 // t = 1 - g + 2 g xi and q = (1 - g^2)/t,
 //   1 - mu = (1 - g)(1 - xi)(q + 1 - g)/t,   1 + mu = (1 + g) xi (q + 1 + g)/t,
 // both products of non-negative terms for every |g| < 1 (g = 0 gives
 // mu = 2 xi - 1).
-__device__ __forceinline__ void hg_sample(float xi, float g, float &mu, float &sin_t)
+__device__ __forceinline__ void hg_sample(const HG &h, float xi, float &mu, float &sin_t)
 {
-    const float t = fmaf(2.f * g, xi, 1.f - g);
+    const float t = fmaf(h.two_g, xi, h.omg);
     const float it = rcp(t);
-    const float q = (1.f - g) * (1.f + g) * it;
-    const float omu = (1.f - g) * (1.f - xi) * (q + 1.f - g) * it;
-    const float opu = (1.f + g) * xi * (q + 1.f + g) * it;
+    const float q = h.omg * h.opg * it;
+    const float omu = h.omg * (1.f - xi) * (q + 1.f - h.g) * it;
+    const float opu = h.opg * xi * (q + 1.f + h.g) * it;
     mu = fminf(fmaxf(0.5f * (opu - omu), -1.f), 1.f);
     sin_t = hw_sqrt(fmaxf(omu * opu, 0.f));
+}
+__device__ __forceinline__ void hg_sample(float xi, float g, float &mu, float &sin_t)
+{
+    hg_sample(hg_consts(g), xi, mu, sin_t);
 }
 
 // Orthonormal basis completing unit n (Duff et al., JCGT 2017, branchless).
@@ -237,6 +263,7 @@ struct Medium {
     float inv4D;      // 1 / (4 D), D = 1 / (3 (sigma_a + sigma_s (1 - g)))  (Eq. (9))
     float ln2_over_sigma_t;
     float inv4D_log2e, sigma_a_log2e;   // the exponent of Eq. (9) in base 2
+    HG hg;
 };
 
 // log of the DA fluence without its constant -1.5 log(4 pi D) (Eq. (9));
@@ -374,11 +401,11 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
         s = hw_sqrt(fmaxf((1.f - mu) * (1.f + mu), 0.f));
         axis = a;
     } else {
-        hg_sample(u1, m.g, mu, s);
+        hg_sample(m.hg, u1, mu, s);
         axis = w_prev;
     }
     const V3 w = from_frame(axis, mu, s, u2);
-    const float p_hg = hg_pdf(dot(w_prev, w), m.g);
+    const float p_hg = hg_pdf(m.hg, dot(w_prev, w));
     float p_mix = p_hg;
     if (gam > 0.f) {
         if (!eda_branch) {
