@@ -314,14 +314,29 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
     // candidate on top of the row's offset.
     constexpr uint32_t kRev3[8] = {0x00000000u, 0x80000000u, 0x40000000u, 0xC0000000u,
                                    0x20000000u, 0xA0000000u, 0x60000000u, 0xE0000000u};
+    //
+    // Candidate distance d = -ln(1 - pc u) / sigma_t (Eq. (14)) from the
+    // 24-bit integer k of u = k 2^-24, without cancellation:
+    //  - where v = fl(1 - pc u) >= 1/2, one fma gives v and a second its
+    //    rounding error e = (1 - v) - pc u (1 - v is exact there), and
+    //    ln(1 - pc u) = ln(v + e) = ln v + e (error below 2^-24 of the result,
+    //    also for pc u -> 0, where ln v alone would lose the low bits);
+    //  - otherwise u > 1/2 and 1 - pc u = (1 - u) + u e^{-sigma_t d_m}, a sum
+    //    of non-negative terms with 1 - u exact, rounded once.
     const uint32_t base = __builtin_bitreverse32(8u * row) + eps;
+    const float pc24 = pc * 0x1p-24f, em24 = epc * 0x1p-24f;
     float dc[8], q[8], E[8];
     float emax = -kInf;
     const float two_b = 2.f * b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const float ui = u01(base + kRev3[i]);
-        const float di = texp_sample(ui, m.ln2_over_sigma_t, pc, epc);
+        const float k = (float)((base + kRev3[i]) >> 8);
+        const float va = fmaf(-pc24, k, 1.f);
+        const float ea = fmaf(-pc24, k, 1.f - va);
+        const float vb = fmaf(k, em24, fmaf(k, -0x1p-24f, 1.f));
+        const bool near = va >= 0.5f;
+        const float L = fmaf(near ? ea : 0.f, kLog2e, log2_hw(near ? va : vb));   // log2(1 - pc u)
+        const float di = -L * m.ln2_over_sigma_t;
         const float si = R_hi - di;
         const float r2 = fmaf(di, di - two_b, C2);
         // s_i > 0 and r_i < s_i in one compare: s_i |s_i| <= 0 <= r_i^2 when s_i <= 0
