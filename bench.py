@@ -153,6 +153,10 @@ def main():
             ev[1].record(stream)
 
     def timed(mode, steps, warmup, params=pr):
+        # every arm starts from a cleared image (outside the timed region), so
+        # its frames accumulate into the same state whatever ran before
+        hi.zero_()
+        lo.zero_()
         for _ in range(warmup):
             step(mode, None, params)
         torch.cuda.synchronize()
