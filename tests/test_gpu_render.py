@@ -89,6 +89,22 @@ def test_per_path_parity(D, oracle, wname, mode, n):
     assert np.mean((g != 0) == (o != 0)) >= 0.995
 
 
+@pytest.mark.parametrize("alpha", [0.0, 2.0, 4.0])
+def test_per_path_parity_alpha(D, oracle, alpha):
+    """The EDA preference alpha of Eq. (19) away from 0.5: at 0 every
+    direction with C > 0 comes from the table (gamma = 1), at 2 and 4 the
+    phase function dominates."""
+    w = W.with_(W.box_hg_small(), n_paths=1 << 16, alpha=alpha)
+    table, cdf = tables(D, oracle, w)
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    g = D.render_paths(sc, pr, "darts", table).cpu().numpy().astype(np.float64)
+    o, _ = oracle.render_paths(sc, pr, "darts", cdf, dm)
+    close = np.abs(g - o) <= 1e-3 * np.abs(o) + 1e-30
+    print(f"alpha {alpha}: {close.mean():.5f} of paths agree; nonzero {np.mean(o != 0):.3f}")
+    assert close.mean() >= 0.99
+    assert np.mean((g != 0) == (o != 0)) >= 0.995
+
+
 @pytest.mark.parametrize("wname,mode", [
     ("infinite_point", "darts"), ("infinite_point", "uniform"), ("infinite_point", "vanilla"),
     ("box_hg", "darts"), ("box_hg", "uniform"),

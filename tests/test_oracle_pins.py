@@ -367,7 +367,8 @@ def test_table_layout(oracle):
 # --------------------------------------------------------------------------
 # Direction sampling with one-sample MIS (Section V-A, Eq. 19)
 # --------------------------------------------------------------------------
-def _direction_moments(oracle, med, dims, cdf, x, xe, wprev, S, mutation=0, n=60000, seed=5):
+def _direction_moments(oracle, med, dims, cdf, x, xe, wprev, S, mutation=0, n=60000, seed=5, alpha=0.5,
+                       with_se=False):
     L = oracle.lib()
     rng = np.random.default_rng(seed)
     m, dd = C.byref(oracle.medium(med)), C.byref(oracle.dims(dims))
@@ -377,17 +378,28 @@ def _direction_moments(oracle, med, dims, cdf, x, xe, wprev, S, mutation=0, n=60
     wo, wt, eb = _vec([0, 0, 0]), C.c_double(), C.c_int()
     xv, ev, pv = _vec(x), _vec(xe), _vec(wprev)
     acc = np.zeros(3)
+    acc2 = np.zeros(3)
     U = rng.random((n, 4))
     for i in range(n):
-        L.ref_sample_direction(m, dd, cp, 0.5, 1, xv, ev, pv, S, (C.c_double * 4)(*U[i]), wo, C.byref(wt), C.byref(eb), mutation)
+        L.ref_sample_direction(m, dd, cp, alpha, 1, xv, ev, pv, S, (C.c_double * 4)(*U[i]), wo, C.byref(wt), C.byref(eb), mutation)
         mu = np.dot(np.array(wo[:]), a)
-        acc += wt.value * np.array([1.0, mu, mu * mu])
-    return acc / n
+        v = wt.value * np.array([1.0, mu, mu * mu])
+        acc += v
+        acc2 += v * v
+    mean = acc / n
+    if with_se:
+        return mean, np.sqrt(np.maximum(acc2 / n - mean * mean, 0.0) / n)
+    return mean
 
 
-def test_direction_mis_is_unbiased(oracle):
+@pytest.mark.parametrize("alpha,n", [(0.5, 60000), (4.0, 60000), (0.0, 200000)])
+def test_direction_mis_is_unbiased(oracle, alpha, n):
     """E[weight h(w)] = int p_HG(w_prev.w) h(w) dw: for h = 1, a.w and (a.w)^2
-    the right side is 1, g (a.w_prev) and (1 + 2 g^2 P2(a.w_prev))/3."""
+    the right side is 1, g (a.w_prev) and (1 + 2 g^2 P2(a.w_prev))/3.  At
+    alpha = 0 every direction comes from the EDA table (gamma = 1), which
+    covers every cos bin of this row; the weight p_HG / p_EDA then reaches
+    ~30 on the phase function's forward peak, so that case is held to four
+    standard errors of its own sample."""
     w = W.box_hg_small()
     med = w["scene"]["medium"]
     _, cdf = oracle.build_table(med, w["dims"])
@@ -400,8 +412,11 @@ def test_direction_mis_is_unbiased(oracle):
     c = float(np.dot(a, wprev))
     g = med["g"]
     exact = np.array([1.0, g * c, (1 + 2 * g * g * 0.5 * (3 * c * c - 1)) / 3])
-    est = _direction_moments(oracle, med, w["dims"], cdf, x, xe, list(wprev), S=Cd * 1.6)
-    assert np.max(np.abs(est - exact)) < 0.01, (est, exact)
+    est, se = _direction_moments(oracle, med, w["dims"], cdf, x, xe, list(wprev), S=Cd * 1.6, alpha=alpha, n=n,
+                                 with_se=True)
+    assert np.all(np.abs(est - exact) < 4 * se), (est, exact, se)
+    if alpha > 0:
+        assert np.max(np.abs(est - exact)) < 0.01, (est, exact)
 
 
 # --------------------------------------------------------------------------
@@ -472,13 +487,15 @@ def _box_point(oracle, mode, n, seed=0xB0, **kw):
     return mean.ravel(), se.ravel(), st
 
 
-@pytest.mark.parametrize("mode", ["darts", "uniform", "vanilla", "da_only", "eda_only"])
-def test_estimators_agree_all_orders(oracle, mode):
+@pytest.mark.parametrize("mode,alpha", [("darts", 0.5), ("uniform", 0.5), ("vanilla", 0.5), ("da_only", 0.5),
+                                        ("eda_only", 0.5), ("darts", 4.0)])
+def test_estimators_agree_all_orders(oracle, mode, alpha):
     """Box medium, emitter and point detector outside it (bounded weights):
-    DARTS, the uniform-S baseline, vanilla path tracing and both ablation
-    arms against the forward analog walk, which shares no sampling step."""
+    DARTS (at the paper's usual EDA preference and at a larger one), the
+    uniform-S baseline, vanilla path tracing and both ablation arms against
+    the forward analog walk, which shares no sampling step."""
     mf, sf, _ = _box_point(oracle, "forward", 1 << 22)
-    m, s, _ = _box_point(oracle, mode, 1 << 21)
+    m, s, _ = _box_point(oracle, mode, 1 << 21, alpha=alpha)
     # bins both estimators resolve (relative standard error below 15%)
     ok = (sf > 0) & (s > 0) & (sf < 0.15 * np.abs(mf)) & (s < 0.15 * np.abs(m))
     z = (m - mf)[ok] / np.sqrt(s ** 2 + sf ** 2)[ok]
