@@ -16,7 +16,9 @@ HBM.  The line also carries
     quantile, as in the paper's parameter study) for DARTS at three values
     of the EDA preference alpha, DA-only, uniform and vanilla, from per-cell
     variances (all estimators are unbiased, so MSE is their variance, which
-    falls as 1/N).
+    falls as 1/N);
+  - `time_gated`: the same for single time-gated frames of the box workload
+    at three gates, each normalised by its own 0.95 quantile.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -233,7 +235,9 @@ def main():
             "box_hg": time_to_mse(darts, torch, np, w, thr, 1 << 28, k=64),
             "infinite_point": time_to_mse(darts, torch, np, W.infinite_point(), None, 1 << 24),
         }
+        out["time_gated"] = time_gated(darts, torch, np, W)
         print(f"[bench] time to MSE {out['time_to_mse']}", file=sys.stderr, flush=True)
+        print(f"[bench] time-gated {out['time_gated']}", file=sys.stderr, flush=True)
     if not a.no_response:
         out["response"] = response_bench(darts, torch, np, W, w)
         print(f"[bench] response {out['response']}", file=sys.stderr, flush=True)
@@ -329,6 +333,61 @@ def time_to_mse(darts, torch, np, w, thr, n0, target=1e-4, k=16):
         if "seconds" in rep[arm] and "seconds" in rep["uniform"]:
             rep[f"uniform_over_{arm}_time"] = rep["uniform"]["seconds"] / rep[arm]["seconds"]
         rep[f"uniform_over_{arm}_mse_per_path"] = rep["uniform"]["mse_times_paths"] / rep[arm]["mse_times_paths"]
+    return rep
+
+
+GATES = (3.0, 6.0, 10.0)
+
+
+def time_gated(darts, torch, np, W, gates=GATES, width=0.15625, n_thr=1 << 26, k=32, nb=1 << 22, target=1e-4):
+    """Time-gated frames of the box workload, the form of the paper's
+    evaluation (Section VI-B): one frame per gate [L0, L0 + width) (64x64
+    pixels, one bin, every path of the DARTS family dedicated to it), each
+    normalised by its own 0.95 quantile (of the uniform-sampling frame)
+    before MSE.  Per arm: throughput on that frame, MSE x paths from k
+    independent batches of nb paths, the largest pixel's share of the
+    variance, and time to MSE `target` (extrapolated)."""
+    rep = {"width": width, "batches": k, "paths_for_variance": k * nb, "target": target}
+    for L0 in gates:
+        w = W.box_hg()
+        w["scene"]["bins"] = {"l_lo": L0, "l_hi": L0 + width, "n_bins": 1}
+        sc, pr, dm = w["scene"], w["params"], w["dims"]
+        table = darts.build_da_tables(sc["medium"], dm)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        arms, means = {}, {}
+        for arm, mode, alpha in MSE_ARMS:
+            p = dict(pr, n_paths=n_thr, alpha=alpha)
+            hi, lo, _, _ = darts.render_transient(sc, p, mode, table)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            darts.render_transient(sc, p, mode, table, hi, lo)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            thr = n_thr / (e0.elapsed_time(e1) / 1e3)
+            s1 = s2 = None
+            for i in range(k):
+                pb = dict(pr, n_paths=nb, path_offset=(1 << 40) + i * nb, seed=0xEF, alpha=alpha)
+                h, l, _, _ = darts.render_transient(sc, pb, mode, table)
+                n = darts.paths_per_cell(sc, pb, mode).numpy()
+                x = (h.double() + l.double()).cpu().numpy() / np.maximum(n, 1)
+                s1 = x if s1 is None else s1 + x
+                s2 = x * x if s2 is None else s2 + x * x
+            means[arm] = s1 / k
+            v = np.maximum(s2 - k * means[arm] ** 2, 0) / (k - 1) * nb
+            arms[arm] = {"alpha": alpha, "paths_per_s": thr, "var": float(v.mean()),
+                         "max_cell_share": float(v.max() / max(float(v.sum()), 1e-300))}
+        q95 = float(np.quantile(means["uniform"], 0.95))
+        g = {"q95": q95}
+        for arm, r in arms.items():
+            mse_n = r.pop("var") / q95 ** 2
+            r["mse_times_paths"] = mse_n
+            r["seconds_to_target"] = mse_n / target / r["paths_per_s"]
+            g[arm] = r
+        for arm in arms:
+            if arm != "uniform":
+                g[f"uniform_over_{arm}_time"] = g["uniform"]["seconds_to_target"] / g[arm]["seconds_to_target"]
+        rep[f"gate_{L0:g}"] = g
     return rep
 
 
