@@ -618,12 +618,21 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
     double mu = dot3(ps->w, de) / C;          /* cos to the focal axis */
     double R_lo = ps->G_lo - ps->Le, R_hi = ps->G_hi - ps->Le;
     /* Largest reachable length sum: control vertex still inside the medium
-     * (Section V-B, case II with the boundary clipping S_M). */
+     * (Section V-B, case II with the boundary clipping S_M), S_exit = d_m + |b|
+     * with b = x + w d_m - x_e.  By the law of cosines |b|^2 - (C - d_m)^2 =
+     * 2 d_m C (1 - mu), so for C >= d_m S_exit - C = 2 d_m C (1 - mu) /
+     * (|b| + C - d_m), free of the cancellation of d_m + |b| - C when the ray
+     * points at an emitter outside the medium; C (1 - mu) is formed as
+     * C |w - a|^2 / 2 (a = de / C). */
     double S_exit = INFINITY;
     if (!isinf(dm)) {
-        double pb[3];
+        double pb[3], dw[3];
         axpy3(ps->x, ps->w, dm, pb);
-        S_exit = dm + dist3(pb, ps->em->pos);
+        double bl = dist3(pb, ps->em->pos), cd = C - dm;
+        for (int i = 0; i < 3; ++i) dw[i] = ps->w[i] - de[i] / C;
+        double cm = 0.5 * C * dot3(dw, dw);
+        if (cd >= 0.0) S_exit = (bl + cd > 0.0) ? C + 2.0 * dm * cm / (bl + cd) : C;
+        else S_exit = C + (bl - cd);
     }
     double S_lo = fmax(R_lo, C), S_hi = fmin(R_hi, S_exit);
     if (!(S_lo < S_hi)) return 0.0;
@@ -637,6 +646,11 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
         pS = 1.0 / width;
     }
     double t = ref_ell_t(S, C, mu);
+    /* The control vertex lies on the ray inside the medium: t <= d_m, the
+     * same condition as S <= S_exit in exact arithmetic; a length sum that
+     * rounding places past S_exit (rays aimed almost at an emitter outside
+     * the medium) would put it beyond the boundary. */
+    if (!(t <= dm)) return 0.0;
     double r = S - t;
     double pt = ref_ell_pdf_t(pS, S, C, mu, t, pr->mutation == REF_MUT_PRINTED_JACOBIAN);
     double xc[3], wc[3], dv[3];

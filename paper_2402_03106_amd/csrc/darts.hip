@@ -234,15 +234,43 @@ struct Conn {
     float S_lo, S_hi; // length-sum range
     float scale;      // throughput times emitter intensity / selection probability
     float u;          // uniform for S
+    float dm;         // distance along the ray to the medium boundary
 };
 
+// cm = C (1 - mu) = C |w - a|^2 / 2, mu the cosine between the ray and the
+// unit vector a to the emitter: no cancellation when the ray points almost
+// at the emitter.
+__device__ __forceinline__ float focal_cm(V3 x, V3 w, V3 xe, float C)
+{
+    const V3 dw = w - (xe - x) * rcp(C);
+    return 0.5f * C * dot(dw, dw);
+}
+
 // Range of the length sum; false if no control vertex can close the path.
+//
+// The largest sum keeps the control vertex inside the medium: S_exit = d_m +
+// |b|, b = x + w d_m - x_e.  When the ray points at an emitter outside the
+// medium, d_m + |b| - C cancels, and one ulp of rounding would open a range
+// in which the ellipse is degenerate and 1 / (S - C mu) explodes.  By the law
+// of cosines |b|^2 - (C - d_m)^2 = 2 d_m cm, so for C >= d_m
+//   S_exit - C = 2 d_m cm / (|b| + C - d_m),
+// which has no cancellation; it is used where the plain sum leaves less than
+// 2^-10 C above C (elsewhere the two agree to rounding).  For C < d_m the
+// plain sum has no cancellation.
 __device__ __forceinline__ bool connect_range(const KParams &P, const PathState &s, float &S_lo, float &S_hi)
 {
     if (!(s.C > 0.f)) return false;
     const float R_lo = s.G_lo - s.Le, R_hi = s.G_hi - s.Le;
     float S_exit = kInf;
-    if (P.box) S_exit = s.dm + length(fma3(s.x, s.w, s.dm) - s.xe);
+    if (P.box) {
+        const float bl = length(fma3(s.x, s.w, s.dm) - s.xe);
+        const float cd = s.C - s.dm;
+        S_exit = s.dm + bl;
+        if (cd >= 0.f && S_exit - s.C < 0x1p-10f * s.C) {
+            const float den = bl + cd;
+            S_exit = den > 0.f ? s.C + 2.f * s.dm * focal_cm(s.x, s.w, s.xe, s.C) * rcp(den) : s.C;
+        }
+    }
     S_lo = fmaxf(R_lo, s.C);
     S_hi = fminf(R_hi, S_exit);
     return S_lo < S_hi;
@@ -253,12 +281,8 @@ __device__ __forceinline__ bool connect_range(const KParams &P, const PathState 
 __device__ __forceinline__ float connect_eval(const KParams &P, const Conn &q, float &mu_c, float &t_out, float &r_in_out)
 {
     const Medium &m = P.med;
-    const V3 de = q.xe - q.x;
     const float C = q.C;
-    // cm = C (1 - mu) = C |w - a|^2 / 2 with a the unit vector to the emitter:
-    // no cancellation when the ray points almost at the emitter
-    const V3 dw = q.w - de * rcp(C);
-    const float cm = 0.5f * C * dot(dw, dw);
+    const float cm = focal_cm(q.x, q.w, q.xe, C);
     const float W = q.S_hi - q.S_lo;
     const bool texp = (P.flags & DARTS_ELL_TEXP) != 0;
     float S, mass = 0.f;
@@ -275,6 +299,10 @@ __device__ __forceinline__ float connect_eval(const KParams &P, const Conn &q, f
     t_out = 0.f;
     r_in_out = 0.f;
     if (!(den > 0.f) || !(r > 0.f)) return 0.f;
+    // the control vertex lies on the ray inside the medium (t <= d_m is the
+    // same condition as S <= S_exit): a sum that rounding of S_exit still
+    // lets past it would place the vertex beyond the boundary
+    if (!(t <= q.dm)) return 0.f;
     const V3 xc = fma3(q.x, q.w, t);
     const float ir = rcp(r);
     // unit direction from the control vertex to the emitter, normalised from
@@ -304,7 +332,7 @@ __device__ float connect(const KParams &P, const PathState &s, float u4, float *
     Conn q;
     if (!connect_range(P, s, q.S_lo, q.S_hi)) return 0.f;
     st.inc(DARTS_ST_SAMPLES);   // a full path sample, its length inside the target bin
-    q.x = s.x; q.w = s.w; q.xe = s.xe; q.C = s.C; q.scale = s.beta * s.em_scale; q.u = u4;
+    q.x = s.x; q.w = s.w; q.xe = s.xe; q.C = s.C; q.scale = s.beta * s.em_scale; q.u = u4; q.dm = s.dm;
     float mu_c, t, r_in;
     const float c = connect_eval(P, q, mu_c, t, r_in);
     if (dlog) {

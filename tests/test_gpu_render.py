@@ -89,6 +89,31 @@ def test_per_path_parity(D, oracle, wname, mode, n):
     assert np.mean((g != 0) == (o != 0)) >= 0.995
 
 
+def test_ray_aimed_at_an_emitter_outside_the_medium(D, oracle):
+    """Regression: on the early time gate of the box workload a DARTS path
+    (alpha = 4, seed 0xEF, id 1099556017750) reaches, after a table-sampled
+    direction at C/S ~ 1, a ray that points at the emitter (0.5 above the
+    box) to FP32 precision.  There the exact length-sum range is empty
+    (S_exit = C); computed as d_m + |b| it rounded one ulp above C, the
+    connection sampled that ulp with S - C mu ~ 3e-16 and the path was worth
+    4e5 times the mean.  The path and the 2^16 around it agree with the
+    oracle path by path, and no path of the chunk exceeds the oracle's
+    largest value."""
+    w = W.box_hg()
+    w["scene"]["bins"] = {"l_lo": 3.0, "l_hi": 3.15625, "n_bins": 1}
+    pid, k = 1099556017750, 4321
+    w = W.with_(w, n_paths=1 << 16, path_offset=pid - k, seed=0xEF, alpha=4.0)
+    table, cdf = tables(D, oracle, w)
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    g = D.render_paths(sc, pr, "darts", table).cpu().numpy().astype(np.float64)
+    o, _ = oracle.render_paths(sc, pr, "darts", cdf, dm)
+    print(f"path {pid}: gpu {g[k]:.6g} oracle {o[k]:.6g}; chunk max gpu {g.max():.4g} oracle {o.max():.4g}")
+    assert abs(g[k] - o[k]) <= 1e-3 * abs(o[k])
+    close = np.abs(g - o) <= 1e-3 * np.abs(o) + 1e-30
+    assert close.mean() >= 0.99
+    assert g.max() <= 1.01 * o.max()
+
+
 @pytest.mark.parametrize("alpha", [0.0, 2.0, 4.0])
 def test_per_path_parity_alpha(D, oracle, alpha):
     """The EDA preference alpha of Eq. (19) away from 0.5: at 0 every
