@@ -339,8 +339,7 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
         const float di = -L * m.ln2_over_sigma_t;
         const float si = R_hi - di;
         const float r2 = fmaf(di, di - two_b, C2);
-        // s_i > 0 and r_i < s_i in one compare: s_i |s_i| <= 0 <= r_i^2 when s_i <= 0
-        const bool valid = (si > 0.f) && (r2 < si * si);
+        const bool valid = (si > 0.f) && (r2 < si * si);   // inside the residual-time ellipsoid
         const float rq = rsq(si);
         const float e = -fmaf(r2 * m.inv4D_log2e, rq * rq, m.sigma_a_log2e * si);
         dc[i] = di;
