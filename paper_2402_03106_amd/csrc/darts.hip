@@ -92,7 +92,7 @@ constexpr int kBlock = 256;
 // Minimum resident waves per SIMD the render kernel is compiled for (caps its
 // VGPR budget at 512 / waves).
 #ifndef DARTS_RENDER_WAVES_PER_SIMD
-#define DARTS_RENDER_WAVES_PER_SIMD 6
+#define DARTS_RENDER_WAVES_PER_SIMD 7
 #endif
 // The batched kernel keeps more registers (it runs the whole pool per work
 // unit from parameters in constant memory) and is faster at 4.
