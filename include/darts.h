@@ -283,7 +283,8 @@ int darts_batch_render(darts_batch *batch, float *image_hi_dev, float *image_lo_
  * launched on `stream` afterwards. */
 int darts_batch_graph_launch(darts_batch *batch, float *image_hi_dev, float *image_lo_dev, void *stream);
 
-/* Time candidate plans (orders x block sizes x grid sizes x unit sizes), each
+/* Time candidate plans (tile and id orders x 64 and 256 threads per block x
+ * 16 and 32 waves per CU x units of 512, 1024, 2048, 8192 and 32768 paths), each
  * one warm-up launch plus `reps` timed launches on `stream` into the given
  * images (used as scratch: their contents are overwritten), keep the fastest
  * and return it with its mean launch time in ms.  Synchronous. */

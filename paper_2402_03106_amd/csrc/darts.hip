@@ -1751,7 +1751,7 @@ int darts_batch_autotune(darts_batch *batch, float *image_hi_dev, float *image_l
     for (int order : {DARTS_BATCH_TILES, DARTS_BATCH_IDS})
         for (int bt : {64, 256})
             for (int wpc : {16, 32})
-                for (int64_t up : {(int64_t)2048, (int64_t)8192, (int64_t)32768}) {
+                for (int64_t up : {(int64_t)512, (int64_t)1024, (int64_t)2048, (int64_t)8192, (int64_t)32768}) {
                     if (rc != DARTS_OK) break;
                     darts_batch_plan pl{order, bt, wpc, up};
                     if ((rc = upload_units(batch, pl)) != DARTS_OK) break;
