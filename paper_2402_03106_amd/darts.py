@@ -156,6 +156,16 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _hold(t: torch.Tensor, stream) -> torch.Tensor:
+    """A contiguous tensor whose memory stays reserved for work queued on
+    `stream` (the caching allocator otherwise only orders reuse against the
+    stream the tensor was allocated on)."""
+    c = t.contiguous()
+    if stream is not None and stream != torch.cuda.current_stream(c.device):
+        c.record_stream(stream)
+    return c
+
+
 def _f3(v):
     return (C.c_float * 3)(*[float(x) for x in v])
 
@@ -304,8 +314,9 @@ def render_transient_backward(sc: dict, p: dict, mode, table: Table | None, grad
         grad_out = torch.zeros(3, dtype=torch.float64, device=grad_image.device)
     h = _SceneHolder(sc, response)
     tb = C.byref(table.c_struct()) if table is not None else None
+    gi = _hold(grad_image, stream)
     _check(lib().darts_render_transient_backward(C.byref(h.c), C.byref(params(p, mode)), tb,
-                                                 _ptr(grad_image.contiguous()), _ptr(grad_out), _stream(stream)))
+                                                 _ptr(gi), _ptr(grad_out), _stream(stream)))
     return grad_out
 
 
@@ -316,8 +327,8 @@ def debug_pointwise(fn: str, inputs: torch.Tensor, med: dict | None = None, tabl
     out = torch.zeros((inputs.shape[0], PW_OUT), dtype=torch.float32, device=inputs.device)
     m = C.byref(medium(med)) if med is not None else None
     tb = C.byref(table.c_struct()) if table is not None else None
-    _check(lib().darts_debug_pointwise(PW[fn], _ptr(inputs.contiguous()), _ptr(out), inputs.shape[0], m, tb,
-                                       _stream(stream)))
+    x = _hold(inputs, stream)
+    _check(lib().darts_debug_pointwise(PW[fn], _ptr(x), _ptr(out), inputs.shape[0], m, tb, _stream(stream)))
     return out
 
 
