@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--no-fog", action="store_true", help="skip the fog-layer render and the Adam fit")
     ap.add_argument("--batched-reps", type=int, default=5, help="timed graph launches of the batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--converge", action="store_true",
+                    help="also measure time to MSE 1e-4 by progressive launches against a reference "
+                         "on the early time gate (about two minutes)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device once (a kernel of known "
                          "traffic that calibrates the HBM byte counters of a profiler run)")
@@ -247,6 +250,9 @@ def main():
     if not a.no_batched:
         out["batched"] = batched_bench(darts, torch, W, a.batched_reps)
         print(f"[bench] batched {out['batched']}", file=sys.stderr, flush=True)
+    if a.converge:
+        out["measured_time_to_mse"] = measured_convergence(darts, torch, np, W)
+        print(f"[bench] measured time to MSE {out['measured_time_to_mse']}", file=sys.stderr, flush=True)
     if a.copy_bytes > 0:
         src = torch.empty(a.copy_bytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -388,6 +394,85 @@ def time_gated(darts, torch, np, W, gates=GATES, width=0.15625, n_thr=1 << 26, k
             if arm != "uniform":
                 g[f"uniform_over_{arm}_time"] = g["uniform"]["seconds_to_target"] / g[arm]["seconds_to_target"]
         rep[f"gate_{L0:g}"] = g
+    return rep
+
+
+def measured_convergence(darts, torch, np, W, gate=(3.0, 3.15625), ref_log2=38, chunk_log2=28,
+                         arms=(("darts_alpha4", "darts", 4.0), ("uniform", "uniform", 0.5)), target=1e-4):
+    """Time to MSE `target` measured, not extrapolated, on one time-gated
+    frame of the box workload: progressive launches, each doubling the path
+    count (N = 2^20, 2^21, ...; every launch adds as many new paths as the
+    frame already holds), MSE checked after each against a reference, wall
+    time (launches plus one table build) accumulated until the MSE reaches
+    the target; the crossing itself is placed between the last two doublings
+    with MSE ~ 1/N (`seconds_at_crossing`).  The reference is the inverse-variance combination, per
+    pixel, of 2^ref_log2 paths of each arm (seed 0x5EF, path ids disjoint
+    from the progressive runs), its own MSE stated; the MSE is normalised by
+    the reference's 0.95 quantile, as in time_gated."""
+    w = W.box_hg()
+    w["scene"]["bins"] = {"l_lo": gate[0], "l_hi": gate[0] + (gate[1] - gate[0]), "n_bins": 1}
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    t0 = time.perf_counter()
+    table = darts.build_da_tables(sc["medium"], dm)
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    shape = darts.image_shape(sc)
+    chunk = 1 << chunk_log2
+    n_chunks = 1 << (ref_log2 - chunk_log2)
+    means, vars_ = [], []
+    for arm, mode, alpha in arms:
+        s1 = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        s2 = torch.zeros_like(s1)
+        hi = torch.zeros(shape, dtype=torch.float32, device="cuda")
+        lo = torch.zeros_like(hi)
+        for c in range(n_chunks):
+            hi.zero_(); lo.zero_()
+            pc = dict(pr, n_paths=chunk, path_offset=(1 << 45) + c * chunk, seed=0x5EF, alpha=alpha)
+            darts.render_transient(sc, pc, mode, table, hi, lo)
+            n = darts.paths_per_cell(sc, pc, mode).to("cuda")
+            x = (hi.double() + lo.double()) / n.clamp(min=1)
+            s1 += x
+            s2 += x * x
+        m = s1 / n_chunks
+        means.append(m)
+        vars_.append(torch.clamp(s2 / n_chunks - m * m, min=0) / (n_chunks - 1))   # variance of the mean
+    wts = [1.0 / torch.clamp(v, min=1e-300) for v in vars_]
+    ref = sum(wi * mi for wi, mi in zip(wts, means)) / sum(wts)
+    ref_var = 1.0 / sum(wts)
+    refn = ref.cpu().numpy()
+    q95 = float(np.quantile(refn, 0.95))
+    rep = {"gate": list(gate), "target": target, "reference_paths_per_arm": 1 << ref_log2, "q95": q95,
+           "reference_mse": float(ref_var.mean()) / q95 ** 2, "table_build_s": t_table}
+    for arm, mode, alpha in arms:
+        hi = torch.zeros(shape, dtype=torch.float32, device="cuda")
+        lo = torch.zeros_like(hi)
+        total, wall, n_log2, hist = 0, t_table, 20, []
+        while n_log2 <= 40:
+            add = (1 << 20) if total == 0 else total
+            pc = dict(pr, n_paths=add, path_offset=(1 << 44) + total, seed=0xC0, alpha=alpha)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            darts.render_transient(sc, pc, mode, table, hi, lo)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t1
+            total += add
+            pall = dict(pr, n_paths=total, path_offset=1 << 44, seed=0xC0, alpha=alpha)
+            n = darts.paths_per_cell(sc, pall, mode).to("cuda")
+            est = (hi.double() + lo.double()) / n.clamp(min=1)
+            mse = float(((est - ref) ** 2).mean()) / q95 ** 2
+            hist.append((total, wall, mse))
+            if mse <= target:
+                break
+            n_log2 += 1
+        # crossing between the last two doublings, with MSE ~ 1/N and launch time ~ N
+        mse_last = hist[-1][2]
+        frac = min(1.0, mse_last / target)
+        rep[arm] = {"alpha": alpha, "paths": total, "seconds": wall, "mse": mse_last, "reached": mse_last <= target,
+                    "seconds_at_crossing": t_table + (wall - t_table) * frac, "paths_at_crossing": total * frac,
+                    "history": [{"paths": a, "seconds": b, "mse": c} for a, b, c in hist]}
+    if all(rep[a]["reached"] for a, _, _ in arms):
+        rep["uniform_over_darts_alpha4_time"] = (rep["uniform"]["seconds_at_crossing"] /
+                                                 rep["darts_alpha4"]["seconds_at_crossing"])
     return rep
 
 
