@@ -205,6 +205,7 @@ def main():
             "workload": "box_hg: box [-1,1]^3, sigma_t=5, albedo 0.95, HG g=0.7, emitter (0,0,1.5); "
                         "64x64 orthographic sensor x 256 bins over [0,40); 64x64x32 FP32 direction table",
             "paths_per_step": n, "paths_per_cell": n >> 20, "mode": "darts (RIS 8 + EDA/MIS + texp ellipse)",
+            "alpha": pr["alpha"],
             "step": "build_da_tables + render_transient",
         },
         "render_kernel_ms": mean_kern_s * 1e3,
