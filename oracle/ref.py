@@ -296,10 +296,11 @@ def render_paths_steps(sc: dict, p: dict, mode: str, table=None, dims_: dict | N
 
 
 def render_path_list(sc: dict, p: dict, mode: str, ids, table=None, dims_: dict | None = None,
-                     n_threads: int = 0):
-    """Per-path contributions of the given path ids (DARTS family)."""
+                     n_threads: int = 0, response=None):
+    """Per-path contributions of the given path ids (DARTS family; with a
+    sensor response W, the W-weighted values of Eq. (4))."""
     holder = _SceneHolder(sc)
-    pr = params(p, mode)
+    pr = params(p, mode, response=response)
     ids = np.ascontiguousarray(ids, np.uint64)
     val = np.zeros(len(ids), np.float64)
     cdf = None if table is None else np.ascontiguousarray(table, np.float32)

@@ -94,11 +94,16 @@ TAIL_CASES = [("box_hg", "darts", 0.5, None), ("box_hg", "darts", 4.0, None), ("
               ("box_hg", "darts", 0.5, (10.0, 10.15625)), ("infinite_point", "darts", 0.5, None),
               ("infinite_point", "uniform", 0.5, None), ("box_point", "darts", 0.5, None),
               ("fog_slab_small", "darts", 0.5, None), ("fog_slab_small", "da_only", 0.5, None),
-              ("box_floor_point", "darts", 4.0, None)]
+              ("box_floor_point", "darts", 4.0, None), ("box_hg", "darts", 4.0, "response"),
+              ("box_hg", "uniform", 0.5, "response")]
 
 
-@pytest.mark.parametrize("wname,mode,alpha,gate", TAIL_CASES,
-                         ids=[f"{c[0]}-{c[1]}-a{c[2]}" + (f"-gate{c[3][0]:g}" if c[3] else "") for c in TAIL_CASES])
+def _tail_id(c):
+    tag = "" if c[3] is None else ("-response" if c[3] == "response" else f"-gate{c[3][0]:g}")
+    return f"{c[0]}-{c[1]}-a{c[2]}" + tag
+
+
+@pytest.mark.parametrize("wname,mode,alpha,gate", TAIL_CASES, ids=[_tail_id(c) for c in TAIL_CASES])
 def test_largest_paths_match_oracle(D, oracle, wname, mode, alpha, gate):
     """Rare-event parity: the 16 largest of 2^22 GPU path values (fresh ids)
     recomputed one by one by the oracle.  Per-path parity on 99% of paths
@@ -108,16 +113,20 @@ def test_largest_paths_match_oracle(D, oracle, wname, mode, alpha, gate):
     discrete choices that rounding flips, and none may exceed the oracle's
     value by more than 1%)."""
     w = {**WORKLOADS, "fog_slab_small": W.fog_slab_small, "box_floor_point": W.box_floor_point}[wname]()
-    if gate:
+    resp = R = None
+    if gate == "response":   # the two-peak sensor response W over the workload's bins
+        resp = W.two_peak_response(w["scene"]["bins"])
+        R = D.build_response(resp)
+    elif gate:
         w["scene"]["bins"] = {"l_lo": gate[0], "l_hi": gate[1], "n_bins": 1}
     w = W.with_(w, n_paths=1 << 22, path_offset=1 << 41, seed=0xE1, alpha=alpha)
     w["name"] = wname
     table, cdf = tables(D, oracle, w)
     sc, pr, dm = w["scene"], w["params"], w["dims"]
-    g = D.render_paths(sc, pr, mode, table).cpu().numpy().astype(np.float64)
+    g = D.render_paths(sc, pr, mode, table, response=R).cpu().numpy().astype(np.float64)
     top = np.argsort(-g)[:16]
     ids = np.asarray(top, np.uint64) + np.uint64(pr["path_offset"])
-    o = oracle.render_path_list(sc, pr, mode, ids, cdf, dm)
+    o = oracle.render_path_list(sc, pr, mode, ids, cdf, dm, response=resp)
     gt = g[top]
     rel = np.abs(gt - o) / np.maximum(np.abs(o), 1e-300)
     print(f"{wname}/{mode}/a{alpha}: largest {gt[0] / max(g.mean(), 1e-300):.4g} x mean; "
