@@ -89,6 +89,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-media launch")
     ap.add_argument("--no-response", action="store_true", help="skip the two-peak sensor-response study")
     ap.add_argument("--no-fog", action="store_true", help="skip the fog-layer render and the Adam fit")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing on the differentiable box")
     ap.add_argument("--batched-reps", type=int, default=5, help="timed graph launches of the batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--converge", action="store_true",
@@ -248,6 +249,9 @@ def main():
     if not a.no_fog:
         out["fog_slab"] = fog_bench(darts, torch, W)
         print(f"[bench] fog_slab {out['fog_slab']}", file=sys.stderr, flush=True)
+    if not a.no_adjoint:
+        out["adjoint"] = adjoint_bench(darts, torch, W)
+        print(f"[bench] adjoint {out['adjoint']}", file=sys.stderr, flush=True)
     if not a.no_batched:
         out["batched"] = batched_bench(darts, torch, W, a.batched_reps)
         print(f"[bench] batched {out['batched']}", file=sys.stderr, flush=True)
@@ -565,6 +569,47 @@ def fog_bench(darts, torch, W, reps=2):
                 "paths_per_render": fit["paths_per_render"], "mode": fit["mode"],
                 "image": "16x16 x 128 bins over [0,40)"},
     }
+
+
+def adjoint_bench(darts, torch, W, reps=3):
+    """The differentiable box (sigma_s = 8, sigma_a = 0.2, g = 0.5; 128x128
+    pixels x 512 bins, 2^22 paths): forward render and adjoint replay
+    (darts_render_transient_backward) of the L2 loss against a target
+    rendered at sigma_s = 10, sigma_a = 0.1, g = 0.6 (2^24 paths, other
+    ids), each launch timed with HIP events on its stream; the gradient
+    d loss / d(sigma_s, sigma_a, g) it gives is reported alongside."""
+    w = W.box_hg_grad()
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    tsc = dict(sc, medium=w["target_medium"])
+    stream = torch.cuda.current_stream()
+    ttab = darts.build_da_tables(tsc["medium"], dm)
+    tp = dict(pr, n_paths=1 << 24, path_offset=1 << 42)
+    th, tl, _, _ = darts.render_transient(tsc, tp, "darts", ttab)
+    T = (th.double() + tl.double()) / darts.paths_per_cell(tsc, tp, "darts").to("cuda").clamp(min=1)
+    table = darts.build_da_tables(sc["medium"], dm)
+    n = darts.paths_per_cell(sc, pr, "darts").to("cuda").clamp(min=1)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    fwd, bwd = [], []
+    for _ in range(reps + 1):
+        hi = torch.zeros_like(th)
+        lo = torch.zeros_like(tl)
+        e0.record(stream)
+        darts.render_transient(sc, pr, "darts", table, hi, lo)
+        e1.record(stream)
+        I = (hi.double() + lo.double()) / n
+        gimg = (2.0 * (I - T) / n).float()
+        e2.record(stream)
+        g = darts.render_transient_backward(sc, pr, "darts", table, gimg)
+        e3 = torch.cuda.Event(enable_timing=True)
+        e3.record(stream)
+        torch.cuda.synchronize()
+        fwd.append(e0.elapsed_time(e1))
+        bwd.append(e2.elapsed_time(e3))
+    fwd, bwd = fwd[1:], bwd[1:]      # the first pass warms up
+    paths = int(pr["n_paths"])
+    return {"workload": "box_hg_grad: 128x128 x 512 bins, 2^22 paths, L2 loss vs the target medium",
+            "forward_ms": min(fwd), "backward_ms": min(bwd), "backward_paths_per_s": paths / min(bwd) * 1e3,
+            "cells": int(n.numel()), "grad": [float(x) for x in g.cpu()]}
 
 
 def batched_bench(darts, torch, W, reps):
