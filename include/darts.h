@@ -324,6 +324,19 @@ enum {
 int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n,
                           const darts_medium *medium, const darts_table *table, void *stream);
 
+/* Tuning knobs: process-wide settings of how later renders split their work
+ * over waves.  They change no result beyond the order of the floating-point
+ * additions and may be called from any thread.
+ *  - darts_set_ids_max_reps: a render whose cells hold at most `reps`
+ *    repetitions of a path uses the id-range decomposition (each wave takes
+ *    consecutive path ids; every finished path adds its sum with one
+ *    compensated global atomic pair), otherwise the tile decomposition
+ *    (per-cell sums in LDS).  Default 16; negative: never id ranges.
+ *  - darts_set_target_waves: the number of waves a tile-decomposed launch
+ *    aims for (default 65536).  Returns DARTS_ERR_INVALID_ARG below 1. */
+int darts_set_ids_max_reps(int64_t reps);
+int darts_set_target_waves(int64_t waves);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *darts_last_error(void);
 

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1158,10 +1159,10 @@ int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &
     return DARTS_OK;
 }
 
-int64_t g_ids_max_reps = 16;         // id ranges when no cell has more repetitions
+std::atomic<int64_t> g_ids_max_reps{16};         // id ranges when no cell has more repetitions
 constexpr uint64_t kIdsUnit = 2048;   // most paths per wave in the id-range decomposition
 constexpr uint64_t kIdsWaves = 16384; // waves the id-range decomposition aims for
-int64_t g_target_waves = 1 << 16;   // measured: 4 chunks per tile balance the 2^28-path box frame best
+std::atomic<int64_t> g_target_waves{1 << 16};   // measured: 4 chunks per tile balance the 2^28-path box frame best
 
 int make_params(const darts_scene *sc, const darts_params *pr, const darts_table *table, KParams &P,
                 bool per_path_only)
@@ -1265,7 +1266,8 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     // g_target_waves waves.
     P.max_reps = (P.q1 + (P.r1 > 0 ? 1 : 0)) - P.q0;
     P.n_tiles = (nc + 63) / 64;
-    uint64_t n_chunks = (uint64_t)std::max<int64_t>(1, (g_target_waves + (int64_t)P.n_tiles - 1) / (int64_t)P.n_tiles);
+    const int64_t target_waves = g_target_waves.load(std::memory_order_relaxed);
+    uint64_t n_chunks = (uint64_t)std::max<int64_t>(1, (target_waves + (int64_t)P.n_tiles - 1) / (int64_t)P.n_tiles);
     n_chunks = std::max<uint64_t>(1, std::min(n_chunks, (P.max_reps + 31) / 32));
     P.chunk_reps = (P.max_reps + n_chunks - 1) / n_chunks;
     if (P.chunk_reps == 0) P.chunk_reps = 1;
@@ -1277,7 +1279,7 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     // (units of up to kIdsUnit paths, smaller when that would leave fewer
     // than about kIdsWaves waves to spread over the device)
     P.unit_paths = 0;
-    if ((int64_t)P.max_reps <= g_ids_max_reps) {
+    if ((int64_t)P.max_reps <= g_ids_max_reps.load(std::memory_order_relaxed)) {
         const uint64_t want = (pr->n_paths + kIdsWaves - 1) / kIdsWaves;
         P.unit_paths = std::min<uint64_t>(nc, std::max<uint64_t>(64, std::min<uint64_t>(kIdsUnit, want)));
         P.n_waves = (pr->n_paths + P.unit_paths - 1) / P.unit_paths;
@@ -1831,19 +1833,19 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
     return ok();
 }
 
-// Tuning knob (not part of the stable ABI): renders whose cells hold at most
-// this many repetitions use the id-range decomposition (negative: never).
+// Tuning knob: renders whose cells hold at most this many repetitions use
+// the id-range decomposition (negative: never).
 int darts_set_ids_max_reps(int64_t reps)
 {
-    g_ids_max_reps = reps;
+    g_ids_max_reps.store(reps, std::memory_order_relaxed);
     return ok();
 }
 
-// Tuning knob (not part of the stable ABI): waves a render launch aims for.
+// Tuning knob: waves a tile-decomposed render launch aims for.
 int darts_set_target_waves(int64_t waves)
 {
     if (waves < 1) return fail(DARTS_ERR_INVALID_ARG, "target waves must be >= 1");
-    g_target_waves = waves;
+    g_target_waves.store(waves, std::memory_order_relaxed);
     return ok();
 }
 
