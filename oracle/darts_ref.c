@@ -602,6 +602,27 @@ typedef struct {
     uint64_t st[REF_ST_COUNT];
 } ref_stats;
 
+/* Largest reachable length sum: control vertex still inside the medium
+ * (Section V-B, case II with the boundary clipping S_M), S_exit = d_m + |b|
+ * with b = x + w d_m - x_e.  By the law of cosines |b|^2 - (C - d_m)^2 =
+ * 2 d_m C (1 - mu), so for C >= d_m S_exit - C = 2 d_m C (1 - mu) /
+ * (|b| + C - d_m), free of the cancellation of d_m + |b| - C when the ray
+ * points at an emitter outside the medium; C (1 - mu) is formed as
+ * C |w - a|^2 / 2 (a = (x_e - x) / C).  Infinite for an unbounded medium. */
+double ref_exit_length(const double x[3], const double w[3], const double xe[3], double dm)
+{
+    if (isinf(dm)) return INFINITY;
+    double de[3], pb[3], dw[3];
+    sub3(xe, x, de);
+    double C = len3(de);
+    axpy3(x, w, dm, pb);
+    double bl = dist3(pb, xe), cd = C - dm;
+    for (int i = 0; i < 3; ++i) dw[i] = w[i] - de[i] / C;
+    double cm = 0.5 * C * dot3(dw, dw);
+    if (cd >= 0.0) return (bl + cd > 0.0) ? C + 2.0 * dm * cm / (bl + cd) : C;
+    return C + (bl - cd);
+}
+
 /* Generalised shadow connection through a control vertex on the current
  * ray (Section V-B, case I; Eq. (21)-(22)).  Returns the contribution. */
 static double connect_elliptical(const ref_scene *sc, const ref_params *pr, const path_state *ps,
@@ -617,23 +638,7 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
     if (!(C > 0.0)) return 0.0;
     double mu = dot3(ps->w, de) / C;          /* cos to the focal axis */
     double R_lo = ps->G_lo - ps->Le, R_hi = ps->G_hi - ps->Le;
-    /* Largest reachable length sum: control vertex still inside the medium
-     * (Section V-B, case II with the boundary clipping S_M), S_exit = d_m + |b|
-     * with b = x + w d_m - x_e.  By the law of cosines |b|^2 - (C - d_m)^2 =
-     * 2 d_m C (1 - mu), so for C >= d_m S_exit - C = 2 d_m C (1 - mu) /
-     * (|b| + C - d_m), free of the cancellation of d_m + |b| - C when the ray
-     * points at an emitter outside the medium; C (1 - mu) is formed as
-     * C |w - a|^2 / 2 (a = de / C). */
-    double S_exit = INFINITY;
-    if (!isinf(dm)) {
-        double pb[3], dw[3];
-        axpy3(ps->x, ps->w, dm, pb);
-        double bl = dist3(pb, ps->em->pos), cd = C - dm;
-        for (int i = 0; i < 3; ++i) dw[i] = ps->w[i] - de[i] / C;
-        double cm = 0.5 * C * dot3(dw, dw);
-        if (cd >= 0.0) S_exit = (bl + cd > 0.0) ? C + 2.0 * dm * cm / (bl + cd) : C;
-        else S_exit = C + (bl - cd);
-    }
+    double S_exit = ref_exit_length(ps->x, ps->w, ps->em->pos, dm);
     double S_lo = fmax(R_lo, C), S_hi = fmin(R_hi, S_exit);
     if (!(S_lo < S_hi)) return 0.0;
     *reached = 1;

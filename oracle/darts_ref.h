@@ -129,6 +129,9 @@ double ref_texp_pdf(double x, double sigma, double width);
 double ref_ell_t(double S, double C, double mu);
 double ref_ell_pdf_t(double pS, double S, double C, double mu, double t, int printed);
 double ref_gamma(double kappa, double alpha);
+/* Largest length sum S whose control vertex (Eq. (21)) on the ray x + t w
+ * stays inside the medium, t <= dm (INFINITY for dm = INFINITY). */
+double ref_exit_length(const double x[3], const double w[3], const double xe[3], double dm);
 double ref_box_exit(const ref_geometry *g, const double x[3], const double w[3]);
 /* 1 if the ray (x, w) leaves the medium through the Lambertian floor. */
 int    ref_exits_through_floor(const ref_geometry *g, const double x[3], const double w[3]);

@@ -105,6 +105,8 @@ def lib():
         L.ref_texp_sample.argtypes = [d, d, d]
         L.ref_texp_pdf.restype = d
         L.ref_texp_pdf.argtypes = [d, d, d]
+        L.ref_exit_length.restype = d
+        L.ref_exit_length.argtypes = [pd, pd, pd, d]
         L.ref_ell_pdf_t.restype = d
         L.ref_ell_pdf_t.argtypes = [d, d, d, d, d, C.c_int]
         L.ref_onb.argtypes = [pd, pd, pd]

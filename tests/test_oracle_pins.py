@@ -211,6 +211,64 @@ def test_ellipse_density_matches_histogram(oracle):
     assert np.max(np.abs(hist - pred)) < 2e-4
 
 
+def _exit_length_exact(x, w, xe, dm):
+    """S_exit = d_m + |x + w d_m - x_e| in 60-digit decimal arithmetic from
+    the same double inputs (the definition, free of rounding)."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 60
+        D = [Decimal(float(v)) for v in (*x, *w, *xe, dm)]
+        b = [D[i] + D[3 + i] * D[9] - D[6 + i] for i in range(3)]
+        return float(D[9] + sum(v * v for v in b).sqrt())
+
+
+def test_exit_length(oracle):
+    """The largest length sum whose control vertex stays inside the medium
+    (Section V-B, boundary clipping of the sampled S) against its definition
+    evaluated without rounding: random geometries, and rays aimed within
+    1e-9..1e-3 rad of an emitter beyond the boundary, where the excess over C
+    is tiny and d_m + |b| - C cancels.  The control vertex at S_exit lies on
+    the boundary, t(S_exit) = d_m, wherever t(S) is well conditioned."""
+    L = oracle.lib()
+    rng = np.random.default_rng(21)
+
+    def case(x, w, xe, dm):
+        got = L.ref_exit_length(_vec(x), _vec(w), _vec(xe), dm)
+        want = _exit_length_exact(x, w, xe, dm)
+        scale = max(1.0, *np.abs(x), *np.abs(xe), dm)
+        assert abs(got - want) <= 1e-14 * scale, (got, want)
+        return got
+
+    for _ in range(400):
+        x, xe = rng.normal(size=3), rng.normal(size=3)
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        Cd = np.linalg.norm(xe - x)
+        mu = np.dot(w, xe - x) / Cd
+        dm = Cd * rng.uniform(0.01, 3.0)
+        S = case(x, w, xe, dm)
+        assert S >= Cd * (1 - 1e-15)
+        if mu < 0.99:
+            assert abs(L.ref_ell_t(S, Cd, mu) - dm) < 1e-9 * (dm + Cd)
+    for eta in [0.0, 1e-9, 1e-7, 1e-5, 1e-3]:
+        for _ in range(20):
+            x, xe = rng.normal(size=3), rng.normal(size=3)
+            a = (xe - x) / np.linalg.norm(xe - x)
+            n = np.cross(a, rng.normal(size=3))
+            w = a * math.cos(eta) + n / np.linalg.norm(n) * math.sin(eta)
+            w /= np.linalg.norm(w)
+            Cd = np.linalg.norm(xe - x)
+            dm = Cd * rng.uniform(0.05, 0.95)        # the emitter lies beyond the boundary
+            S = case(x, w, xe, dm)
+            # excess over C: about C (1 - mu) d_m / (C - d_m) = C eta^2 d_m / (2 (C - d_m))
+            assert S - Cd >= -1e-15 * Cd
+            assert S - Cd <= Cd * eta * eta * dm / (Cd - dm) + 4e-16 * Cd
+    assert L.ref_exit_length(_vec([0, 0, 0]), _vec([0, 0, 1]), _vec([0, 0, 2]), np.inf) == np.inf
+    assert L.ref_exit_length(_vec([0, 0, 0]), _vec([0, 0, 1]), _vec([0, 0, 2]), 1.0) == 2.0
+    assert L.ref_exit_length(_vec([0, 0, 0]), _vec([0, 0, 1]), _vec([0, 0, 2]), 3.0) == 4.0
+    assert L.ref_exit_length(_vec([0, 0, 0]), _vec([1, 0, 0]), _vec([0, 0, 2]), 1.5) == 1.5 + 2.5
+
+
 def test_gamma(oracle):
     L = oracle.lib()
     assert L.ref_gamma(0.0, 0.5) == 0.0
