@@ -319,6 +319,9 @@ enum {
     DARTS_PW_MATH,        /* in: x                       out: rcp, rsqrt, log2, exp2 of x,
                                                          sin 2 pi x, cos 2 pi x (hardware
                                                          transcendental unit)          */
+    DARTS_PW_EXIT_LENGTH, /* in: x[3], w[3], xe[3], d_m  out: S_exit, S_exit - C as formed
+                                                         (largest length sum of a
+                                                         connection, Section V-B)      */
     DARTS_PW_COUNT
 };
 int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n,

@@ -247,30 +247,41 @@ __device__ __forceinline__ float focal_cm(V3 x, V3 w, V3 xe, float C)
     return 0.5f * C * dot(dw, dw);
 }
 
-// Range of the length sum; false if no control vertex can close the path.
-//
-// The largest sum keeps the control vertex inside the medium: S_exit = d_m +
-// |b|, b = x + w d_m - x_e.  When the ray points at an emitter outside the
-// medium, d_m + |b| - C cancels, and one ulp of rounding would open a range
-// in which the ellipse is degenerate and 1 / (S - C mu) explodes.  By the law
-// of cosines |b|^2 - (C - d_m)^2 = 2 d_m cm, so for C >= d_m
+// Largest length sum whose control vertex stays inside the medium (the
+// boundary clipping of Section V-B): S_exit = d_m + |b|, b = x + w d_m - x_e,
+// with d_m the finite distance to the boundary along the ray.  When the ray
+// points at an emitter outside the medium, d_m + |b| - C cancels, and one ulp
+// of rounding would open a range in which the ellipse is degenerate and
+// 1 / (S - C mu) explodes.  By the law of cosines |b|^2 - (C - d_m)^2 =
+// 2 d_m cm, so for C >= d_m
 //   S_exit - C = 2 d_m cm / (|b| + C - d_m),
 // which has no cancellation; it is used where the plain sum leaves less than
 // 2^-10 C above C (elsewhere the two agree to rounding).  For C < d_m the
-// plain sum has no cancellation.
+// plain sum has no cancellation.  `excess` receives S_exit - C as formed.
+__device__ __forceinline__ float exit_length(V3 x, V3 w, V3 xe, float C, float dm, float &excess)
+{
+    const float bl = length(fma3(x, w, dm) - xe);
+    const float cd = C - dm;
+    float S_exit = dm + bl;
+    excess = S_exit - C;
+    if (cd >= 0.f && excess < 0x1p-10f * C) {
+        const float den = bl + cd;
+        const float num = 2.f * dm * focal_cm(x, w, xe, C), rden = rcp(den);
+        excess = den > 0.f ? num * rden : 0.f;
+        S_exit = den > 0.f ? fmaf(num, rden, C) : C;
+    }
+    return S_exit;
+}
+
+// Range of the length sum; false if no control vertex can close the path.
 __device__ __forceinline__ bool connect_range(const KParams &P, const PathState &s, float &S_lo, float &S_hi)
 {
     if (!(s.C > 0.f)) return false;
     const float R_lo = s.G_lo - s.Le, R_hi = s.G_hi - s.Le;
     float S_exit = kInf;
     if (P.box) {
-        const float bl = length(fma3(s.x, s.w, s.dm) - s.xe);
-        const float cd = s.C - s.dm;
-        S_exit = s.dm + bl;
-        if (cd >= 0.f && S_exit - s.C < 0x1p-10f * s.C) {
-            const float den = bl + cd;
-            S_exit = den > 0.f ? s.C + 2.f * s.dm * focal_cm(s.x, s.w, s.xe, s.C) * rcp(den) : s.C;
-        }
+        float excess;
+        S_exit = exit_length(s.x, s.w, s.xe, s.C, s.dm, excess);
     }
     S_lo = fmaxf(R_lo, s.C);
     S_hi = fminf(R_hi, S_exit);
@@ -1083,6 +1094,13 @@ __global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
         bool eb;
         const V3 w = sample_direction(Q.med, Q.tb, a[15], a[14] != 0.f, de * rcp(C), C, S, wp, r, wt, eb);
         o[0] = w.x; o[1] = w.y; o[2] = w.z; o[3] = wt; o[4] = eb ? 1.f : 0.f;
+        break;
+    }
+    case DARTS_PW_EXIT_LENGTH: {
+        const V3 x{a[0], a[1], a[2]}, w{a[3], a[4], a[5]}, xe{a[6], a[7], a[8]};
+        float excess;
+        o[0] = exit_length(x, w, xe, length(xe - x), a[9], excess);
+        o[1] = excess;
         break;
     }
     case DARTS_PW_MATH: {

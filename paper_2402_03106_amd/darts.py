@@ -36,7 +36,7 @@ ST_COUNT = 16
 PW_IN, PW_OUT = 16, 8
 PW = {name: i for i, name in enumerate(
     ["philox", "hg_pdf", "hg_sample", "da_logphi", "texp", "ellipse", "sobol", "onb", "box_exit",
-     "ris", "direction", "math"])}
+     "ris", "direction", "math", "exit_length"])}
 
 
 class DartsError(RuntimeError):

@@ -52,6 +52,16 @@ def test_library_has_no_torch_dependency(D):
     assert not [n for n in names if "torch" in n or n.startswith("libc10")], names
 
 
+def test_pointwise_ids_match_header(D):
+    """The binding's diagnostic ids follow the header's enum order."""
+    src = open(HEADER).read()
+    block = re.search(r"enum\s*\{([^}]*DARTS_PW_COUNT[^}]*)\}", src, flags=re.S).group(1)
+    block = re.sub(r"/\*.*?\*/", "", block, flags=re.S)
+    names = re.findall(r"DARTS_PW_(\w+)", block)
+    assert names[-1] == "COUNT"
+    assert [n.lower() for n in names[:-1]] == sorted(D.PW, key=D.PW.get)
+
+
 def test_table_bytes(D):
     assert D.table_bytes(dict(n_cs=64, n_s=64, n_cos=32, s_max=40.0)) == 64 * 64 * 33 * 4
     for bad in [dict(n_cs=0, n_s=4, n_cos=4, s_max=1.0), dict(n_cs=4, n_s=4, n_cos=4, s_max=0.0),

@@ -188,6 +188,67 @@ def test_box_exit(D, oracle):
     assert np.all(rel_ok(out[:, 0], ref, 1e-5, 1e-6))
 
 
+def test_exit_length(D, oracle):
+    """Largest length sum of a connection (boundary clipping, Section V-B)
+    against the FP64 oracle on the same float inputs.  General rays: S_exit
+    to FP32 rounding of its terms.  Rays aimed within 1e-6..1e-2 rad of an
+    emitter beyond the boundary: the excess S_exit - C, which d_m + |b| - C
+    loses to cancellation in FP32, to within what FP32 rounding of the unit
+    vector a to the emitter allows (a few ulp; the bar allows 16 eps on
+    |w - a|, hence C |w - a| 16 eps on C (1 - mu) = C |w - a|^2 / 2); the
+    plain FP32 sum is shown to miss that bar, so the test sees the
+    difference."""
+    L = oracle.lib()
+    eps = float(np.finfo(np.float32).eps)
+    rng = np.random.default_rng(22)
+    rows, kind = [], []
+    for _ in range(2000):
+        x, xe = rng.uniform(-1, 1, 3), rng.normal(size=3) * 2
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        rows.append([*x, *w, *xe, rng.uniform(0.01, 3)])
+        kind.append(0)
+    for eta in [0.0, 1e-6, 1e-5, 1e-4, 1e-3, 1e-2]:
+        for _ in range(300):
+            x = rng.uniform(-1, 1, 3)
+            xe = x + rng.normal(size=3) * rng.uniform(0.5, 3)
+            a = (xe - x) / np.linalg.norm(xe - x)
+            n = np.cross(a, rng.normal(size=3))
+            w = a * math.cos(eta) + n / np.linalg.norm(n) * math.sin(eta)
+            rows.append([*x, *(w / np.linalg.norm(w)), *xe, np.linalg.norm(xe - x) * rng.uniform(0.05, 0.95)])
+            kind.append(1)
+    rows = [[F32(v) for v in r] for r in rows]
+    kind = np.array(kind)
+    out, inp, _ = run(D, "exit_length", rows)
+    x, w, xe, dm = inp[:, 0:3], inp[:, 3:6], inp[:, 6:9], inp[:, 9]
+    ref = np.array([L.ref_exit_length(_v(a), _v(b), _v(c), d) for a, b, c, d in zip(x, w, xe, dm)])
+    Cd = np.linalg.norm(xe - x, axis=1)
+    bl = np.linalg.norm(x + w * dm[:, None] - xe, axis=1)
+    g = kind == 0
+    assert np.all(np.abs(out[g, 0] - ref[g]) <= 4 * eps * (dm[g] + bl[g] + Cd[g]))
+    # excess on the aimed rays; the oracle's own excess from its cancellation-free terms
+    a_hat = (xe - x) / Cd[:, None]
+    wa = np.linalg.norm(w - a_hat, axis=1)
+    ex_ref = 2 * dm * (0.5 * Cd * wa * wa) / (bl + Cd - dm)
+    h = kind == 1
+    assert np.all(np.abs(ref[h] - (Cd[h] + ex_ref[h])) <= 4e-16 * Cd[h])   # the oracle agrees with its terms
+    delta = 16 * eps
+    tol = 2 * dm * 0.5 * Cd * (2 * wa * delta + delta * delta) / (bl + Cd - dm) + 1e-5 * ex_ref
+    err = np.abs(out[:, 1] - ex_ref)
+    assert np.all(err[h] <= tol[h]), np.max(err[h] / tol[h])
+    assert np.all(out[h, 0] >= Cd[h] * (1 - 4 * eps))
+    # the plain FP32 sum d_m + |b| - C fails the same bar on most aimed rays within 1e-3 rad
+    x32, w32, xe32, dm32 = (v.astype(np.float32) for v in (x, w, xe, dm))
+    b32 = np.linalg.norm(x32 + w32 * dm32[:, None] - xe32, axis=1).astype(np.float32)
+    plain = (dm32 + b32).astype(np.float32) - np.linalg.norm(xe32 - x32, axis=1).astype(np.float32)
+    tight = h & (wa < 1.5e-3)
+    assert np.mean(np.abs(plain[tight] - ex_ref[tight]) > tol[tight]) > 0.5
+
+
+def _v(x):
+    return (C.c_double * 3)(*x)
+
+
 def test_ris_step(D, oracle):
     """Whole RIS free-flight step: validity, selected distance, weight."""
     L = oracle.lib()
