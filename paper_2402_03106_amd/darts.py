@@ -442,6 +442,8 @@ def set_ids_max_reps(n: int):
 
 
 def set_target_waves(n: int):
+    """Tuning knob: the number of waves a tile-decomposed render aims for
+    (default 65536); results change only in the order of the additions."""
     _check(lib().darts_set_target_waves(int(n)))
 
 
