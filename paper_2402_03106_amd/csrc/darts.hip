@@ -774,7 +774,11 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
     __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
-    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    // the wave's index within the block is the same on all of its lanes: read
+    // it as a scalar so that the wave's cell and path ranges live in scalar
+    // registers rather than occupying vector registers for the whole loop
+    const uint32_t wave_in_block = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + wave_in_block;
     const bool have = wave < P.n_waves;
     int64_t c0;
     uint64_t j_begin, j_end;
@@ -802,11 +806,17 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
                                            acc_m2 + wbase, st, gacc);
 
     if (SRC == SRC_TILE && MODE == 0 && OUT == OUT_IMAGE && have) {
-        const int64_t cell = c0 + lane;
-        const float h = acc_hi[threadIdx.x], l = acc_lo[threadIdx.x];
+        // The flush indices are formed again from the thread index here; the
+        // empty asm hides that they equal values known before the path loop,
+        // which the compiler would otherwise keep alive across the loop in
+        // registers it has to spill to scratch memory.
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        const int64_t cell = c0 + (t & 63);
+        const float h = acc_hi[t], l = acc_lo[t];
         if (cell < P.ncells) {
             if (h != 0.f || l != 0.f) add_compensated(P.hi, P.lo, cell, h, l);
-            if (P.m2 && acc_m2[threadIdx.x] != 0.f) unsafeAtomicAdd(P.m2 + cell, acc_m2[threadIdx.x]);
+            if (P.m2 && acc_m2[t] != 0.f) unsafeAtomicAdd(P.m2 + cell, acc_m2[t]);
         }
     }
     if (OUT == OUT_GRAD) {
