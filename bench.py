@@ -675,8 +675,15 @@ def cpu_baseline(w, seconds):
         if dt >= seconds or n >= (1 << 26):
             break
         n = n * 2 if dt * 2.5 < seconds else int(n * seconds / max(dt, 1e-3))
+    # one thread on about a quarter of that work: the per-core rate
+    n1 = max(1 << 12, int(n / max(threads, 1) / 4))
+    t0 = time.perf_counter()
+    ref.render(sc, dict(pr, n_paths=n1), "darts", cdf, dm, n_threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} DARTS paths of the box workload (ids 0..{n - 1}), FP64, {dt:.1f} s"}
+            "sample": f"{n} DARTS paths of the box workload (ids 0..{n - 1}), FP64, {dt:.1f} s",
+            "single_thread_value": n1 / dt1,
+            "single_thread_sample": f"{n1} paths (ids 0..{n1 - 1}) on one thread, {dt1:.1f} s"}
 
 
 if __name__ == "__main__":
