@@ -92,9 +92,11 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing on the differentiable box")
     ap.add_argument("--batched-reps", type=int, default=5, help="timed graph launches of the batch")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--converge", action="store_true",
-                    help="also measure time to MSE 1e-4 by progressive launches against a reference "
-                         "on the early time gate (about two minutes)")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the measured (progressive-launch) time to MSE 1e-4 on the early time gate")
+    ap.add_argument("--converge-ref-log2", type=int, default=36,
+                    help="log2 of the reference's paths per arm for the measured time to MSE "
+                         "(36: about 20 s, reference MSE about 3e-6; 38: about 80 s)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device once (a kernel of known "
                          "traffic that calibrates the HBM byte counters of a profiler run)")
@@ -255,8 +257,8 @@ def main():
     if not a.no_batched:
         out["batched"] = batched_bench(darts, torch, W, a.batched_reps)
         print(f"[bench] batched {out['batched']}", file=sys.stderr, flush=True)
-    if a.converge:
-        out["measured_time_to_mse"] = measured_convergence(darts, torch, np, W)
+    if not a.no_converge:
+        out["measured_time_to_mse"] = measured_convergence(darts, torch, np, W, ref_log2=a.converge_ref_log2)
         print(f"[bench] measured time to MSE {out['measured_time_to_mse']}", file=sys.stderr, flush=True)
     if a.copy_bytes > 0:
         src = torch.empty(a.copy_bytes // 4, dtype=torch.float32, device=dev)
