@@ -73,7 +73,7 @@ def compare_images(img_g, m2_g, img_o, m2_o, n):
     ("infinite_point", "darts", 1 << 16), ("infinite_point", "uniform", 1 << 16),
     ("box_hg", "darts", 1 << 18), ("box_hg", "uniform", 1 << 18),
     ("box_hg_small", "da_only", 1 << 16), ("box_hg_small", "eda_only", 1 << 16),
-    ("box_point", "darts", 1 << 16),
+    ("box_hg_small", "texp_only", 1 << 16), ("box_point", "darts", 1 << 16),
 ])
 def test_per_path_parity(D, oracle, wname, mode, n):
     w = W.with_(WORKLOADS[wname](), n_paths=n)
@@ -180,10 +180,12 @@ def test_per_path_parity_alpha(D, oracle, alpha):
     ("infinite_point", "darts"), ("infinite_point", "uniform"), ("infinite_point", "vanilla"),
     ("box_hg", "darts"), ("box_hg", "uniform"),
     ("box_hg_small", "vanilla"), ("box_point", "darts"), ("box_point", "vanilla"),
+    ("box_hg_small", "da_only"), ("box_hg_small", "eda_only"), ("box_hg_small", "texp_only"),
 ])
 def test_image_parity(D, oracle, wname, mode):
-    """The configurations' own sizes (2^16 paths for the infinite medium,
-    2^20 for the box medium): the spec image bar."""
+    """The workloads' own sizes (2^16 paths for the infinite medium, 2^20 for
+    the box medium, 2^16 for the small box): relative L2 <= 1% and
+    |delta|/sigma <= 4 on 99.9% of the cells."""
     w = WORKLOADS[wname]()
     table, cdf = tables(D, oracle, w)
     sc, pr, dm = w["scene"], w["params"], w["dims"]
