@@ -279,11 +279,13 @@ def test_ris_step(D, oracle):
     assert n_ok >= 0.998 * n_cmp, (n_ok, n_cmp)
 
 
-def test_direction_sampling(D, oracle):
-    """EDA/HG mixture with MIS weight on a real table."""
+@pytest.mark.parametrize("n_cos", [32, 256])
+def test_direction_sampling(D, oracle, n_cos):
+    """EDA/HG mixture with MIS weight on a real table (the small box's 32
+    cos-bins, and the paper's 256)."""
     L = oracle.lib()
     w = W.box_hg_small()
-    med, dims = w["scene"]["medium"], w["dims"]
+    med, dims = w["scene"]["medium"], dict(w["dims"], n_cos=n_cos)
     table = D.build_da_tables(med, dims)
     _, cdf = oracle.build_table(med, dims)
     torch.cuda.synchronize()
@@ -313,9 +315,20 @@ def test_direction_sampling(D, oracle):
     assert n_ok >= 0.995 * len(rows), n_ok
 
 
-def test_table_matches_oracle(D, oracle):
-    for w in [W.box_hg_small(), W.infinite_point()]:
-        med, dims = w["scene"]["medium"], w["dims"]
+TABLE_CASES = [("box_hg_small", None), ("infinite_point", None), ("box_hg", None),
+               ("box_hg", {"n_cs": 16, "n_s": 16, "n_cos": 256, "s_max": 40.0}),
+               ("box_hg", {"n_cs": 8, "n_s": 8, "n_cos": 1024, "s_max": 40.0}),
+               ("box_hg", {"n_cs": 3, "n_s": 5, "n_cos": 7, "s_max": 13.0})]
+
+
+@pytest.mark.parametrize("wname,dims_", TABLE_CASES,
+                         ids=[f"{c[0]}-{'own' if c[1] is None else c[1]['n_cos']}" for c in TABLE_CASES])
+def test_table_matches_oracle(D, oracle, wname, dims_):
+    """The elliptical-DA table against the oracle's: the workloads' own
+    dimensions, the paper's 256 cos-bins, the largest allowed count (1024,
+    more bins than a wave has lanes) and a ragged odd-sized table."""
+    for w in [getattr(W, wname)()]:
+        med, dims = w["scene"]["medium"], dims_ or w["dims"]
         t = D.build_da_tables(med, dims)
         torch.cuda.synchronize()
         _, cdf = oracle.build_table(med, dims)
