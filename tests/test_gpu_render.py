@@ -176,6 +176,22 @@ def test_per_path_parity_alpha(D, oracle, alpha):
     assert np.mean((g != 0) == (o != 0)) >= 0.995
 
 
+@pytest.mark.parametrize("n_cos", [256, 1024])
+def test_per_path_parity_fine_table(D, oracle, n_cos):
+    """Whole paths on finer direction tables: the paper's 256 cos-bins and
+    the largest allowed 1024 (a 16x16 grid of (C/S, S) cells)."""
+    w = W.with_(W.box_hg_small(), n_paths=1 << 16, alpha=0.5)
+    w["dims"] = dict(w["dims"], n_cs=16, n_s=16, n_cos=n_cos)
+    table, cdf = tables(D, oracle, w)
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    g = D.render_paths(sc, pr, "darts", table).cpu().numpy().astype(np.float64)
+    o, _ = oracle.render_paths(sc, pr, "darts", cdf, dm)
+    close = np.abs(g - o) <= 1e-3 * np.abs(o) + 1e-30
+    print(f"n_cos {n_cos}: {close.mean():.5f} of paths agree; nonzero {np.mean(o != 0):.3f}")
+    assert close.mean() >= 0.99
+    assert np.mean((g != 0) == (o != 0)) >= 0.995
+
+
 @pytest.mark.parametrize("wname,mode", [
     ("infinite_point", "darts"), ("infinite_point", "uniform"), ("infinite_point", "vanilla"),
     ("box_hg", "darts"), ("box_hg", "uniform"),
