@@ -176,6 +176,23 @@ def test_per_path_parity_alpha(D, oracle, alpha):
     assert np.mean((g != 0) == (o != 0)) >= 0.995
 
 
+@pytest.mark.parametrize("g", [0.95, -0.5, 0.0])
+def test_per_path_parity_phase_extremes(D, oracle, g):
+    """Whole paths for a sharply forward-peaked, a backward-scattering and an
+    isotropic phase function (the HG sampler and density near their limits)."""
+    w = W.with_(W.box_hg_small(), n_paths=1 << 16, alpha=0.5)
+    w["scene"]["medium"] = dict(w["scene"]["medium"], g=g)
+    table, cdf = tables(D, oracle, w)
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    for mode in ["darts", "uniform"]:
+        gv = D.render_paths(sc, pr, mode, table).cpu().numpy().astype(np.float64)
+        o, _ = oracle.render_paths(sc, pr, mode, cdf, dm)
+        close = np.abs(gv - o) <= 1e-3 * np.abs(o) + 1e-30
+        print(f"g {g} {mode}: {close.mean():.5f} of paths agree; nonzero {np.mean(o != 0):.3f}")
+        assert close.mean() >= 0.99
+        assert np.mean((gv != 0) == (o != 0)) >= 0.995
+
+
 @pytest.mark.parametrize("n_cos", [256, 1024])
 def test_per_path_parity_fine_table(D, oracle, n_cos):
     """Whole paths on finer direction tables: the paper's 256 cos-bins and
@@ -299,15 +316,20 @@ def test_empty_and_degenerate(D, oracle):
     assert D.stats_dict(st)["zero_paths"] == 1 << 12
 
 
-def test_single_bounce_and_start_time_and_two_emitters(D, oracle):
-    """max_bounces = 1 (single scattering), an emitter start offset, and two
-    emitters with different start times against the oracle."""
+def test_single_bounce_and_start_time_and_emitters(D, oracle):
+    """max_bounces = 1 (single scattering), an emitter start offset, two
+    emitters with different start times and the largest emitter count (8)
+    against the oracle."""
     base = W.box_hg_small()
     cases = [
         W.with_(base, max_bounces=1),
         W.with_(base, emitters=[{"pos": (0.0, 0.0, 1.5), "start": 2.5, "power": 1.0}]),
         W.with_(base, emitters=[{"pos": (0.0, 0.0, 1.5), "start": 0.0, "power": 1.0},
                                 {"pos": (0.5, -0.25, 1.25), "start": 3.0, "power": 2.0}]),
+        # the largest emitter count, around and above the box, staggered starts
+        W.with_(base, emitters=[{"pos": (1.5 * math.cos(k * math.pi / 4), 1.5 * math.sin(k * math.pi / 4),
+                                         0.25 + 0.25 * k), "start": 0.5 * k, "power": 1.0 + 0.25 * k}
+                                for k in range(8)]),
     ]
     for w in cases:
         table, cdf = tables(D, oracle, w)
