@@ -193,6 +193,29 @@ def test_per_path_parity_phase_extremes(D, oracle, g):
         assert np.mean((gv != 0) == (o != 0)) >= 0.995
 
 
+@pytest.mark.parametrize("sigma_t", [0.05, 50.0])
+def test_per_path_parity_optical_depth(D, oracle, sigma_t):
+    """Whole paths in an almost transparent box (0.1 mean free paths across)
+    and an optically thick one (100 across, long walks that reach the
+    bounce limit), albedo 0.95.  In the thick box many path values lie far
+    below the FP32 range (transmittance e^{-50 L}); the comparison of which
+    paths contribute counts a value as nonzero above 1e-30."""
+    w = W.with_(W.box_hg_small(), n_paths=1 << 16, alpha=0.5)
+    w["scene"]["medium"] = dict(w["scene"]["medium"], sigma_s=0.95 * sigma_t, sigma_a=0.05 * sigma_t)
+    table, cdf = tables(D, oracle, w)
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    for mode in ["darts", "uniform"]:
+        gv = D.render_paths(sc, pr, mode, table).cpu().numpy().astype(np.float64)
+        o, _ = oracle.render_paths(sc, pr, mode, cdf, dm)
+        close = np.abs(gv - o) <= 1e-3 * np.abs(o) + 1e-30
+        mism = (gv != 0) != (o != 0)
+        print(f"sigma_t {sigma_t} {mode}: {close.mean():.5f} of paths agree; nonzero {np.mean(o != 0):.3f}; "
+              f"zero on one side only: {mism.mean():.4f}, largest such value {np.abs(o[mism]).max(initial=0):.3g} "
+              f"(oracle) {np.abs(gv[mism]).max(initial=0):.3g} (GPU); largest path {np.abs(o).max():.3g}")
+        assert close.mean() >= 0.99
+        assert np.mean((np.abs(gv) > 1e-30) == (np.abs(o) > 1e-30)) >= 0.995
+
+
 @pytest.mark.parametrize("n_cos", [256, 1024])
 def test_per_path_parity_fine_table(D, oracle, n_cos):
     """Whole paths on finer direction tables: the paper's 256 cos-bins and
