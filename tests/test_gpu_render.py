@@ -363,6 +363,35 @@ def test_single_bounce_and_start_time_and_emitters(D, oracle):
         assert rel <= 0.01 and frac >= 0.999, (rel, frac)
 
 
+def test_ragged_sensor_and_unnormalised_direction(D, oracle):
+    """A 7x5 sensor with 13 bins (455 cells: the last tile of 64 cells is
+    partly empty) whose viewing direction is given unnormalised, with 3
+    paths per cell and a few over: image bar against the oracle under both
+    work decompositions, and the same paths path by path."""
+    w = W.box_hg_small()
+    sc = w["scene"]
+    sc["sensor"] = dict(sc["sensor"], width=7, height=5, dir=(0.0, 0.0, -2.5))
+    sc["bins"] = {"l_lo": 0.0, "l_hi": 10.0, "n_bins": 13}
+    w["params"]["n_paths"] = 3 * 455 + 200
+    table, cdf = tables(D, oracle, w)
+    pr, dm = w["params"], w["dims"]
+    img_o, m2_o, _ = oracle.render(sc, pr, "darts", cdf, dm)
+    n = oracle.paths_per_cell(sc, pr, "darts")
+    try:
+        for reps in [-1, 1 << 40]:          # tiles of cells, then ranges of path ids
+            D.set_ids_max_reps(reps)
+            img_g, m2_g, st = gpu_image(D, w, "darts", table)
+            rel, frac = compare_images(img_g, m2_g, img_o, m2_o, n)
+            assert rel <= 0.01 and frac >= 0.999, (reps, rel, frac)
+            assert st["paths"] == pr["n_paths"]
+    finally:
+        D.set_ids_max_reps(16)
+    g = D.render_paths(sc, pr, "darts", table).cpu().numpy().astype(np.float64)
+    o, cells = oracle.render_paths(sc, pr, "darts", cdf, dm)
+    assert np.array_equal(cells, np.arange(pr["n_paths"]) % 455)
+    assert np.mean(np.abs(g - o) <= 1e-3 * np.abs(o) + 1e-30) >= 0.99
+
+
 def test_full_size_sampled_cells(D, oracle):
     """The box workload in the benchmark's launch configuration (2^28 paths,
     256 per cell): sampled cells recomputed by the oracle path by path."""
