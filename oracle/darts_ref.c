@@ -412,7 +412,7 @@ void ref_eda_row_raw(const ref_medium *m, double C, double S, int n_cos, double 
 }
 
 int ref_build_da_tables(const ref_medium *m, const ref_table_dims *dm,
-                        double *pmf, float *cdf, int n_threads)
+                        double *pmf, float *cdf, int n_threads, int mutation)
 {
     if (dm->n_cs <= 0 || dm->n_s <= 0 || dm->n_cos <= 0 || !(dm->s_max > 0.0)) return -1;
     int ncell = dm->n_cs * dm->n_s;
@@ -423,8 +423,9 @@ int ref_build_da_tables(const ref_medium *m, const ref_table_dims *dm,
     for (int cell = 0; cell < ncell; ++cell) {
         int i = cell / dm->n_s, j = cell % dm->n_s;
         /* cell centres in C/S and S */
-        double kappa = (i + 0.5) / dm->n_cs;
-        double S = (j + 0.5) * dm->s_max / dm->n_s;
+        double off = mutation == REF_MUT_TABLE_CELL_EDGE ? 0.0 : 0.5;
+        double kappa = (i + off) / dm->n_cs;
+        double S = (j + off) * dm->s_max / dm->n_s;
         double *row = (double *)malloc(sizeof(double) * dm->n_cos);
         ref_eda_row_raw(m, kappa * S, S, dm->n_cos, row);
         double tot = 0.0;
@@ -455,7 +456,7 @@ int ref_build_da_tables(const ref_medium *m, const ref_table_dims *dm,
 void ref_sample_direction(const ref_medium *m, const ref_table_dims *dm, const float *cdf,
                           double alpha, int use_eda, const double x[3], const double xe[3],
                           const double w_prev[3], double S, const double u[4],
-                          double w_out[3], double *weight, int *eda_branch, int mutation)
+                          double w_out[3], double *weight, int *eda_branch, int *bin, int mutation)
 {
     double a[3];
     sub3(xe, x, a);
@@ -466,6 +467,7 @@ void ref_sample_direction(const ref_medium *m, const ref_table_dims *dm, const f
     if (gam > 0.0) {
         int i = (int)floor(C / S * dm->n_cs);
         int j = (int)floor(S / dm->s_max * dm->n_s);
+        if (mutation == REF_MUT_TABLE_ROW_OFF_BY_ONE) ++i;
         if (i > dm->n_cs - 1) i = dm->n_cs - 1;
         if (i < 0) i = 0;
         if (j > dm->n_s - 1) j = dm->n_s - 1;
@@ -500,6 +502,7 @@ void ref_sample_direction(const ref_medium *m, const ref_table_dims *dm, const f
         p_eda = (mutation == REF_MUT_EDA_PDF_UNSCALED) ? pk : pk * dm->n_cos / (4.0 * PI);
     }
     *weight = p_hg / (gam * p_eda + (1.0 - gam) * p_hg);
+    if (bin) *bin = k;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -602,25 +605,17 @@ typedef struct {
     uint64_t st[REF_ST_COUNT];
 } ref_stats;
 
-/* Largest reachable length sum: control vertex still inside the medium
- * (Section V-B, case II with the boundary clipping S_M), S_exit = d_m + |b|
- * with b = x + w d_m - x_e.  By the law of cosines |b|^2 - (C - d_m)^2 =
- * 2 d_m C (1 - mu), so for C >= d_m S_exit - C = 2 d_m C (1 - mu) /
- * (|b| + C - d_m), free of the cancellation of d_m + |b| - C when the ray
- * points at an emitter outside the medium; C (1 - mu) is formed as
- * C |w - a|^2 / 2 (a = (x_e - x) / C).  Infinite for an unbounded medium. */
+/* Largest reachable length sum (Section V-B, case II, boundary clipping S_M):
+ * the control vertex must stay inside the medium, so the longest connected
+ * path leaves the ray at the boundary point x + w d_m and goes straight to
+ * the emitter: S_exit = d_m + |x + w d_m - x_e|.  Infinite for an unbounded
+ * medium. */
 double ref_exit_length(const double x[3], const double w[3], const double xe[3], double dm)
 {
     if (isinf(dm)) return INFINITY;
-    double de[3], pb[3], dw[3];
-    sub3(xe, x, de);
-    double C = len3(de);
+    double pb[3];
     axpy3(x, w, dm, pb);
-    double bl = dist3(pb, xe), cd = C - dm;
-    for (int i = 0; i < 3; ++i) dw[i] = w[i] - de[i] / C;
-    double cm = 0.5 * C * dot3(dw, dw);
-    if (cd >= 0.0) return (bl + cd > 0.0) ? C + 2.0 * dm * cm / (bl + cd) : C;
-    return C + (bl - cd);
+    return dm + dist3(pb, xe);
 }
 
 /* Generalised shadow connection through a control vertex on the current
@@ -651,11 +646,6 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
         pS = 1.0 / width;
     }
     double t = ref_ell_t(S, C, mu);
-    /* The control vertex lies on the ray inside the medium: t <= d_m, the
-     * same condition as S <= S_exit in exact arithmetic; a length sum that
-     * rounding places past S_exit (rays aimed almost at an emitter outside
-     * the medium) would put it beyond the boundary. */
-    if (!(t <= dm)) return 0.0;
     double r = S - t;
     double pt = ref_ell_pdf_t(pS, S, C, mu, t, pr->mutation == REF_MUT_PRINTED_JACOBIAN);
     double xc[3], wc[3], dv[3];
@@ -722,7 +712,7 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
             } else {
                 int eb;
                 ref_sample_direction(m, dm_t, cdf, pr->alpha, (pr->flags & REF_EDA_DIR) != 0,
-                                     ps.x, ps.em->pos, ps.w, R_hi, u, wn, &weight, &eb, pr->mutation);
+                                     ps.x, ps.em->pos, ps.w, R_hi, u, wn, &weight, &eb, NULL, pr->mutation);
                 S->st[REF_ST_EDA_BRANCH] += (uint64_t)eb;
                 dlg += dlog_hg_dg(dot3(ps.w, wn), m->g);
             }
@@ -738,6 +728,7 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
         /* a full path sample exists when a control vertex can close the
          * path; its length lies in the target segment, where W > 0 */
         if (reached) S->st[REF_ST_SAMPLES]++;
+        if (pr->sigma_a_shift != 0.0) c *= exp(-pr->sigma_a_shift * (L_med + tc + rin));
         if (c != 0.0) {
             S->st[REF_ST_CONNECTIONS]++;
             if (grad) {
@@ -761,6 +752,7 @@ static double trace_darts(const ref_scene *sc, const ref_params *pr, const ref_t
             S->st[REF_ST_SAMPLES]++;
             if (L >= ps.G_lo && L < ps.G_hi) {
                 double cs = ps.beta * ps.J * Ie * fc;
+                if (pr->sigma_a_shift != 0.0) cs *= exp(-pr->sigma_a_shift * (L_med + dm + rin_s));
                 if (cs != 0.0) {
                     S->st[REF_ST_CONNECTIONS]++;
                     if (grad) {

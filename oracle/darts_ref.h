@@ -88,6 +88,12 @@ typedef struct {
      * - cdf[k]); vanilla weights every connection by W of its length.  Paths
      * map to pixels (id mod pixels) and the image is [height][width]. */
     const double *response;
+    /* Test hook for the absorption-scaling invariant (DARTS family only; 0
+     * in normal use): every connection's contribution is multiplied by
+     * exp(-sigma_a_shift * in-medium length of the connected path), which
+     * turns an estimate of the medium (sigma_s, sigma_a) into one of
+     * (sigma_s, sigma_a + sigma_a_shift) with the first medium's sampling. */
+    double sigma_a_shift;
 } ref_params;
 
 /* Planted mistakes. They exist so the test-suite can show that its pins
@@ -101,6 +107,8 @@ typedef struct {
 #define REF_MUT_GRAD_NO_COUNT     6 /* gradient: drop n / sigma_s              */
 #define REF_MUT_RESPONSE_UNWEIGHTED 7 /* response: drop W_k / P(segment k)     */
 #define REF_MUT_FLOOR_NO_COSINE   8 /* floor connection without its cosine      */
+#define REF_MUT_TABLE_CELL_EDGE   9 /* table rows built at cell edges, not centres */
+#define REF_MUT_TABLE_ROW_OFF_BY_ONE 10 /* direction lookup reads the next C/S row */
 
 /* Statistics, uint64 counters. */
 enum {
@@ -130,7 +138,7 @@ double ref_ell_t(double S, double C, double mu);
 double ref_ell_pdf_t(double pS, double S, double C, double mu, double t, int printed);
 double ref_gamma(double kappa, double alpha);
 /* Largest length sum S whose control vertex (Eq. (21)) on the ray x + t w
- * stays inside the medium, t <= dm (INFINITY for dm = INFINITY). */
+ * stays inside the medium: dm + |x + w dm - xe| (INFINITY for dm = INFINITY). */
 double ref_exit_length(const double x[3], const double w[3], const double xe[3], double dm);
 double ref_box_exit(const ref_geometry *g, const double x[3], const double w[3]);
 /* 1 if the ray (x, w) leaves the medium through the Lambertian floor. */
@@ -155,13 +163,15 @@ void ref_eda_row_raw(const ref_medium *m, double C, double S, int n_cos, double 
 /* Full table: pmf (double, [n_cs][n_s][n_cos]) and the float CDF the
  * sampler uses ([n_cs][n_s][n_cos+1]); either output may be NULL. */
 int ref_build_da_tables(const ref_medium *m, const ref_table_dims *dims,
-                        double *pmf, float *cdf, int n_threads);
+                        double *pmf, float *cdf, int n_threads, int mutation);
 
 /* EDA/HG mixture direction sampling (Section V-A, Eq. (19)); for tests. */
 void ref_sample_direction(const ref_medium *m, const ref_table_dims *dims, const float *cdf,
                           double alpha, int use_eda, const double x[3], const double xe[3],
                           const double w_prev[3], double S, const double u[4],
-                          double w_out[3], double *weight, int *eda_branch, int mutation);
+                          double w_out[3], double *weight, int *eda_branch, int *bin, int mutation);
+/* (bin, may be NULL: the cos-bin whose mass enters the EDA density, -1 when
+ * the EDA density is not used) */
 
 /* Render: raw per-cell sums into image[n_bins][height][width] (+= semantics
  * are not used: the oracle writes, the caller accumulates); m2 (may be NULL)

@@ -32,7 +32,7 @@ MODES = {
 }
 MUT = {"none": 0, "printed_jacobian": 1, "ris_no_mean": 2, "eda_pdf_unscaled": 3,
        "no_emitter_trans": 4, "hg_sample_flip": 5, "grad_no_count": 6, "response_unweighted": 7,
-       "floor_no_cosine": 8}
+       "floor_no_cosine": 8, "table_cell_edge": 9, "table_row_off_by_one": 10}
 STATS = ["paths", "vertices", "connections", "early_exit", "medium_exit", "ris_all_invalid",
          "eda_branch", "truncated", "zero_paths", "ris_invalid_cands", "samples", "rejected"]
 
@@ -80,7 +80,8 @@ class _Dims(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("n_paths", C.c_uint64), ("path_offset", C.c_uint64), ("seed", C.c_uint64),
                 ("max_bounces", C.c_int), ("n_ris", C.c_int), ("alpha", C.c_double),
-                ("flags", C.c_uint), ("mutation", C.c_int), ("response", C.POINTER(C.c_double))]
+                ("flags", C.c_uint), ("mutation", C.c_int), ("response", C.POINTER(C.c_double)),
+                ("sigma_a_shift", C.c_double)]
 
 
 _lib = None
@@ -128,10 +129,10 @@ def lib():
         L.ref_eda_row_raw.argtypes = [C.POINTER(_Medium), d, d, C.c_int, pd]
         L.ref_build_da_tables.restype = C.c_int
         L.ref_build_da_tables.argtypes = [C.POINTER(_Medium), C.POINTER(_Dims), pd,
-                                          C.POINTER(C.c_float), C.c_int]
+                                          C.POINTER(C.c_float), C.c_int, C.c_int]
         L.ref_sample_direction.argtypes = [C.POINTER(_Medium), C.POINTER(_Dims), C.POINTER(C.c_float),
                                            d, C.c_int, pd, pd, pd, d, pd, pd, pd,
-                                           C.POINTER(C.c_int), C.c_int]
+                                           C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]
         L.ref_render_transient.restype = C.c_int
         L.ref_render_transient.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Dims),
                                            C.POINTER(C.c_float), pd, pd, C.POINTER(C.c_uint64), C.c_int]
@@ -193,7 +194,7 @@ def params(p: dict, mode: str | None = None, mutation: str = "none", response=No
     flags = MODES[mode] if mode is not None else int(p["flags"])
     pr = _Params(int(p["n_paths"]), int(p.get("path_offset", 0)), int(p["seed"]),
                  int(p["max_bounces"]), int(p.get("n_ris", 8)), float(p.get("alpha", 0.5)),
-                 flags, MUT[mutation], None)
+                 flags, MUT[mutation], None, float(p.get("sigma_a_shift", 0.0)))
     if response is not None:
         arr = np.ascontiguousarray(response, np.float64)
         pr.flags |= RESPONSE
@@ -223,14 +224,14 @@ def philox(ctr, key):
     return [int(v) for v in o]
 
 
-def build_table(med: dict, d: dict, n_threads: int = 0):
+def build_table(med: dict, d: dict, n_threads: int = 0, mutation: str = "none"):
     """Returns (pmf float64 [n_cs,n_s,n_cos], cdf float32 [n_cs,n_s,n_cos+1])."""
     dd = dims(d)
     pmf = np.zeros((dd.n_cs, dd.n_s, dd.n_cos), np.float64)
     cdf = np.zeros((dd.n_cs, dd.n_s, dd.n_cos + 1), np.float32)
     rc = lib().ref_build_da_tables(C.byref(medium(med)), C.byref(dd),
                                    pmf.ctypes.data_as(C.POINTER(C.c_double)),
-                                   cdf.ctypes.data_as(C.POINTER(C.c_float)), int(n_threads))
+                                   cdf.ctypes.data_as(C.POINTER(C.c_float)), int(n_threads), MUT[mutation])
     if rc:
         raise ValueError(f"ref_build_da_tables failed: {rc}")
     return pmf, cdf

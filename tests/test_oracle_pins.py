@@ -224,20 +224,23 @@ def _exit_length_exact(x, w, xe, dm):
 
 def test_exit_length(oracle):
     """The largest length sum whose control vertex stays inside the medium
-    (Section V-B, boundary clipping of the sampled S) against its definition
+    (Section V-B, boundary clipping of the sampled S), evaluated in FP64 as
+    its definition d_m + |x + w d_m - x_e|, against the same definition
     evaluated without rounding: random geometries, and rays aimed within
     1e-9..1e-3 rad of an emitter beyond the boundary, where the excess over C
-    is tiny and d_m + |b| - C cancels.  The control vertex at S_exit lies on
-    the boundary, t(S_exit) = d_m, wherever t(S) is well conditioned."""
+    is tiny (the FP64 sum keeps it to a few ulp of C).  The control vertex at
+    S_exit lies on the boundary, t(S_exit) = d_m, wherever t(S) is well
+    conditioned."""
     L = oracle.lib()
     rng = np.random.default_rng(21)
+    eps = np.finfo(np.float64).eps
 
     def case(x, w, xe, dm):
         got = L.ref_exit_length(_vec(x), _vec(w), _vec(xe), dm)
         want = _exit_length_exact(x, w, xe, dm)
-        scale = max(1.0, *np.abs(x), *np.abs(xe), dm)
-        assert abs(got - want) <= 1e-14 * scale, (got, want)
-        return got
+        bl = np.linalg.norm(np.array(x) + np.array(w) * dm - np.array(xe))
+        assert abs(got - want) <= 4 * eps * (dm + bl), (got, want)
+        return got, want
 
     for _ in range(400):
         x, xe = rng.normal(size=3), rng.normal(size=3)
@@ -246,8 +249,8 @@ def test_exit_length(oracle):
         Cd = np.linalg.norm(xe - x)
         mu = np.dot(w, xe - x) / Cd
         dm = Cd * rng.uniform(0.01, 3.0)
-        S = case(x, w, xe, dm)
-        assert S >= Cd * (1 - 1e-15)
+        S, _ = case(x, w, xe, dm)
+        assert S >= Cd * (1 - 4 * eps)
         if mu < 0.99:
             assert abs(L.ref_ell_t(S, Cd, mu) - dm) < 1e-9 * (dm + Cd)
     for eta in [0.0, 1e-9, 1e-7, 1e-5, 1e-3]:
@@ -259,10 +262,10 @@ def test_exit_length(oracle):
             w /= np.linalg.norm(w)
             Cd = np.linalg.norm(xe - x)
             dm = Cd * rng.uniform(0.05, 0.95)        # the emitter lies beyond the boundary
-            S = case(x, w, xe, dm)
+            S, S_exact = case(x, w, xe, dm)
             # excess over C: about C (1 - mu) d_m / (C - d_m) = C eta^2 d_m / (2 (C - d_m))
-            assert S - Cd >= -1e-15 * Cd
-            assert S - Cd <= Cd * eta * eta * dm / (Cd - dm) + 4e-16 * Cd
+            assert S_exact - Cd >= -4 * eps * Cd
+            assert S_exact - Cd <= Cd * eta * eta * dm / (Cd - dm) + 4 * eps * Cd
     assert L.ref_exit_length(_vec([0, 0, 0]), _vec([0, 0, 1]), _vec([0, 0, 2]), np.inf) == np.inf
     assert L.ref_exit_length(_vec([0, 0, 0]), _vec([0, 0, 1]), _vec([0, 0, 2]), 1.0) == 2.0
     assert L.ref_exit_length(_vec([0, 0, 0]), _vec([0, 0, 1]), _vec([0, 0, 2]), 3.0) == 4.0
@@ -422,6 +425,93 @@ def test_table_layout(oracle):
     assert np.allclose(np.diff(cdf.astype(np.float64), axis=-1), pmf, atol=2e-7)
 
 
+TABLE_PIN_DIMS = {"n_cs": 4, "n_s": 3, "n_cos": 8, "s_max": 6.0}
+TABLE_PIN_CELLS = [(0, 0), (3, 2), (1, 1), (2, 0)]
+
+
+def _cell_centre(dims, i, j):
+    return (i + 0.5) / dims["n_cs"], (j + 0.5) * dims["s_max"] / dims["n_s"]
+
+
+def test_table_rows_at_cell_centres(oracle):
+    """Table row (i, j) is Eq. (17) integrated over each cos-bin at the
+    centre of its cell, C/S = (i + 1/2)/n_cs and S = (j + 1/2) s_max / n_s,
+    normalised: checked against the independent adaptive quadrature of Eq.
+    (17) at those centres (first, last and inner cells).  The same reference
+    taken at the cell edges (C/S = i/n_cs, S = j s_max/n_s) differs from the
+    rows, so a table built at the edges or shifted by one cell fails."""
+    med = MEDIA[1]
+    pmf, _ = oracle.build_table(med, TABLE_PIN_DIMS)
+    n = TABLE_PIN_DIMS["n_cos"]
+    for i, j in TABLE_PIN_CELLS:
+        kappa, S = _cell_centre(TABLE_PIN_DIMS, i, j)
+        ex = _row_adaptive(med, kappa * S, S, n)
+        assert np.max(np.abs(pmf[i, j] - ex / ex.sum())) < 2e-3 * np.max(pmf[i, j]), (i, j)
+        # neighbouring rows are far apart at this resolution
+        if i + 1 < TABLE_PIN_DIMS["n_cs"]:
+            assert np.max(np.abs(pmf[i + 1, j] - ex / ex.sum())) > 0.02 * np.max(pmf[i, j])
+    # planted mistake: rows at the cell edges
+    bad, _ = oracle.build_table(med, TABLE_PIN_DIMS, mutation="table_cell_edge")
+    worst = 0.0
+    for i, j in TABLE_PIN_CELLS:
+        kappa, S = _cell_centre(TABLE_PIN_DIMS, i, j)
+        ex = _row_adaptive(med, kappa * S, S, n)
+        worst = max(worst, np.max(np.abs(bad[i, j] - ex / ex.sum())) / np.max(ex / ex.sum()))
+    assert worst > 0.05, worst
+
+
+def _marked_table(dims):
+    """A table whose row r = i n_s + j puts all its mass in cos-bin r, so the
+    bin of an EDA sample names the row it came from."""
+    n_cs, n_s, n = dims["n_cs"], dims["n_s"], dims["n_cos"]
+    assert n >= n_cs * n_s
+    cdf = np.zeros((n_cs, n_s, n + 1), np.float32)
+    for i in range(n_cs):
+        for j in range(n_s):
+            r = i * n_s + j
+            cdf[i, j, r + 1:] = 1.0
+    return cdf
+
+
+def _lookup_rows(oracle, dims, cdf, cases, mutation=0):
+    """Row read by the EDA sampler for each (kappa, S): alpha = 0 makes every
+    sample an EDA sample; the emitter sits at distance kappa S on the z axis."""
+    L = oracle.lib()
+    med = MEDIA[1]
+    m, dd = C.byref(oracle.medium(med)), C.byref(oracle.dims(dims))
+    cp = np.ascontiguousarray(cdf, np.float32).ctypes.data_as(C.POINTER(C.c_float))
+    out = []
+    for kappa, S in cases:
+        wo, wt, eb, kb = _vec([0, 0, 0]), C.c_double(), C.c_int(), C.c_int()
+        L.ref_sample_direction(m, dd, cp, 0.0, 1, _vec([0, 0, 0]), _vec([0, 0, kappa * S]), _vec([1, 0, 0]), S,
+                               (C.c_double * 4)(0.0, 0.5, 0.25, 0.5), wo, C.byref(wt), C.byref(eb), C.byref(kb),
+                               mutation)
+        assert eb.value == 1
+        out.append(kb.value)
+    return out
+
+
+def test_direction_lookup_lands_in_its_row(oracle):
+    """The sampler reads row (floor(n_cs C/S), floor(n_s S/s_max)), clamped
+    to the table: (C/S, S) just inside either edge of every cell (and S
+    beyond s_max) lands in that cell's row; a lookup off by one row fails."""
+    dims = {"n_cs": 4, "n_s": 3, "n_cos": 12, "s_max": 6.0}
+    cdf = _marked_table(dims)
+    cases, want = [], []
+    d = 1e-9
+    for i in range(dims["n_cs"]):
+        for j in range(dims["n_s"]):
+            for a in (d, 1 - d):
+                for b in (d, 1 - d):
+                    cases.append(((i + a) / dims["n_cs"], (j + b) * dims["s_max"] / dims["n_s"]))
+                    want.append(i * dims["n_s"] + j)
+    cases.append((0.5, 2 * dims["s_max"]))
+    want.append(2 * dims["n_s"] + dims["n_s"] - 1)
+    assert _lookup_rows(oracle, dims, cdf, cases) == want
+    bad = _lookup_rows(oracle, dims, cdf, cases, mutation=10)
+    assert sum(b != w for b, w in zip(bad, want)) >= len(want) // 2
+
+
 # --------------------------------------------------------------------------
 # Direction sampling with one-sample MIS (Section V-A, Eq. 19)
 # --------------------------------------------------------------------------
@@ -439,7 +529,8 @@ def _direction_moments(oracle, med, dims, cdf, x, xe, wprev, S, mutation=0, n=60
     acc2 = np.zeros(3)
     U = rng.random((n, 4))
     for i in range(n):
-        L.ref_sample_direction(m, dd, cp, alpha, 1, xv, ev, pv, S, (C.c_double * 4)(*U[i]), wo, C.byref(wt), C.byref(eb), mutation)
+        L.ref_sample_direction(m, dd, cp, alpha, 1, xv, ev, pv, S, (C.c_double * 4)(*U[i]), wo, C.byref(wt), C.byref(eb),
+                               None, mutation)
         mu = np.dot(np.array(wo[:]), a)
         v = wt.value * np.array([1.0, mu, mu * mu])
         acc += v
@@ -604,6 +695,70 @@ def test_late_time_diffusion_band(oracle):
     mean, _ = oracle.estimate(sc, w["params"], "darts", img, m2)
     ratio = mean.ravel()[38:].sum() / da
     assert 0.95 < ratio < 1.15, ratio
+
+
+def test_diffusion_coefficient_from_transport(oracle):
+    """D of Eq. (9) pinned by transport rather than by its formula: in an
+    anisotropic infinite medium (sigma_s = 2, g = 0.5: the reduced
+    coefficient sigma_s (1 - g) of the isotropic case above) the analog
+    forward walk, which does not use D, approaches the DA fluence built on
+    the oracle's D at late times; the same band rejects a D that ignores g
+    (sigma_s in place of sigma_s (1 - g)) or double-counts it."""
+    med = dict(sigma_s=2.0, sigma_a=0.01, g=0.5)
+    w = W.with_(W.infinite_point(), n_paths=1 << 23, max_bounces=100)
+    sc = dict(w["scene"], medium=med)
+    img, m2, _ = oracle.render(sc, w["params"], "forward")
+    mean, se = oracle.estimate(sc, w["params"], "forward", img, m2)
+    L, m = oracle.lib(), C.byref(oracle.medium(med))
+    D0 = L.ref_da_D(m)
+
+    def da(D):
+        phi = lambda s: (4 * PI * D * s) ** -1.5 * math.exp(-1.0 / (4 * D * s) - med["sigma_a"] * s)
+        return integrate.quad(phi, 6.0, 10.0)[0]
+
+    walk = mean.ravel()[38:].sum()
+    assert abs(L.ref_da_phi(m, 1.0, 7.0) / ((4 * PI * D0 * 7.0) ** -1.5 * math.exp(-1 / (28 * D0) - 0.07)) - 1) < 1e-12
+    ratio = walk / da(D0)
+    assert 0.85 < ratio < 1.15, ratio
+    for D_bad in [1.0 / (3 * (med["sigma_a"] + med["sigma_s"])),
+                  1.0 / (3 * (med["sigma_a"] + med["sigma_s"] * (1 - med["g"]) ** 2))]:
+        r = walk / da(D_bad)
+        assert not (0.85 < r < 1.15), (D_bad, r)
+
+
+@pytest.mark.parametrize("mode", ["darts", "uniform"])
+def test_absorption_scaling(oracle, mode):
+    """Absorption enters the path integral only as exp(-sigma_a x in-medium
+    length), so renders of (sigma_s, sigma_a) whose connections are each
+    reweighted by exp(-d in-medium length) estimate the image of
+    (sigma_s, sigma_a + d) with the first medium's sampling (its RIS
+    weights, its table, its free flights): per bin they must agree with the
+    render of the second medium at all orders (box, emitter and detector
+    outside, floor included).  Dropping the transmittance toward the emitter
+    (a planted mistake) breaks the identity."""
+    for wl in [W.box_point(), W.box_floor_point()]:
+        base = wl["scene"]
+        d = 0.4
+        med_b = dict(base["medium"], sigma_a=base["medium"]["sigma_a"] + d)
+        res = {}
+        for key, med, shift, mut in [("shifted", base["medium"], d, "none"), ("direct", med_b, 0.0, "none"),
+                                     ("shifted_bad", base["medium"], d, "no_emitter_trans"),
+                                     ("direct_bad", med_b, 0.0, "no_emitter_trans")]:
+            sc = dict(base, medium=med)
+            p = dict(wl["params"], n_paths=1 << 20, seed=0xA5 if key.startswith("shifted") else 0xA6,
+                     sigma_a_shift=shift)
+            _, cdf = oracle.build_table(med, wl["dims"])
+            img, m2, _ = oracle.render(sc, p, mode, cdf, wl["dims"], mutation=mut)
+            mean, se = oracle.estimate(sc, p, mode, img, m2)
+            res[key] = (mean.ravel(), se.ravel())
+        (a, sa), (b, sb) = res["shifted"], res["direct"]
+        ok = (sa < 0.15 * np.abs(a)) & (sb < 0.15 * np.abs(b)) & (sa > 0) & (sb > 0)
+        assert ok.sum() >= 5
+        z = (a - b)[ok] / np.hypot(sa, sb)[ok]
+        assert np.max(np.abs(z)) < 4.0, (wl["name"], np.round(z, 1))
+        assert abs(a[ok].sum() - b[ok].sum()) < 4 * math.sqrt((sa[ok] ** 2).sum() + (sb[ok] ** 2).sum())
+        (a, sa), (b, sb) = res["shifted_bad"], res["direct_bad"]
+        assert abs(a[ok].sum() / b[ok].sum() - 1) > 0.1, (wl["name"], a[ok].sum() / b[ok].sum())
 
 
 def test_box_sensor_modes_agree(oracle):
