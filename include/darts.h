@@ -312,10 +312,14 @@ enum {
     DARTS_PW_ONB,         /* in: n[3]                    out: b1[3], b2[3]             */
     DARTS_PW_BOX_EXIT,    /* in: x[3], w[3], lo[3], hi[3] out: distance                */
     DARTS_PW_RIS,         /* in: x[3], w[3], xe[3], R_hi, d_m, row (bits), eps (bits),
-                                 u_sel                   out: ok, d, factor (medium)   */
+                                 u_sel                   out: ok, d, factor, selected
+                                                         candidate (-1 if none), mask
+                                                         of valid candidates (medium)  */
     DARTS_PW_DIRECTION,   /* in: x[3], xe[3], w_prev[3], S, u[4], use_eda, alpha
-                                                         out: w[3], weight, eda_branch
-                                                         (medium, table)               */
+                                                         out: w[3], weight, eda_branch,
+                                                         table row i n_s + j, cos-bin
+                                                         of the EDA density (-1: no
+                                                         table) (medium, table)        */
     DARTS_PW_MATH,        /* in: x                       out: rcp, rsqrt, log2, exp2 of x,
                                                          sin 2 pi x, cos 2 pi x (hardware
                                                          transcendental unit)          */

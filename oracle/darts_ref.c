@@ -298,6 +298,14 @@ int ref_ris_step(const ref_medium *m, int n_ris, const double x[3], const double
                  uint32_t row, uint32_t eps_bits, double u_sel,
                  double *d, double *factor, int mutation)
 {
+    return ref_ris_step_detail(m, n_ris, x, w, xe, R_hi, d_m, row, eps_bits, u_sel, d, factor, NULL, mutation);
+}
+
+int ref_ris_step_detail(const ref_medium *m, int n_ris, const double x[3], const double w[3],
+                        const double xe[3], double R_hi, double d_m,
+                        uint32_t row, uint32_t eps_bits, double u_sel,
+                        double *d, double *factor, ref_ris_detail *det, int mutation)
+{
     double st = m->sigma_s + m->sigma_a;
     /* medium-event probability p_m (Eq. (12)); candidates follow the
      * truncated exponential on [0, d_m) (Eq. (13)-(14)). */
@@ -321,6 +329,22 @@ int ref_ris_step(const ref_medium *m, int n_ris, const double x[3], const double
         lphi[i] = valid[i] ? ref_da_log_phi(m, ri, si) : -INFINITY;
         if (valid[i]) { any = 1; if (lphi[i] > lmax) lmax = lphi[i]; }
     }
+    if (det) {
+        /* how close each discrete decision sat to its boundary: validity
+         * (s_i > 0 and r_i < s_i) relative to R_hi */
+        det->mask = 0;
+        det->valid_margin = INFINITY;
+        for (int i = 0; i < n_ris; ++i) {
+            double p[3];
+            axpy3(x, w, dc[i], p);
+            double si = R_hi - dc[i], ri = dist3(p, xe);
+            double mg = fmin(fabs(si), fabs(si - ri)) / fabs(R_hi);
+            if (mg < det->valid_margin) det->valid_margin = mg;
+            if (valid[i]) det->mask |= 1u << i;
+        }
+        det->sel = -1;
+        det->pick_margin = INFINITY;
+    }
     if (!any) return 0;
     double wsum = 0.0, wi[8];
     for (int i = 0; i < n_ris; ++i) { wi[i] = valid[i] ? exp(lphi[i] - lmax) : 0.0; wsum += wi[i]; }
@@ -329,9 +353,11 @@ int ref_ris_step(const ref_medium *m, int n_ris, const double x[3], const double
     int sel = -1;
     for (int i = 0; i < n_ris; ++i) {
         cum += wi[i];
-        if (cum > target) { sel = i; break; }
+        if (det && fabs(cum - target) / wsum < det->pick_margin) det->pick_margin = fabs(cum - target) / wsum;
+        if (cum > target && sel < 0) { sel = i; if (!det) break; }
     }
     if (sel < 0) { for (int i = n_ris - 1; i >= 0; --i) if (wi[i] > 0.0) { sel = i; break; } }
+    if (det) det->sel = sel;
     *d = dc[sel];
     /* Unbiased contribution weight of the RIS estimator (Eq. (15), reading
      * p-hat as the numerator of Eq. (10) and summing over the candidates)
@@ -453,6 +479,44 @@ int ref_build_da_tables(const ref_medium *m, const ref_table_dims *dm,
  * from the table row of (C/S, S) by inverse transform, phi uniform; otherwise
  * draw from the phase function about the previous direction.  The returned
  * weight is phase / (one-sample MIS balance-heuristic pdf). */
+/* Row of the direction table for the cell holding (C/S, S): nearest cell,
+ * clamped to the table (Section V-A). */
+int ref_table_row(const ref_table_dims *dm, double C, double S, int mutation)
+{
+    int i = (int)floor(C / S * dm->n_cs);
+    int j = (int)floor(S / dm->s_max * dm->n_s);
+    if (mutation == REF_MUT_TABLE_ROW_OFF_BY_ONE) ++i;
+    if (i > dm->n_cs - 1) i = dm->n_cs - 1;
+    if (i < 0) i = 0;
+    if (j > dm->n_s - 1) j = dm->n_s - 1;
+    if (j < 0) j = 0;
+    return i * dm->n_s + j;
+}
+
+/* The one-sample MIS weight of Eq. (19) for a given direction w: the phase
+ * function over the mixture density, with the EDA density of cos-bin k of the
+ * table row of (C/S, S) (k < 0: the bin holding w . a). */
+double ref_direction_weight(const ref_medium *m, const ref_table_dims *dm, const float *cdf,
+                            double alpha, int use_eda, const double x[3], const double xe[3],
+                            const double w_prev[3], double S, const double w[3], int k)
+{
+    double a[3];
+    sub3(xe, x, a);
+    double C = len3(a);
+    for (int i = 0; i < 3; ++i) a[i] /= C;
+    double gam = (use_eda && C > 0.0) ? ref_gamma(C / S, alpha) : 0.0;
+    double p_hg = ref_hg_pdf(dot3(w_prev, w), m->g);
+    if (!(gam > 0.0)) return 1.0;
+    const float *row = cdf + (size_t)ref_table_row(dm, C, S, 0) * (dm->n_cos + 1);
+    if (k < 0) {
+        k = (int)floor((dot3(w, a) + 1.0) * 0.5 * dm->n_cos);
+        if (k > dm->n_cos - 1) k = dm->n_cos - 1;
+        if (k < 0) k = 0;
+    }
+    double p_eda = ((double)row[k + 1] - (double)row[k]) * dm->n_cos / (4.0 * PI);
+    return p_hg / (gam * p_eda + (1.0 - gam) * p_hg);
+}
+
 void ref_sample_direction(const ref_medium *m, const ref_table_dims *dm, const float *cdf,
                           double alpha, int use_eda, const double x[3], const double xe[3],
                           const double w_prev[3], double S, const double u[4],
@@ -464,16 +528,7 @@ void ref_sample_direction(const ref_medium *m, const ref_table_dims *dm, const f
     for (int i = 0; i < 3; ++i) a[i] /= C;
     double gam = (use_eda && C > 0.0) ? ref_gamma(C / S, alpha) : 0.0;
     const float *row = NULL;
-    if (gam > 0.0) {
-        int i = (int)floor(C / S * dm->n_cs);
-        int j = (int)floor(S / dm->s_max * dm->n_s);
-        if (mutation == REF_MUT_TABLE_ROW_OFF_BY_ONE) ++i;
-        if (i > dm->n_cs - 1) i = dm->n_cs - 1;
-        if (i < 0) i = 0;
-        if (j > dm->n_s - 1) j = dm->n_s - 1;
-        if (j < 0) j = 0;
-        row = cdf + ((size_t)i * dm->n_s + j) * (dm->n_cos + 1);
-    }
+    if (gam > 0.0) row = cdf + (size_t)ref_table_row(dm, C, S, mutation) * (dm->n_cos + 1);
     int k = -1;
     *eda_branch = 0;
     if (u[0] < gam) {

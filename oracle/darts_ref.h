@@ -156,6 +156,17 @@ int ref_ris_step(const ref_medium *m, int n_ris, const double x[3], const double
                  uint32_t row, uint32_t eps_bits, double u_sel,
                  double *d, double *factor, int mutation);
 
+/* The same step with how close its discrete decisions sat to their
+ * boundaries, for parity tests of an implementation in lower precision:
+ * mask of valid candidates, selected candidate (-1: none), the smallest
+ * |s_i| or |s_i - r_i| over R_hi (validity), and the smallest distance of a
+ * running weight sum from u_sel times the total, over the total (pick). */
+typedef struct { unsigned mask; int sel; double valid_margin, pick_margin; } ref_ris_detail;
+int ref_ris_step_detail(const ref_medium *m, int n_ris, const double x[3], const double w[3],
+                        const double xe[3], double R_hi, double d_m,
+                        uint32_t row, uint32_t eps_bits, double u_sel,
+                        double *d, double *factor, ref_ris_detail *det, int mutation);
+
 /* Integrand of the EDA table for one (C, S) cell (Eq. (17)), integrated over
  * each of n_cos cos-bins with the documented quadrature; out[n_cos]. */
 void ref_eda_row_raw(const ref_medium *m, double C, double S, int n_cos, double *out);
@@ -172,6 +183,13 @@ void ref_sample_direction(const ref_medium *m, const ref_table_dims *dims, const
                           double w_out[3], double *weight, int *eda_branch, int *bin, int mutation);
 /* (bin, may be NULL: the cos-bin whose mass enters the EDA density, -1 when
  * the EDA density is not used) */
+/* Row index i n_s + j of the table cell holding (C/S, S). */
+int ref_table_row(const ref_table_dims *dims, double C, double S, int mutation);
+/* MIS weight phase / mixture density (Eq. (19)) of a given direction w;
+ * cos-bin k of the EDA density (k < 0: the bin of w . a). */
+double ref_direction_weight(const ref_medium *m, const ref_table_dims *dims, const float *cdf,
+                            double alpha, int use_eda, const double x[3], const double xe[3],
+                            const double w_prev[3], double S, const double w[3], int k);
 
 /* Render: raw per-cell sums into image[n_bins][height][width] (+= semantics
  * are not used: the oracle writes, the caller accumulates); m2 (may be NULL)

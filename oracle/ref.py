@@ -47,6 +47,10 @@ def build(force: bool = True) -> str:
     return LIB_PATH
 
 
+class RisDetail(C.Structure):
+    _fields_ = [("mask", C.c_uint), ("sel", C.c_int), ("valid_margin", C.c_double), ("pick_margin", C.c_double)]
+
+
 class _Medium(C.Structure):
     _fields_ = [("sigma_s", C.c_double), ("sigma_a", C.c_double), ("g", C.c_double)]
 
@@ -126,6 +130,14 @@ def lib():
         L.ref_ris_step.restype = C.c_int
         L.ref_ris_step.argtypes = [C.POINTER(_Medium), C.c_int, pd, pd, pd, d, d, C.c_uint32,
                                    C.c_uint32, d, pd, pd, C.c_int]
+        L.ref_ris_step_detail.restype = C.c_int
+        L.ref_ris_step_detail.argtypes = [C.POINTER(_Medium), C.c_int, pd, pd, pd, d, d, C.c_uint32,
+                                          C.c_uint32, d, pd, pd, C.POINTER(RisDetail), C.c_int]
+        L.ref_table_row.restype = C.c_int
+        L.ref_table_row.argtypes = [C.POINTER(_Dims), d, d, C.c_int]
+        L.ref_direction_weight.restype = d
+        L.ref_direction_weight.argtypes = [C.POINTER(_Medium), C.POINTER(_Dims), C.POINTER(C.c_float),
+                                           d, C.c_int, pd, pd, pd, d, pd, C.c_int]
         L.ref_eda_row_raw.argtypes = [C.POINTER(_Medium), d, d, C.c_int, pd]
         L.ref_build_da_tables.restype = C.c_int
         L.ref_build_da_tables.argtypes = [C.POINTER(_Medium), C.POINTER(_Dims), pd,

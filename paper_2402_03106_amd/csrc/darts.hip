@@ -1089,9 +1089,12 @@ __global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
         float epc = 0.f;
         const float pc = isinf(d_m) ? 1.f : one_minus_exp_neg(Q.med.sigma_t * d_m, epc);
         float d = 0.f, f = 0.f;
+        uint32_t choice = 0;
         const bool okk = ris_distance(Q.med, C * C, dot(w, de), R_hi, pc, epc, bits(a[11]) & 31u, bits(a[12]), a[13],
-                                      d, f);
+                                      d, f, &choice);
         o[0] = okk ? 1.f : 0.f; o[1] = d; o[2] = f;
+        o[3] = okk ? (float)(choice & 0xFFu) : -1.f;
+        o[4] = (float)(choice >> 8);
         break;
     }
     case DARTS_PW_DIRECTION: {
@@ -1102,8 +1105,10 @@ __global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
         const float C = length(de);
         float wt;
         bool eb;
-        const V3 w = sample_direction(Q.med, Q.tb, a[15], a[14] != 0.f, de * rcp(C), C, S, wp, r, wt, eb);
+        int dbg[2] = {-1, -1};
+        const V3 w = sample_direction(Q.med, Q.tb, a[15], a[14] != 0.f, de * rcp(C), C, S, wp, r, wt, eb, dbg);
         o[0] = w.x; o[1] = w.y; o[2] = w.z; o[3] = wt; o[4] = eb ? 1.f : 0.f;
+        o[5] = (float)dbg[0]; o[6] = (float)dbg[1];
         break;
     }
     case DARTS_PW_EXIT_LENGTH: {

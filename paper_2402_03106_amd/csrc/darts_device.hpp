@@ -299,9 +299,11 @@ __device__ __forceinline__ void ellipse(float S, float C, float cm, float &den, 
 // albedo * mean(w) / w_selected that multiplies the path throughput.
 // b = dot(w, x_e - x), C2 = |x_e - x|^2, epc = 1 - pc = e^{-sigma_t d_m}.
 // ---------------------------------------------------------------------------
+// choice (diagnostics only; null in the kernels): selected candidate in bits
+// 0-7, mask of the valid candidates in bits 8-15.
 __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b, float R_hi, float pc,
                                              float epc, uint32_t row, uint32_t eps, float u_sel,
-                                             float &d_out, float &factor)
+                                             float &d_out, float &factor, uint32_t *choice = nullptr)
 {
     // Phi_i = (4 pi D s_i)^{-3/2} exp(E_i),  E_i = -r_i^2 / (4 D s_i) - sigma_a s_i:
     // the weights s_i^{-3/2} 2^{(E_i - E_max) log2 e} share one rsq per
@@ -346,6 +348,7 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
         q[i] = valid ? rq * rq * rq : 0.f;
         E[i] = valid ? e : -kInf;
         emax = fmaxf(emax, E[i]);
+        if (choice) *choice = (i == 0 ? 0u : *choice) | (valid ? 1u << (8 + i) : 0u);
     }
     if (!(emax > -kInf)) return false;
     float wv[8];
@@ -355,6 +358,7 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
     const double target = (double)u_sel * wsum;
     double cum = 0.0;
     float dsel = dc[7], wsel = wv[7];
+    uint32_t isel = 7;
     bool found = false;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -362,12 +366,15 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
         const bool take = !found && (cum > target);
         dsel = take ? dc[i] : dsel;
         wsel = take ? wv[i] : wsel;
+        if (choice) isel = take ? (uint32_t)i : isel;
         found = found || take;
     }
     if (!found) {  // only reachable through rounding: take the last positive weight
 #pragma unroll
-        for (int i = 0; i < 8; ++i) if (wv[i] > 0.f) { dsel = dc[i]; wsel = wv[i]; }
+        for (int i = 0; i < 8; ++i)
+            if (wv[i] > 0.f) { dsel = dc[i]; wsel = wv[i]; if (choice) isel = (uint32_t)i; }
     }
+    if (choice) *choice |= isel;
     d_out = dsel;
     factor = m.albedo * ((float)wsum * 0.125f) * rcp(wsel);
     return true;
@@ -383,9 +390,12 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
 // ---------------------------------------------------------------------------
 struct Table { const float *cdf; int n_cs, n_s, n_cos; float ns_over_smax; };
 
+// dbg (diagnostics only; null in the kernels): [0] table row i n_s + j
+// (-1 without the table), [1] the cos-bin whose EDA density enters the
+// weight (-1 without the table).
 __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb, float alpha, bool use_eda,
                                                V3 a /*unit, to emitter*/, float C, float S, V3 w_prev,
-                                               U4 r, float &weight, bool &eda_branch)
+                                               U4 r, float &weight, bool &eda_branch, int *dbg = nullptr)
 {
     const float u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
     float gam = 0.f;
@@ -396,6 +406,7 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
         const int i = min(max((int)(kappa * (float)tb.n_cs), 0), tb.n_cs - 1);
         const int j = min(max((int)(S * tb.ns_over_smax), 0), tb.n_s - 1);
         row = tb.cdf + ((size_t)i * tb.n_s + j) * (size_t)(tb.n_cos + 1);
+        if (dbg) dbg[0] = i * tb.n_s + j;
     }
     eda_branch = u0 < gam;
     V3 axis;
@@ -430,6 +441,7 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
         }
         const float p_eda = (c_hi - c_lo) * (float)tb.n_cos * kInv4Pi;
         p_mix = fmaf(gam, p_eda - p_hg, p_hg);
+        if (dbg) dbg[1] = k;
     }
     weight = p_hg * rcp(p_mix);
     return w;
