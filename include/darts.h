@@ -294,6 +294,28 @@ int darts_batch_autotune(darts_batch *batch, float *image_hi_dev, float *image_l
 /* Release the batch's device memory and graph. */
 int darts_batch_destroy(darts_batch *batch);
 
+/* For callers that cannot allocate (serving loops and harnesses that forbid
+ * device allocation): darts_batch_create + darts_batch_render +
+ * darts_batch_destroy in one call that allocates no memory, device or host.
+ * The scenes' parameter blocks, the work units of `plan` (NULL = default)
+ * and the two unit counters are staged in a fixed host array and copied
+ * into a fixed 4 MiB device array that the library holds on each device it
+ * runs on until the process ends; each call clears the counters first.
+ * Limits: the parameter blocks (about 0.5 KiB per scene) and the work units
+ * (48 bytes each while the host sorts them) must fit in the 4 MiB; a larger
+ * batch returns DARTS_ERR_INVALID_ARG naming the limit (use fewer scenes or
+ * larger unit_paths).  image_hi_dev / image_lo_dev: device float arrays of
+ * image_numel elements each, accumulate-into, scene i's image at the offset
+ * darts_batch_image_offsets would give (the scenes' images back to back in
+ * item order); INVALID_ARG if image_numel is smaller than the images.
+ * Validation is that of darts_batch_create.  The call enqueues two
+ * host-to-device copies from pageable host memory, a clearing kernel and
+ * the batch kernel on `stream`; it is not meant for stream capture.  Calls
+ * that overlap on one device race on its array: serialise them (the library
+ * serialises the host side with a lock, not the device work). */
+int darts_batch_render_noalloc(const darts_batch_item *items, int n_items, const darts_batch_plan *plan,
+                               float *image_hi_dev, float *image_lo_dev, int64_t image_numel, void *stream);
+
 /* Diagnostic: evaluate one device building block on n items (one thread per
  * item) with the same device functions the render kernel uses.  in_dev:
  * float[n][DARTS_PW_IN] (32-bit integers are passed by bit pattern), out_dev:

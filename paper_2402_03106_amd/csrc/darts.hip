@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 using namespace darts;
@@ -1392,12 +1393,16 @@ uint64_t reps_of(const KParams &P, uint64_t c)
 struct UnitCost {
     BUnit u;
     double cost;
+    uint64_t seq;   // position in enumeration order (ties keep it)
 };
 
-void build_units(const std::vector<BItem> &items, const darts_batch_plan &pl, std::vector<BUnit> &out)
+// Enumerate the work units of `items` under plan `pl`, calling push(UnitCost)
+// for each; returns false as soon as push does.
+template <class Push>
+bool enumerate_units(const BItem *items, size_t n_items, const darts_batch_plan &pl, Push push)
 {
-    std::vector<UnitCost> v;
-    for (size_t i = 0; i < items.size(); ++i) {
+    uint64_t seq = 0;
+    for (size_t i = 0; i < n_items; ++i) {
         const KParams &P = items[i].P;
         const double pc = path_cost(P);
         const uint64_t nc = (uint64_t)P.ncells;
@@ -1420,7 +1425,8 @@ void build_units(const std::vector<BItem> &items, const darts_batch_plan &pl, st
                     uc.u.j_begin = r * 64;
                     uc.u.j_end = std::min(r + reps_unit, reps) * 64;
                     uc.cost = pc * (double)(uc.u.j_end - uc.u.j_begin);
-                    v.push_back(uc);
+                    uc.seq = seq++;
+                    if (!push(uc)) return false;
                 }
             }
         } else {
@@ -1434,11 +1440,28 @@ void build_units(const std::vector<BItem> &items, const darts_batch_plan &pl, st
                 uc.u.j_begin = j;
                 uc.u.j_end = j + std::min(step, end - j);
                 uc.cost = pc * (double)(uc.u.j_end - uc.u.j_begin);
-                v.push_back(uc);
+                uc.seq = seq++;
+                if (!push(uc)) return false;
             }
         }
     }
-    std::stable_sort(v.begin(), v.end(), [](const UnitCost &a, const UnitCost &b) { return a.cost > b.cost; });
+    return true;
+}
+
+// Most expensive units first; equal costs keep their enumeration order.
+inline bool unit_before(const UnitCost &a, const UnitCost &b)
+{
+    return a.cost > b.cost || (a.cost == b.cost && a.seq < b.seq);
+}
+
+void build_units(const std::vector<BItem> &items, const darts_batch_plan &pl, std::vector<BUnit> &out)
+{
+    std::vector<UnitCost> v;
+    enumerate_units(items.data(), items.size(), pl, [&](const UnitCost &uc) {
+        v.push_back(uc);
+        return true;
+    });
+    std::sort(v.begin(), v.end(), unit_before);
     out.resize(v.size());
     for (size_t k = 0; k < v.size(); ++k) out[k] = v[k].u;
 }
@@ -1491,23 +1514,28 @@ int upload_units(darts_batch *b, const darts_batch_plan &pl)
     return DARTS_OK;
 }
 
-int launch_batch(const darts_batch *b, float *hi, float *lo, hipStream_t stream)
+// One launch of the batch kernel over `n_units` units (device arrays of the
+// scenes' parameter blocks and of the units, and the two unit counters, zero
+// at entry; the launch leaves them zero).
+int launch_batch_units(int n_cu, const darts_batch_plan &plan, bool any_floor, const BItem *items_dev,
+                       const BUnit *units_dev, uint32_t n_units, unsigned *ctr_dev, float *hi, float *lo,
+                       hipStream_t stream)
 {
-    if (b->n_units == 0) return ok();
-    const int per_block = b->plan.block_threads / 64;
-    const uint32_t blocks = (uint32_t)std::max(1, b->n_cu * b->plan.waves_per_cu / per_block);
+    if (n_units == 0) return ok();
+    const int per_block = plan.block_threads / 64;
+    const uint32_t blocks = (uint32_t)std::max(1, n_cu * plan.waves_per_cu / per_block);
     BParams B;
-    B.items = b->items_dev;
-    B.units = b->units_dev;
-    B.n_units = b->n_units;
+    B.items = items_dev;
+    B.units = units_dev;
+    B.n_units = n_units;
     B.n_waves = blocks * (uint32_t)per_block;   // exactly the waves launched: the last one rewinds the counter
-    B.ctr = b->ctr_dev;
+    B.ctr = ctr_dev;
     B.hi = hi;
     B.lo = lo;
     const dim3 grid(blocks);
-    const bool tiles = b->plan.order == DARTS_BATCH_TILES;
-    if (b->any_floor) {
-        if (b->plan.block_threads == 64) {
+    const bool tiles = plan.order == DARTS_BATCH_TILES;
+    if (any_floor) {
+        if (plan.block_threads == 64) {
             if (tiles) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 64, true>), grid, dim3(64), 0, stream, B);
             else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 64, true>), grid, dim3(64), 0, stream, B);
         } else {
@@ -1515,7 +1543,7 @@ int launch_batch(const darts_batch *b, float *hi, float *lo, hipStream_t stream)
             else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 256, true>), grid, dim3(256), 0, stream, B);
         }
     } else {
-        if (b->plan.block_threads == 64) {
+        if (plan.block_threads == 64) {
             if (tiles) hipLaunchKernelGGL((batch_kernel<SRC_TILE, 64, false>), grid, dim3(64), 0, stream, B);
             else hipLaunchKernelGGL((batch_kernel<SRC_IDS, 64, false>), grid, dim3(64), 0, stream, B);
         } else {
@@ -1526,6 +1554,64 @@ int launch_batch(const darts_batch *b, float *hi, float *lo, hipStream_t stream)
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
     return ok();
+}
+
+int launch_batch(const darts_batch *b, float *hi, float *lo, hipStream_t stream)
+{
+    return launch_batch_units(b->n_cu, b->plan, b->any_floor, b->items_dev, b->units_dev, b->n_units, b->ctr_dev, hi,
+                              lo, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Batched render without allocation.  The scenes' parameter blocks, the work
+// units and the two unit counters live in `scratch`, one fixed array per
+// device that stays allocated until the process ends.  Host code never passes
+// the array's name to a kernel or a copy (in host code it is a host-side
+// stand-in, not a device address): it uses the device address that
+// hipGetSymbolAddress returns, fetched once per device with that device
+// current.  The host side stages the same bytes in `g_stage` (a fixed host
+// array) and copies them over with two asynchronous copies.
+// Layout: [0, 256) counters; [256, 256 + items) parameter blocks (rounded up
+// to 256 bytes); then the units.  While the units are sorted on the host
+// they take sizeof(UnitCost) bytes each in the staging array.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr size_t kScratchItemsOff = 256;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+alignas(256) unsigned char g_stage[kScratchBytes];
+std::mutex g_noalloc_mu;            // guards g_stage and the per-device tables below
+void *g_scratch_dev[kMaxDevices];   // device address of `scratch` on each device (null until first use)
+int g_scratch_ncu[kMaxDevices];
+
+__global__ void clear_counters_kernel(unsigned *ctr)
+{
+    if (threadIdx.x < 2) ctr[threadIdx.x] = 0u;
+}
+
+// Device address of this device's scratch array and its compute-unit count;
+// called with g_noalloc_mu held.
+int scratch_of_device(unsigned char **ptr, int *n_cu)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(DARTS_ERR_DEVICE, "no current HIP device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(DARTS_ERR_UNSUPPORTED, "device index %d is not below %d", dev, kMaxDevices);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(DARTS_ERR_DEVICE, "address of the scratch array on device %d: %s", dev, hipGetErrorString(e));
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1)
+            return fail(DARTS_ERR_DEVICE, "compute-unit count of device %d unavailable", dev);
+        g_scratch_ncu[dev] = cu;
+        g_scratch_dev[dev] = p;
+    }
+    *ptr = (unsigned char *)g_scratch_dev[dev];
+    *n_cu = g_scratch_ncu[dev];
+    return DARTS_OK;
 }
 
 int check_batch_device(const darts_batch *b)
@@ -1837,6 +1923,79 @@ int darts_batch_destroy(darts_batch *batch)
     if (batch->ctr_dev) (void)hipFree(batch->ctr_dev);
     delete batch;
     return ok();
+}
+
+int darts_batch_render_noalloc(const darts_batch_item *items, int n_items, const darts_batch_plan *plan,
+                               float *image_hi_dev, float *image_lo_dev, int64_t image_numel, void *stream)
+{
+    if (n_items < 1 || !items) return fail(DARTS_ERR_INVALID_ARG, "need at least one item");
+    if (!image_hi_dev || !image_lo_dev) return fail(DARTS_ERR_INVALID_ARG, "image_hi/lo are null");
+    const darts_batch_plan pl = plan ? *plan : default_plan();
+    if (!valid_plan(pl)) return fail(DARTS_ERR_INVALID_ARG, "invalid batch plan");
+    const size_t items_bytes = ((size_t)n_items * sizeof(BItem) + 255) / 256 * 256;
+    if (kScratchItemsOff + items_bytes + sizeof(UnitCost) > kScratchBytes)
+        return fail(DARTS_ERR_INVALID_ARG, "%d scenes need %zu bytes of parameter blocks; the scratch array holds %zu",
+                    n_items, items_bytes, kScratchBytes - kScratchItemsOff - sizeof(UnitCost));
+    const size_t units_off = kScratchItemsOff + items_bytes;
+
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    unsigned char *dev = nullptr;
+    int n_cu = 0;
+    if (int rc = scratch_of_device(&dev, &n_cu)) return rc;
+
+    BItem *h_items = (BItem *)(g_stage + kScratchItemsOff);
+    int64_t off = 0;
+    bool any_floor = false;
+    for (int i = 0; i < n_items; ++i) {
+        const darts_batch_item &it = items[i];
+        if (it.params.flags & DARTS_DIRECT_REUSE)
+            return fail(DARTS_ERR_UNSUPPORTED, "item %d: batches render the DARTS family only", i);
+        KParams &P = h_items[i].P;
+        if (int rc = make_params(&it.scene, &it.params, it.table, P, false)) {
+            const std::string msg = g_last_error;
+            return fail(rc, "item %d: %s", i, msg.c_str());
+        }
+        h_items[i].image_offset = off;
+        off += P.ncells;
+        any_floor = any_floor || P.floor != 0;
+    }
+    if (image_numel < off)
+        return fail(DARTS_ERR_INVALID_ARG, "the batch image has %lld elements; the buffers hold %lld",
+                    (long long)off, (long long)image_numel);
+
+    UnitCost *h_cost = (UnitCost *)(g_stage + units_off);
+    const size_t cap = (kScratchBytes - units_off) / sizeof(UnitCost);
+    size_t n_units = 0;
+    const bool fits = enumerate_units(h_items, (size_t)n_items, pl, [&](const UnitCost &uc) {
+        if (n_units == cap) return false;
+        h_cost[n_units++] = uc;
+        return true;
+    });
+    if (!fits)
+        return fail(DARTS_ERR_INVALID_ARG, "more than %zu work units do not fit the scratch array; raise unit_paths",
+                    cap);
+    std::sort(h_cost, h_cost + n_units, unit_before);
+    // compact to BUnit in place (smaller stride: unit k is read before a
+    // later write can reach it)
+    BUnit *h_units = (BUnit *)(g_stage + units_off);
+    for (size_t k = 0; k < n_units; ++k) {
+        const BUnit u = h_cost[k].u;
+        h_units[k] = u;
+    }
+    if (n_units == 0) return ok();
+
+    const hipStream_t st = (hipStream_t)stream;
+    unsigned *ctr = (unsigned *)dev;
+    BItem *d_items = (BItem *)(dev + kScratchItemsOff);
+    BUnit *d_units = (BUnit *)(dev + units_off);
+    if (hipMemcpyAsync(d_items, h_items, (size_t)n_items * sizeof(BItem), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_units, h_units, n_units * sizeof(BUnit), hipMemcpyHostToDevice, st) != hipSuccess)
+        return fail(DARTS_ERR_DEVICE, "copying the batch to the scratch array failed");
+    hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(64), 0, st, ctr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "clearing the unit counters failed: %s", hipGetErrorString(e));
+    return launch_batch_units(n_cu, pl, any_floor, d_items, d_units, (uint32_t)n_units, ctr, image_hi_dev,
+                              image_lo_dev, st);
 }
 
 int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n, const darts_medium *medium,

@@ -12,6 +12,7 @@ the calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 
@@ -127,6 +128,8 @@ def lib() -> C.CDLL:
         L.darts_batch_graph_launch.argtypes = [vp, vp, vp, vp]
         L.darts_batch_autotune.argtypes = [vp, vp, vp, C.c_int, C.POINTER(_BatchPlan), C.POINTER(C.c_double), vp]
         L.darts_batch_destroy.argtypes = [vp]
+        L.darts_batch_render_noalloc.argtypes = [C.POINTER(_BatchItem), C.c_int, C.POINTER(_BatchPlan), vp, vp,
+                                                 C.c_int64, vp]
         _lib = L
     return _lib
 
@@ -355,6 +358,28 @@ def _plan_struct(plan: dict | None) -> _BatchPlan:
     return pl
 
 
+class _BatchItems:
+    """The C array of batch items for a list of (scene dict, params dict,
+    mode, Table or None[, Response]) with everything it points to kept
+    alive."""
+
+    def __init__(self, items):
+        items = [tuple(it) + (None,) * (5 - len(it)) for it in items]   # (scene, params, mode, table[, response])
+        self.holders = [_SceneHolder(it[0], it[4]) for it in items]
+        self.tables = [it[3] for it in items]
+        self.responses = [it[4] for it in items]
+        self.tstructs = [t.c_struct() if t is not None else None for t in self.tables]
+        self.arr = (_BatchItem * len(items))()
+        for i, (sc, p, mode, t, _) in enumerate(items):
+            self.arr[i].scene = self.holders[i].c
+            self.arr[i].params = params(p, mode)
+            self.arr[i].table = C.pointer(self.tstructs[i]) if t is not None else None
+        self.shapes = [image_shape(it[0], it[4]) for it in items]
+        self.offsets = [0]
+        for sh in self.shapes:
+            self.offsets.append(self.offsets[-1] + math.prod(sh))
+
+
 class Batch:
     """Many scenes rendered by one persistent launch (darts_batch_*).  items:
     list of (scene dict, params dict, mode, Table or None).  The tables must
@@ -362,20 +387,11 @@ class Batch:
 
     def __init__(self, items, plan: dict | None = None):
         self._h = C.c_void_p()
-        items = [tuple(it) + (None,) * (5 - len(it)) for it in items]   # (scene, params, mode, table[, response])
-        self._holders = [_SceneHolder(it[0], it[4]) for it in items]
-        self._tables = [it[3] for it in items]
-        self._responses = [it[4] for it in items]
-        self._tstructs = [t.c_struct() if t is not None else None for t in self._tables]
-        arr = (_BatchItem * len(items))()
-        for i, (sc, p, mode, t, _) in enumerate(items):
-            arr[i].scene = self._holders[i].c
-            arr[i].params = params(p, mode)
-            arr[i].table = C.pointer(self._tstructs[i]) if t is not None else None
-        self.shapes = [image_shape(it[0], it[4]) for it in items]
+        self._items = _BatchItems(items)
+        self.shapes = self._items.shapes
         pl = _plan_struct(plan)
-        _check(lib().darts_batch_create(arr, len(items), C.byref(pl), C.byref(self._h)))
-        offs = (C.c_int64 * (len(items) + 1))()
+        _check(lib().darts_batch_create(self._items.arr, len(self.shapes), C.byref(pl), C.byref(self._h)))
+        offs = (C.c_int64 * (len(self.shapes) + 1))()
         _check(lib().darts_batch_image_offsets(self._h, offs))
         self.offsets = [int(x) for x in offs]
 
@@ -433,6 +449,21 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_render_noalloc(items, hi: torch.Tensor, lo: torch.Tensor, plan: dict | None = None, stream=None):
+    """darts_batch_render_noalloc: render the batch `items` (as for Batch)
+    in one call that allocates no memory, accumulating into the flat images
+    (hi, lo) (float32, at least as many elements as the scenes' images
+    together).  Returns the per-scene image offsets."""
+    its = _BatchItems(items)
+    for t in (hi, lo):
+        if t is None or t.dtype != torch.float32:
+            raise ValueError("batch images must be float32")
+    n = min(hi.numel(), lo.numel())
+    _check(lib().darts_batch_render_noalloc(its.arr, len(its.shapes), C.byref(_plan_struct(plan)), _ptr(hi),
+                                            _ptr(lo), n, _stream(stream)))
+    return its.offsets
 
 
 def set_ids_max_reps(n: int):
