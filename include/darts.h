@@ -188,8 +188,10 @@ int darts_build_response(const float *w_host, int n_bins, float *response_dev, v
  *   image_hi_dev, image_lo_dev: device float[n_bins][height][width]
  *     ([height][width] with a sensor response),
  *     accumulate-into; hi + lo is a compensated (two-float) sum.
- *   image_m2_dev (nullable): accumulate-into sums of squared per-path (DARTS
- *     family) or per-path-per-bin (vanilla) contributions.
+ *   image_m2_dev (nullable): accumulate-into sums over paths of the square
+ *     of each path's total contribution to the cell (the DARTS family adds
+ *     to one cell per path; a vanilla path adds to every bin its length
+ *     reaches, and each of those sums is squared once).
  *   stats_dev (nullable): accumulate-into uint64[DARTS_ST_COUNT].
  *   table: required when flags contain DARTS_EDA_DIR, else may be NULL.
  * The per-cell estimate is (hi + lo) / (number of paths mapped to the cell),

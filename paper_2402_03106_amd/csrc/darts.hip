@@ -131,6 +131,10 @@ struct PathState {
     float dlog_g;     // sum of d log f_HG / dg over walk vertices so far
     int n_surf;       // floor vertices among vertices 1..k
     bool on_floor;    // the current vertex lies on the floor
+    // vanilla with squared sums: the bin whose contributions this path is
+    // summing (-1: none yet) and that sum
+    int vbin;
+    float vpart;
 };
 
 // Emitter j's position, start and scale.  The kernels reach the parameter
@@ -185,6 +189,8 @@ __device__ bool setup_path(const KParams &P, U4 r, int bin, int px, int py, Path
     s.acc = 0.f;
     s.L_med = 0.f;
     s.dlog_g = 0.f;
+    s.vbin = -1;
+    s.vpart = 0.f;
     if (P.resp_cdf && !vanilla) {
         // target segment drawn with probability proportional to W, the path
         // weighted by W_k over that probability (Eq. (4))
@@ -520,6 +526,15 @@ __device__ __forceinline__ void direction_vanilla(const KParams &P, PathState &s
     s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
 }
 
+// Adds the square of the path's running sum for its current bin to m2.
+__device__ __forceinline__ void vanilla_flush_m2(const KParams &P, const PathState &s, int64_t pixel)
+{
+    if (s.vbin >= 0) {
+        const int64_t cell = P.resp_w ? pixel : (int64_t)s.vbin * P.npix + pixel;
+        unsafeAtomicAdd(P.m2 + cell, s.vpart * s.vpart);
+    }
+}
+
 template <bool FLOOR, class ST>
 __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathState &s, ST &st)
 {
@@ -563,7 +578,20 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
             const float v = wsens * s.beta * s.em_scale * f_loc * fast_exp(-m.sigma_t * r_in) * ir * ir;
             const int64_t cell = P.resp_w ? pixel : (int64_t)bin * P.npix + pixel;
             add_compensated(P.hi, P.lo, cell, v, 0.f);
-            if (P.m2) unsafeAtomicAdd(P.m2 + cell, v * v);
+            if (P.m2) {
+                // squares of per-path-per-bin sums: a path's length never
+                // decreases (a flight of d adds d to Le and shortens the
+                // distance to the emitter by at most d), so its contributions
+                // to one bin are consecutive and one running sum suffices
+                const int vb = P.resp_w ? 0 : bin;
+                if (vb != s.vbin) {
+                    vanilla_flush_m2(P, s, pixel);
+                    s.vbin = vb;
+                    s.vpart = v;
+                } else {
+                    s.vpart += v;
+                }
+            }
             st.inc(DARTS_ST_CONNECTIONS);
             s.acc += v;
         } else {
@@ -734,6 +762,7 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
             } else {
                 state = LANE_NEED;
                 if (s.acc == 0.f) st.inc(DARTS_ST_ZERO_PATHS);
+                if (MODE == 1 && P.m2) vanilla_flush_m2(P, s, pixel);
                 if (MODE == 0) {
                     if (OUT == OUT_PATHS) {
                         P.path_out[p - P.path_offset] = s.acc;

@@ -154,6 +154,30 @@ def test_batch_autotune(D):
     assert_same(batch_images(D, b, hi, lo), separate(D, items))
 
 
+def test_batch_compensated_global_atomics(D):
+    """Id-order units add every finished path's sum to its cell with a global
+    compensated atomic pair: two infinite-medium scenes with 1024 paths per
+    cell from different waves; hi + lo equals the exact sum of the per-path
+    values to 1e-9 of the sum of their magnitudes."""
+    items, exact, scale = [], [], []
+    for seed in (0xA1, 0xB2):
+        w = W.infinite_point()
+        sc, pr, dm = w["scene"], dict(w["params"], seed=seed), w["dims"]
+        t = D.build_da_tables(sc["medium"], dm)
+        vals = D.render_paths(sc, pr, "darts", t).cpu().numpy().astype(np.float64)
+        idx = np.arange(pr["n_paths"]) % 64
+        exact.append(np.bincount(idx, weights=vals, minlength=64))
+        scale.append(np.bincount(idx, weights=np.abs(vals), minlength=64))
+        items.append((sc, pr, "darts", t))
+    b = D.Batch(items, {"order": "ids", "block_threads": 64, "waves_per_cu": 16, "unit_paths": 64})
+    hi, lo = b.empty()
+    b.render(hi, lo)
+    for h, l, e, sc_ in zip(b.images(hi), b.images(lo), exact, scale):
+        tot = (h.double() + l.double()).cpu().numpy().ravel()
+        err = np.abs(tot - e) / np.maximum(sc_, 1e-300)
+        assert err.max() <= 1e-9, err.max()
+
+
 def test_batch_vs_oracle(D, oracle):
     """Four media of the batched sweep on an 8x8 sensor, 32 bins over
     [0, 10), 2^15 paths each: batch images against the FP64 oracle with the

@@ -24,8 +24,12 @@ def D():
 
 @pytest.mark.parametrize("wname,mode", [("box_point", "darts"), ("box_point", "uniform"),
                                         ("box_hg_small", "darts"), ("box_hg_small", "da_only"),
-                                        ("infinite_point", "darts")])
+                                        ("infinite_point", "darts"), ("box_hg_grad", "darts")])
 def test_gradient_matches_oracle(D, oracle, wname, mode):
+    """Replay gradient of sum_c G_c I_c (G uniform random per cell) against
+    the FP64 oracle's on the same paths, to 2e-3 of the largest component;
+    box_hg_grad is the differentiable workload at its own size (128x128
+    pixels x 512 bins, 2^22 paths)."""
     w = getattr(W, wname)()
     sc, pr, dm = w["scene"], w["params"], w["dims"]
     gimg = np.random.default_rng(1).random(oracle.image_shape(sc))
@@ -60,7 +64,10 @@ def test_gradient_matches_finite_differences_c4(D, loss, h_abs):
     resolved.  Replay gradients vs central differences (h = 3% of each
     parameter, or h = 1e-3 absolute, where the differences are noisier: a
     perturbation flips a fraction ~h of the paths' discrete choices; common
-    random numbers, tables rebuilt at each perturbed medium) over 4 seeds."""
+    random numbers, tables rebuilt at each perturbed medium) over 8 seeds,
+    tested on the per-seed differences (replay and differences share each
+    seed's paths, so their errors are correlated and only the paired
+    difference has the right spread)."""
     w = W.box_hg_grad()
     n_paths = w["params"]["n_paths"]
     tmed, med = w["target_medium"], w["scene"]["medium"]
@@ -73,7 +80,7 @@ def test_gradient_matches_finite_differences_c4(D, loss, h_abs):
         weight = torch.exp(-torch.arange(nb, dtype=torch.float64, device="cuda") / 64.0)[:, None, None] \
             .expand(nb, w["scene"]["sensor"]["height"], w["scene"]["sensor"]["width"]).contiguous()
     G, F = [], []
-    for seed in range(4):
+    for seed in range(8):
         img, n, sc, pr, table = _render(D, w, med, seed + 1, n_paths)
         g = D.render_transient_backward(sc, pr, "darts", table, (weight / n).float())
         torch.cuda.synchronize()
@@ -86,12 +93,15 @@ def test_gradient_matches_finite_differences_c4(D, loss, h_abs):
             fd.append(((weight * (ip - im)).sum() / (2 * h)).item())
         F.append(fd)
     G, F = np.array(G), np.array(F)
-    se = np.hypot(G.std(0, ddof=1), F.std(0, ddof=1)) / math.sqrt(len(G))
-    z = (G.mean(0) - F.mean(0)) / se
-    print(loss, "replay", G.mean(0), "+-", G.std(0, ddof=1) / 2, "fd", F.mean(0), "+-", F.std(0, ddof=1) / 2, "z", z)
+    n = len(G)
+    diff = G - F
+    se = diff.std(0, ddof=1) / math.sqrt(n)
+    z = diff.mean(0) / se
+    print(loss, "replay", G.mean(0), "+-", G.std(0, ddof=1) / math.sqrt(n), "fd", F.mean(0), "+-",
+          F.std(0, ddof=1) / math.sqrt(n), "paired difference", diff.mean(0), "+-", se, "z", z)
     assert np.max(np.abs(z)) < 4.0, (G.mean(0), F.mean(0), z)
     if loss == "time_weighted":   # resolved: each component at least 5 standard errors from zero
-        assert np.all(np.abs(G.mean(0)) > 5 * G.std(0, ddof=1) / 2)
+        assert np.all(np.abs(G.mean(0)) > 5 * G.std(0, ddof=1) / math.sqrt(n))
 
 
 def test_autograd_function(D):

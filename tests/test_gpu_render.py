@@ -276,6 +276,58 @@ def test_compensated_accumulation(D, oracle):
     assert err.max() <= 1e-9, err.max()
 
 
+def test_compensated_global_atomics(D, oracle):
+    """The id-range decomposition adds each finished path's sum to its cell
+    with a global FP32 atomic and forms the rounding error of that addition
+    by TwoSum from the value the atomic returns; this is exact only if the
+    device's atomic addition rounds to nearest like an ordinary FP32 add.
+    Forced onto that path, the infinite-medium render puts 1024 paths from
+    1024 different waves into each of its 64 cells: hi + lo must equal the
+    exact sum of the GPU's own per-path values to 1e-9 of the sum of their
+    magnitudes, where hi alone (plain FP32 accumulation) misses that bar."""
+    w = W.infinite_point()
+    table, _ = tables(D, oracle, w)
+    sc, pr = w["scene"], w["params"]
+    vals = D.render_paths(sc, pr, "darts", table).cpu().numpy().astype(np.float64)
+    idx = np.arange(pr["n_paths"]) % 64
+    exact = np.bincount(idx, weights=vals, minlength=64)
+    scale = np.maximum(np.bincount(idx, weights=np.abs(vals), minlength=64), 1e-300)
+    D.set_ids_max_reps(1 << 40)
+    try:
+        hi, lo, _, _ = D.render_transient(sc, pr, "darts", table)
+        torch.cuda.synchronize()
+    finally:
+        D.set_ids_max_reps(16)
+    h = hi.double().cpu().numpy().ravel()
+    tot = h + lo.double().cpu().numpy().ravel()
+    err, err_hi = np.abs(tot - exact) / scale, np.abs(h - exact) / scale
+    print(f"id ranges: compensated {err.max():.2e}, hi alone {err_hi.max():.2e}")
+    assert err.max() <= 1e-9, err.max()
+    assert err_hi.max() > 1e-8
+
+
+@pytest.mark.parametrize("wname,mode", [("box_hg_small", "vanilla"), ("box_point", "vanilla"),
+                                        ("infinite_point", "vanilla"), ("box_hg_small", "darts"),
+                                        ("box_hg", "darts")])
+def test_second_moments_match_oracle(D, oracle, wname, mode):
+    """Per-cell sums of squares (image_m2) against the oracle's on the same
+    paths: the DARTS family squares each path's value; vanilla squares the
+    sum of each path's contributions to a bin (a path's length never
+    decreases, and its repeated visits of a bin are summed before
+    squaring).  Totals to 2e-4 and relative L2 over the cells to 5e-4 (a
+    path whose FP32 rounding flipped a discrete choice moves its square;
+    measured up to 4e-5 and 7e-5)."""
+    w = WORKLOADS[wname]()
+    table, cdf = tables(D, oracle, w)
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    _, m2_g, _ = gpu_image(D, w, mode, table)
+    _, m2_o, _ = oracle.render(sc, pr, mode, cdf, dm)
+    tot = abs(m2_g.sum() - m2_o.sum()) / m2_o.sum()
+    rel = np.linalg.norm(m2_g - m2_o) / np.linalg.norm(m2_o)
+    print(f"{wname}/{mode}: m2 total {tot:.2e}, relative L2 {rel:.2e}")
+    assert tot <= 2e-4 and rel <= 5e-4, (tot, rel)
+
+
 @pytest.mark.parametrize("wname,mode", [("box_hg", "darts"), ("box_hg", "uniform"), ("infinite_point", "darts"),
                                         ("box_hg_small", "eda_only")])
 def test_image_is_sum_of_path_values(D, oracle, wname, mode):

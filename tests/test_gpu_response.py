@@ -75,6 +75,22 @@ def test_response_image_parity(D, oracle, wname, mode):
         assert sg["rejected"] == 0
 
 
+@pytest.mark.parametrize("mode", ["vanilla", "darts"])
+def test_response_second_moments_match_oracle(D, oracle, mode):
+    """Per-pixel sums of squares under the two-peak response against the
+    oracle's on the same paths: with a response every contribution of a
+    path goes to its pixel, and the path's total is squared once."""
+    sc, pr, dm, resp, R, t, cdf = case(D, oracle, "box_hg_small", 1 << 16)
+    _, _, m2, _ = D.render_transient(sc, pr, mode, t, want_m2=True, response=R)
+    torch.cuda.synchronize()
+    m2_g = m2.double().cpu().numpy()
+    _, m2_o, _ = oracle.render_response(sc, pr, mode, resp, cdf, dm)
+    tot = abs(m2_g.sum() - m2_o.sum()) / m2_o.sum()
+    rel = np.linalg.norm(m2_g - m2_o) / np.linalg.norm(m2_o)
+    print(f"{mode}: m2 total {tot:.2e}, relative L2 {rel:.2e}")
+    assert tot <= 2e-4 and rel <= 5e-4, (tot, rel)
+
+
 def test_vanilla_response_is_weighted_transient_on_gpu(D, oracle):
     """Same paths: the vanilla response image equals the W-weighted sum of
     the vanilla time-resolved image up to the order of the additions."""
