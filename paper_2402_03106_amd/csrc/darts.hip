@@ -59,6 +59,7 @@ struct KParams {
     float em_scale[DARTS_MAX_EMITTERS];  // power / (4 pi) * n_em
     int sensor_kind;
     float origin[3], dir[3], du[3], dv[3];
+    float inv_dir[3];           // 1 / dir per axis (orthographic sensor; 0 where dir is 0)
     int width, height;
     float inv_width, inv_height;
     float beta0;
@@ -92,9 +93,11 @@ struct KParams {
 
 constexpr int kBlock = 256;
 // Minimum resident waves per SIMD the render kernel is compiled for (caps its
-// VGPR budget at 512 / waves).
+// VGPR budget at 512 / waves).  At 4 the path loop keeps its 96 VGPRs without
+// spilling; measured on the box frame, 4 to 8 resident waves time within a
+// few per cent of each other (the loop is bound by VALU issue, not latency).
 #ifndef DARTS_RENDER_WAVES_PER_SIMD
-#define DARTS_RENDER_WAVES_PER_SIMD 7
+#define DARTS_RENDER_WAVES_PER_SIMD 4
 #endif
 // The batched kernel keeps more registers (it runs the whole pool per work
 // unit from parameters in constant memory) and is faster at 4.
@@ -124,6 +127,7 @@ struct PathState {
     float dm;         // distance to the boundary along w (inf: infinite medium)
     int k;            // vertex index
     V3 xe;            // chosen emitter position
+    int em;           // its index
     float em_scale;   // its intensity power / (4 pi) divided by its selection probability
     float acc;        // sum of this path's contributions
     // derivative bookkeeping for the backward pass (detached sampling)
@@ -143,10 +147,21 @@ struct PathState {
 // rather than keeping every emitter's fields live in scalar registers.
 __device__ __forceinline__ void emitter(const KParams &P, int j, V3 &pos, float &start, float &scale)
 {
-    if (P.n_em == 1) j = 0;
+    if (P.n_em == 1) {   // wave-uniform: scalar loads
+        pos = V3{P.em_pos[0][0], P.em_pos[0][1], P.em_pos[0][2]};
+        start = P.em_start[0];
+        scale = P.em_scale[0];
+        return;
+    }
     pos = V3{P.em_pos[j][0], P.em_pos[j][1], P.em_pos[j][2]};
     start = P.em_start[j];
     scale = P.em_scale[j];
+}
+
+__device__ __forceinline__ V3 emitter_pos(const KParams &P, int j)
+{
+    if (P.n_em == 1) return V3{P.em_pos[0][0], P.em_pos[0][1], P.em_pos[0][2]};   // scalar loads
+    return V3{P.em_pos[j][0], P.em_pos[j][1], P.em_pos[j][2]};
 }
 
 __device__ __forceinline__ float dlog_hg_dg(float mu, float g)
@@ -182,6 +197,7 @@ __device__ bool setup_path(const KParams &P, U4 r, int bin, int px, int py, Path
     j = min(j, P.n_em - 1);
     float start;
     emitter(P, j, s.xe, start, s.em_scale);
+    s.em = j;
     s.beta = P.beta0;
     s.k = 0;
     s.n_surf = 0;
@@ -215,7 +231,28 @@ __device__ bool setup_path(const KParams &P, U4 r, int bin, int px, int py, Path
     st.inc(DARTS_ST_PATHS);
     float t_in = 0.f, t_out = kInf;
     if (P.box) {
-        if (!box_entry(P.bx, pos, w, t_in, t_out)) return false;
+        if (P.sensor_kind == 1) {
+            // every ray of the orthographic sensor has the same direction: its
+            // zero components are wave-uniform tests and 1/dir comes from the host
+            float tn = -kInf, tf = kInf;
+            bool hit = true;
+            const float xs[3] = {pos.x, pos.y, pos.z};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (P.dir[a] == 0.f) {
+                    hit = hit && !(xs[a] < P.bx.lo[a] || xs[a] > P.bx.hi[a]);
+                } else {
+                    const float t1 = (P.bx.lo[a] - xs[a]) * P.inv_dir[a], t2 = (P.bx.hi[a] - xs[a]) * P.inv_dir[a];
+                    tn = fmaxf(tn, fminf(t1, t2));
+                    tf = fminf(tf, fmaxf(t1, t2));
+                }
+            }
+            t_in = fmaxf(tn, 0.f);
+            t_out = tf;
+            if (!(hit && tf > t_in)) return false;
+        } else if (!box_entry(P.bx, pos, w, t_in, t_out)) {
+            return false;
+        }
     }
     s.x = fma3(pos, w, t_in);
     s.w = w;
@@ -605,28 +642,41 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
 }
 
 // ---------------------------------------------------------------------------
-// Path pool.  A wave works through a range [j_begin, j_end) of path slots; its
-// lanes pull the next slots once kRefillMin of them have finished their paths
-// (ballot + popcount on a wave-uniform counter, no memory atomics), so lanes
-// stay busy until the range is exhausted.  One loop iteration is: stream-0 Philox of
-// the current vertex -> camera set-up (fresh path) or direction sampling;
-// stream-1 Philox -> connection and free flight.
+// Path pool.  A wave works through a range [j_begin, j_end) of path slots.
+// New paths are set up in bulk: when lanes need a path and the wave's queue
+// is empty, all 64 lanes set up the next 64 slots at once (camera ray, entry
+// into the medium, target interval, early-exit test) and the paths that
+// survive set-up are written, compacted, to the wave's queue in LDS.  A lane
+// whose path has ended takes the next queued path at the top of the next
+// iteration (ballot + popcount on the wave-uniform queue head), so set-up
+// runs with full lanes once per 64 paths instead of for the few lanes that
+// happen to need a path, and no lane waits for others before it refills.
+// One loop iteration is then: stream-0 Philox of the current vertex and
+// direction sampling (paths past their first vertex); stream-1 Philox ->
+// connection and free flight.
 //
 // Two slot sources:
 //  - SRC_TILE: slot j is repetition j / 64 of cell c0 + (j mod 64) of a tile
-//    of 64 consecutive cells.  Per-cell sums go to compensated LDS
-//    accumulators (one slot per tile cell), flushed by the caller with one
-//    compensated global atomic pair per cell: the histogram is privatised.
+//    of 64 consecutive cells; a bulk set-up covers one repetition of the
+//    whole tile, lane l taking cell c0 + l.  Per-cell sums go to compensated
+//    LDS accumulators (one slot per tile cell), flushed by the caller with
+//    one compensated global atomic pair per cell: the histogram is
+//    privatised.
 //  - SRC_IDS: slot j is path id j itself, in cell c0 + (j - j_begin) (wrapped
 //    once at n_cells; the caller keeps ranges no longer than n_cells).  Each
 //    finished path adds its sum to the global image with one compensated
 //    atomic pair: suited to scenes with few paths per cell.
 // ---------------------------------------------------------------------------
 enum { LANE_NEED = 0, LANE_FRESH = 1, LANE_ACTIVE = 2, LANE_DONE = 3 };
-// Lanes waiting for a new path before the wave sets up new paths (box frame:
-// 8 is fastest among 1-16; DARTS -2%, uniform sampling -9%).
-constexpr int kRefillMin = 8;
 enum { SRC_TILE = 0, SRC_IDS = 1 };
+
+// Set-up path queue of one wave in LDS, structure of arrays: field f of
+// entry i at q[f * 64 + i].
+enum {
+    Q_X = 0, Q_W = 3, Q_LE = 6, Q_DM, Q_C, Q_GLO, Q_GHI, Q_EMS, Q_EM, Q_PLO, Q_PHI, Q_CLO, Q_CHI, Q_PIX,
+    Q_FIELDS
+};
+constexpr int kQueueFloats = Q_FIELDS * 64;
 
 __device__ __forceinline__ void compensated_lds_add(float *hi, float *lo, int i, float v)
 {
@@ -638,19 +688,17 @@ __device__ __forceinline__ void compensated_lds_add(float *hi, float *lo, int i,
 template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, int SRC, bool FLOOR>
 __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end,
                                          float *img_hi, float *img_lo, float *acc_hi, float *acc_lo,
-                                         float *acc_m2, Stats<STATS> &st, double *gacc)
+                                         float *acc_m2, float *q, Stats<STATS> &st, double *gacc)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t lanes_below = (1ull << lane) - 1ull;
 
-    // SRC_TILE: lane l describes tile cell c0 + l (time bin, pixel, repetition
-    // bounds); a lane starting a path of cell c0 + sl reads lane sl's
-    // description with a cross-lane permute instead of dividing 64-bit
-    // indices per path.
-    // packed in two registers: my_bf = bin | flags << 29 (bit 29: the cell
-    // exists, bit 30: cell < r0, bit 31: cell < r1), my_xy = px | py << 16
+    // SRC_TILE: lane l describes tile cell c0 + l (time bin, pixel,
+    // repetition bounds), packed in two registers: my_bf = bin | flags << 29
+    // (bit 29: the cell exists, bit 30: cell < r0, bit 31: cell < r1),
+    // my_xy = px | py << 16.  A bulk set-up of repetition m gives lane l a
+    // path of its own cell.
     uint32_t my_bf = 0, my_xy = 0;
-    float my_gw = 0.f;
     if (SRC == SRC_TILE) {
         const int64_t my_cell = c0 + lane;
         if (j_begin < j_end && my_cell < P.ncells) {
@@ -661,12 +709,12 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
             my_bf = (uint32_t)b | (1u << 29) | ((uint64_t)my_cell < P.r0 ? 1u << 30 : 0u) |
                     ((uint64_t)my_cell < P.r1 ? 1u << 31 : 0u);
             my_xy = x | (y << 16);
-            if (OUT == OUT_GRAD) my_gw = P.grad_image[my_cell];
         }
     }
 
     PathState s;
-    uint64_t next = j_begin;
+    uint64_t next = j_begin;   // next slot to set up (wave-uniform)
+    uint32_t qh = 0, qn = 0;   // queue head and length (wave-uniform)
     int state = j_begin < j_end ? LANE_NEED : LANE_DONE;
     uint64_t p = 0;
     int slot = 0;
@@ -674,89 +722,131 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
     float grad_w = 0.f;
 
     while (true) {
-        // Deferred regeneration: a lane whose path ended waits until at least
-        // kRefillMin lanes need a path (or none is active), so that path
-        // set-up, which every lane skips but the new ones, runs for several
-        // lanes at once rather than for one or two in almost every iteration.
-        const uint64_t need_all = __ballot(state == LANE_NEED);
-        const uint64_t busy = __ballot(state == LANE_ACTIVE || state == LANE_FRESH);
-        const bool want = state == LANE_NEED && (busy == 0 || __popcll(need_all) >= kRefillMin);
-        const uint64_t need = __ballot(want);
-        // the new path's bin and pixel are set and used in the same iteration
-        // (declared here, they are not carried around the loop in registers)
-        int bin = 0, px = 0, py = 0;
+        const uint64_t need = __ballot(state == LANE_NEED);
         if (need) {
-            const uint64_t j = next + (uint64_t)__popcll(need & lanes_below);
-            if (SRC == SRC_TILE) {
-                // whole wave active here: the permutes read every lane's description
-                const int sl = (int)(j & 63);
-                const uint32_t bf = (uint32_t)__shfl((int)my_bf, sl), xy = (uint32_t)__shfl((int)my_xy, sl);
-                const float c_gw = OUT == OUT_GRAD ? __shfl(my_gw, sl) : 0.f;
-                if (want) {
-                    if (j >= j_end) {
-                        state = LANE_DONE;
+            if (qh == qn && next < j_end) {
+                // bulk set-up of slots next .. next + 63, one per lane
+                const uint64_t j = next + (uint64_t)lane;
+                bool ok = false;
+                PathState t;
+                uint64_t pj = 0;
+                int64_t cj = 0, pixj = 0;
+                if (j < j_end) {
+                    int bin = 0, px = 0, py = 0;
+                    bool valid = false;
+                    if (SRC == SRC_TILE) {
+                        const uint64_t m = P.q0 + (uint64_t)((my_bf >> 30) & 1u) + (j >> 6);
+                        const uint64_t m_hi = P.q1 + (uint64_t)(my_bf >> 31);
+                        valid = ((my_bf >> 29) & 1u) && m < m_hi;   // else an empty slot of a ragged range
+                        cj = c0 + lane;
+                        pj = (uint64_t)cj + m * (uint64_t)P.ncells;
+                        bin = (int)(my_bf & ((1u << 29) - 1u));
+                        px = (int)(my_xy & 0xFFFFu);
+                        py = (int)(my_xy >> 16);
+                        pixj = (int64_t)py * P.width + px;
                     } else {
-                        const uint64_t rep = j >> 6;
-                        const uint64_t m = P.q0 + (uint64_t)((bf >> 30) & 1u) + rep;
-                        const uint64_t m_hi = P.q1 + (uint64_t)(bf >> 31);
-                        if (((bf >> 29) & 1u) && m < m_hi) {
-                            cell = c0 + sl;
-                            p = (uint64_t)cell + m * (uint64_t)P.ncells;
-                            slot = sl;
-                            bin = (int)(bf & ((1u << 29) - 1u));
-                            px = (int)(xy & 0xFFFFu);
-                            py = (int)(xy >> 16);
-                            pixel = (int64_t)py * P.width + px;
-                            if (OUT == OUT_GRAD) grad_w = c_gw;
-                            state = LANE_FRESH;
-                        }   // else: an empty slot of a ragged range; pull again next iteration
+                        valid = true;
+                        pj = j;
+                        cj = c0 + (int64_t)(j - j_begin);
+                        if (cj >= P.ncells) cj -= P.ncells;
+                        if (P.ncells <= 0xFFFFFFFFll) {
+                            const uint32_t c32 = (uint32_t)cj, np = (uint32_t)P.npix;
+                            const uint32_t b = c32 / np, pix = c32 - b * np;
+                            const uint32_t y = pix / (uint32_t)P.width;
+                            bin = (int)b;
+                            py = (int)y;
+                            px = (int)(pix - y * (uint32_t)P.width);
+                            pixj = pix;
+                        } else {
+                            const int64_t b = cj / P.npix;
+                            pixj = cj - b * P.npix;
+                            bin = (int)b;
+                            py = (int)(pixj / P.width);
+                            px = (int)(pixj - (int64_t)py * P.width);
+                        }
+                    }
+                    if (valid) {
+                        const U4 r0 = philox((uint32_t)pj, (uint32_t)(pj >> 32), 0u, 0u, P.key0, P.key1);
+                        ok = setup_path(P, r0, bin, px, py, t, st, MODE == 1);
+                        if (!ok) {
+                            st.inc(DARTS_ST_ZERO_PATHS);
+                            if (MODE == 0 && OUT == OUT_PATHS) P.path_out[pj - P.path_offset] = 0.f;
+                        }
                     }
                 }
-            } else if (want) {
-                if (j >= j_end) {
-                    state = LANE_DONE;
-                } else {
-                    p = j;
-                    cell = c0 + (int64_t)(j - j_begin);
-                    if (cell >= P.ncells) cell -= P.ncells;
-                    if (P.ncells <= 0xFFFFFFFFll) {
-                        const uint32_t c32 = (uint32_t)cell, np = (uint32_t)P.npix;
-                        const uint32_t b = c32 / np, pix = c32 - b * np;
-                        const uint32_t y = pix / (uint32_t)P.width;
-                        bin = (int)b;
-                        py = (int)y;
-                        px = (int)(pix - y * (uint32_t)P.width);
-                        pixel = pix;
-                    } else {
-                        const int64_t b = cell / P.npix;
-                        pixel = cell - b * P.npix;
-                        bin = (int)b;
-                        py = (int)(pixel / P.width);
-                        px = (int)(pixel - (int64_t)py * P.width);
-                    }
+                const uint64_t okb = __ballot(ok);
+                if (ok) {
+                    const int i = __popcll(okb & lanes_below);
+                    q[(Q_X + 0) * 64 + i] = t.x.x; q[(Q_X + 1) * 64 + i] = t.x.y; q[(Q_X + 2) * 64 + i] = t.x.z;
+                    q[(Q_W + 0) * 64 + i] = t.w.x; q[(Q_W + 1) * 64 + i] = t.w.y; q[(Q_W + 2) * 64 + i] = t.w.z;
+                    q[Q_LE * 64 + i] = t.Le;
+                    q[Q_DM * 64 + i] = t.dm;
+                    q[Q_C * 64 + i] = t.C;
+                    q[Q_GLO * 64 + i] = t.G_lo;
+                    q[Q_GHI * 64 + i] = t.G_hi;
+                    q[Q_EMS * 64 + i] = t.em_scale;
+                    q[Q_EM * 64 + i] = __int_as_float(t.em);
+                    q[Q_PLO * 64 + i] = __uint_as_float((uint32_t)pj);
+                    q[Q_PHI * 64 + i] = __uint_as_float((uint32_t)(pj >> 32));
+                    q[Q_CLO * 64 + i] = __uint_as_float((uint32_t)cj);
+                    q[Q_CHI * 64 + i] = __uint_as_float((uint32_t)((uint64_t)cj >> 32));
+                    q[Q_PIX * 64 + i] = __uint_as_float((uint32_t)pixj);
+                }
+                qh = 0;
+                qn = (uint32_t)__popcll(okb);
+                next += 64;
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (qh < qn) {
+                const uint32_t rank = (uint32_t)__popcll(need & lanes_below);
+                if (state == LANE_NEED && rank < qn - qh) {
+                    const int i = (int)(qh + rank);
+                    s.x = V3{q[(Q_X + 0) * 64 + i], q[(Q_X + 1) * 64 + i], q[(Q_X + 2) * 64 + i]};
+                    s.w = V3{q[(Q_W + 0) * 64 + i], q[(Q_W + 1) * 64 + i], q[(Q_W + 2) * 64 + i]};
+                    s.Le = q[Q_LE * 64 + i];
+                    s.dm = q[Q_DM * 64 + i];
+                    s.C = q[Q_C * 64 + i];
+                    s.G_lo = q[Q_GLO * 64 + i];
+                    s.G_hi = q[Q_GHI * 64 + i];
+                    s.em_scale = q[Q_EMS * 64 + i];
+                    s.em = __float_as_int(q[Q_EM * 64 + i]);
+                    s.beta = P.beta0;
+                    s.k = 0;
+                    s.n_surf = 0;
+                    s.on_floor = false;
+                    s.acc = 0.f;
+                    s.L_med = 0.f;
+                    s.dlog_g = 0.f;
+                    s.vbin = -1;
+                    s.vpart = 0.f;
+                    p = (uint64_t)__float_as_uint(q[Q_PLO * 64 + i]) |
+                        ((uint64_t)__float_as_uint(q[Q_PHI * 64 + i]) << 32);
+                    cell = (int64_t)((uint64_t)__float_as_uint(q[Q_CLO * 64 + i]) |
+                                     ((uint64_t)__float_as_uint(q[Q_CHI * 64 + i]) << 32));
+                    pixel = (int64_t)__float_as_uint(q[Q_PIX * 64 + i]);
+                    slot = (int)(cell - c0);
                     if (OUT == OUT_GRAD) grad_w = P.grad_image[cell];
                     state = LANE_FRESH;
                 }
+                const uint32_t took = (uint32_t)__popcll(need);
+                qh += took < qn - qh ? took : qn - qh;
+            } else if (next >= j_end && state == LANE_NEED) {
+                state = LANE_DONE;
             }
-            next += (uint64_t)__popcll(need);
         }
         if (__ballot(state != LANE_DONE) == 0) break;
         if (state == LANE_FRESH || state == LANE_ACTIVE) {
-            const bool fresh = state == LANE_FRESH;
-            const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), fresh ? 0u : (uint32_t)s.k, 0u, P.key0, P.key1);
-            bool alive = true;
-            if (fresh) {
-                alive = setup_path(P, r0, bin, px, py, s, st, MODE == 1);
-                if (!alive) s.acc = 0.f;
-            } else if (MODE == 1) {
-                direction_vanilla<FLOOR>(P, s, r0);
-            } else {
-                direction_darts<OUT, FLOOR>(P, s, r0, st);
+            // the emitter position is looked up again in every iteration
+            // rather than carried across it (scalar loads for one emitter)
+            s.xe = emitter_pos(P, s.em);
+            if (state == LANE_ACTIVE) {
+                const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 0u, P.key0, P.key1);
+                if (MODE == 1) direction_vanilla<FLOOR>(P, s, r0);
+                else direction_darts<OUT, FLOOR>(P, s, r0, st);
             }
-            if (alive) {
-                if (MODE == 1) alive = fly_vanilla<FLOOR>(P, p, pixel, s, st);
-                else alive = connect_and_fly<OUT, FLOOR>(P, p, s, st, grad_w, gacc);
-            }
+            bool alive;
+            if (MODE == 1) alive = fly_vanilla<FLOOR>(P, p, pixel, s, st);
+            else alive = connect_and_fly<OUT, FLOOR>(P, p, s, st, grad_w, gacc);
             if (alive) {
                 state = LANE_ACTIVE;
             } else {
@@ -787,8 +877,8 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
 // compensated global atomic pair per cell.
 typedef __attribute__((address_space(4))) const KParams CKParams;
 
-// The adjoint keeps three FP64 accumulators per lane: at the image kernels'
-// occupancy it would spill, so it is compiled for 4 waves per SIMD.
+// The adjoint keeps three FP64 accumulators per lane; it is compiled for 4
+// waves per SIMD like the image kernels.
 template <int OUT>
 constexpr int render_waves_per_simd()
 {
@@ -802,6 +892,7 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
     (void)P_arg;
     const KParams &P = *(const KParams *)(CKParams *)__builtin_amdgcn_kernarg_segment_ptr();
     __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
+    __shared__ float qmem[(kBlock / 64) * kQueueFloats];
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
     // the wave's index within the block is the same on all of its lanes: read
@@ -833,7 +924,7 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
     for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     double gacc[3] = {0.0, 0.0, 0.0};
     run_pool<MODE, OUT, STATS, SRC, FLOOR>(P, c0, j_begin, j_end, P.hi, P.lo, acc_hi + wbase, acc_lo + wbase,
-                                           acc_m2 + wbase, st, gacc);
+                                           acc_m2 + wbase, qmem + wave_in_block * kQueueFloats, st, gacc);
 
     if (SRC == SRC_TILE && MODE == 0 && OUT == OUT_IMAGE && have) {
         // The flush indices are formed again from the thread index here; the
@@ -904,8 +995,10 @@ template <int SRC, int BLOCK, bool FLOOR>
 __global__ __launch_bounds__(BLOCK, DARTS_BATCH_WAVES_PER_SIMD) void batch_kernel(BParams B)
 {
     __shared__ float acc_hi[BLOCK], acc_lo[BLOCK];
+    __shared__ float qmem[(BLOCK / 64) * kQueueFloats];
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
+    const uint32_t wave_in_block = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     Stats<false> st;
     while (true) {
         uint32_t u = 0;
@@ -928,7 +1021,7 @@ __global__ __launch_bounds__(BLOCK, DARTS_BATCH_WAVES_PER_SIMD) void batch_kerne
             acc_lo[threadIdx.x] = 0.f;
         }
         run_pool<0, OUT_IMAGE, false, SRC, FLOOR>(P, c0, j_begin, j_end, img_hi, img_lo, acc_hi + wbase, acc_lo + wbase,
-                                           nullptr, st, nullptr);
+                                                  nullptr, qmem + wave_in_block * kQueueFloats, st, nullptr);
         if (SRC == SRC_TILE) {
             const int64_t cell = c0 + lane;
             const float h = acc_hi[threadIdx.x], l = acc_lo[threadIdx.x];
@@ -1179,7 +1272,8 @@ int check_dims(const darts_table_dims *d)
         !std::isfinite(d->s_max))
         return fail(DARTS_ERR_INVALID_ARG, "table dims must be positive, n_cos <= %d, s_max > 0",
                     DARTS_MAX_COS_BINS);
-    if ((int64_t)d->n_cs * d->n_s > (1 << 26)) return fail(DARTS_ERR_INVALID_ARG, "table too large");
+    if ((int64_t)d->n_cs * d->n_s > (1 << 26) || (int64_t)d->n_cs * d->n_s * (d->n_cos + 1) > INT32_MAX)
+        return fail(DARTS_ERR_INVALID_ARG, "table too large");
     return DARTS_OK;
 }
 
@@ -1208,7 +1302,7 @@ bool same_medium(const darts_medium &a, const darts_medium &b)
 
 int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &tb)
 {
-    tb = Table{nullptr, 1, 1, 1, 0.f};
+    tb = Table{nullptr, 1, 1, 1, 0.f, 1.f, 1.f, 2.f};
     if (!needed) return DARTS_OK;
     if (!t || !t->cdf_dev) return fail(DARTS_ERR_INVALID_ARG, "EDA direction sampling needs a built table");
     if (int rc = check_dims(&t->dims)) return rc;
@@ -1219,6 +1313,9 @@ int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &
     tb.n_s = t->dims.n_s;
     tb.n_cos = t->dims.n_cos;
     tb.ns_over_smax = (float)t->dims.n_s / t->dims.s_max;
+    tb.fn_cs = (float)tb.n_cs;
+    tb.fn_cos = (float)tb.n_cos;
+    tb.cos_step = 2.f / (float)tb.n_cos;
     return DARTS_OK;
 }
 
@@ -1287,6 +1384,7 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     for (int a = 0; a < 3; ++a) {
         P.origin[a] = sn.origin[a];
         P.dir[a] = sn.kind == 1 ? (float)(sn.dir[a] / dl) : 0.f;
+        P.inv_dir[a] = P.dir[a] != 0.f ? 1.f / P.dir[a] : 0.f;
         P.du[a] = sn.du[a];
         P.dv[a] = sn.dv[a];
     }

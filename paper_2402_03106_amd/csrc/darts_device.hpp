@@ -200,11 +200,14 @@ __device__ __forceinline__ float texp_sample(float u, float ln2_over_sigma, floa
 struct Box { float lo[3], hi[3]; };
 
 // Distance from x (inside) along w to the boundary, iw = componentwise 1/w.
+// Per axis the face ahead is chosen by the sign bit of w, so a zero
+// component (iw = +inf for +0, -inf for -0) gives +inf, or NaN for a point
+// on that face, which the minimum ignores.
 __device__ __forceinline__ float box_exit_inv(const Box &b, V3 x, V3 w, V3 iw)
 {
-    const float tx = w.x > 0.f ? (b.hi[0] - x.x) * iw.x : (w.x < 0.f ? (b.lo[0] - x.x) * iw.x : kInf);
-    const float ty = w.y > 0.f ? (b.hi[1] - x.y) * iw.y : (w.y < 0.f ? (b.lo[1] - x.y) * iw.y : kInf);
-    const float tz = w.z > 0.f ? (b.hi[2] - x.z) * iw.z : (w.z < 0.f ? (b.lo[2] - x.z) * iw.z : kInf);
+    const float tx = ((__float_as_int(w.x) < 0 ? b.lo[0] : b.hi[0]) - x.x) * iw.x;
+    const float ty = ((__float_as_int(w.y) < 0 ? b.lo[1] : b.hi[1]) - x.y) * iw.y;
+    const float tz = ((__float_as_int(w.z) < 0 ? b.lo[2] : b.hi[2]) - x.z) * iw.z;
     return fmaxf(fminf(fminf(tx, ty), tz), 0.f);
 }
 __device__ __forceinline__ float box_exit(const Box &b, V3 x, V3 w)
@@ -388,7 +391,14 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
 // otherwise from the phase function about the previous direction.  The
 // throughput is multiplied by phase / (gamma p_EDA + (1 - gamma) p_HG).
 // ---------------------------------------------------------------------------
-struct Table { const float *cdf; int n_cs, n_s, n_cos; float ns_over_smax; };
+// A built direction table as the kernels read it: the float constants are
+// formed once on the host (fn_cs = n_cs, fn_cos = n_cos, cos_step =
+// 2 / n_cos, ns_over_smax = n_s / s_max); offsets fit 32 bits.
+struct Table {
+    const float *cdf;
+    int n_cs, n_s, n_cos;
+    float ns_over_smax, fn_cs, fn_cos, cos_step;
+};
 
 // dbg (diagnostics only; null in the kernels): [0] table row i n_s + j
 // (-1 without the table), [1] the cos-bin whose EDA density enters the
@@ -403,9 +413,9 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
     if (use_eda && C > 0.f) {
         const float kappa = C * rcp(S);
         gam = kappa * rcp(kappa + alpha);
-        const int i = min(max((int)(kappa * (float)tb.n_cs), 0), tb.n_cs - 1);
+        const int i = min(max((int)(kappa * tb.fn_cs), 0), tb.n_cs - 1);
         const int j = min(max((int)(S * tb.ns_over_smax), 0), tb.n_s - 1);
-        row = tb.cdf + ((size_t)i * tb.n_s + j) * (size_t)(tb.n_cos + 1);
+        row = tb.cdf + (uint32_t)(i * tb.n_s + j) * (uint32_t)(tb.n_cos + 1);
         if (dbg) dbg[0] = i * tb.n_s + j;
     }
     eda_branch = u0 < gam;
@@ -422,7 +432,7 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
             if (v <= u1) { lo = mid; c_lo = v; } else { hi = mid; c_hi = v; }
         }
         k = lo;
-        mu = fmaf((float)k + u3, 2.f / (float)tb.n_cos, -1.f);
+        mu = fmaf((float)k + u3, tb.cos_step, -1.f);
         s = hw_sqrt(fmaxf((1.f - mu) * (1.f + mu), 0.f));
         axis = a;
     } else {
@@ -434,12 +444,12 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
     float p_mix = p_hg;
     if (gam > 0.f) {
         if (!eda_branch) {
-            k = (int)floorf((dot(w, a) + 1.f) * 0.5f * (float)tb.n_cos);
+            k = (int)floorf((dot(w, a) + 1.f) * 0.5f * tb.fn_cos);
             k = min(max(k, 0), tb.n_cos - 1);
             c_lo = row[k];
             c_hi = row[k + 1];
         }
-        const float p_eda = (c_hi - c_lo) * (float)tb.n_cos * kInv4Pi;
+        const float p_eda = (c_hi - c_lo) * tb.fn_cos * kInv4Pi;
         p_mix = fmaf(gam, p_eda - p_hg, p_hg);
         if (dbg) dbg[1] = k;
     }
