@@ -152,8 +152,8 @@ enum {
 };
 
 /* Size in bytes of the cdf array of a table of these dimensions.
- * Returns INVALID_ARG for non-positive dims, n_cos > DARTS_MAX_COS_BINS or
- * s_max <= 0. */
+ * Returns INVALID_ARG for non-positive dims, n_cos > DARTS_MAX_COS_BINS,
+ * s_max <= 0, n_cs * n_s > 2^26 or more than 2^31 - 1 floats in all. */
 int darts_table_bytes(const darts_table_dims *dims, size_t *bytes);
 
 /* Build the elliptical-DA direction table of Section V-A (Eq. (16)-(18)).
@@ -364,9 +364,16 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
  *    compensated global atomic pair), otherwise the tile decomposition
  *    (per-cell sums in LDS).  Default 16; negative: never id ranges.
  *  - darts_set_target_waves: the number of waves a tile-decomposed launch
- *    aims for (default 65536).  Returns DARTS_ERR_INVALID_ARG below 1. */
+ *    aims for (default 65536).  Returns DARTS_ERR_INVALID_ARG below 1.
+ *  - darts_set_vanilla_privatised: with `on` (the default), a vanilla render
+ *    with at least 256 paths per pixel and at most 384 histogram bins (the
+ *    scene's bins, or 1 with a sensor response) gives each wave the paths of
+ *    one pixel and histograms their contributions in LDS, flushed with one
+ *    compensated global atomic pair per bin and wave; otherwise every
+ *    contribution is a compensated global atomic pair. */
 int darts_set_ids_max_reps(int64_t reps);
 int darts_set_target_waves(int64_t waves);
+int darts_set_vanilla_privatised(int on);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *darts_last_error(void);

@@ -89,6 +89,12 @@ struct KParams {
     // id-range decomposition (few paths per cell): wave w takes path ids
     // path_offset + [w unit_paths, (w + 1) unit_paths)
     uint64_t unit_paths;
+    // vanilla pixel decomposition (vtile != 0): wave w owns pixel w mod npix
+    // and the chunk w div npix (of vt_chunk ids i) of that pixel's paths
+    // p = pixel + i npix, histogramming their contributions over hist_bins
+    // bins in LDS
+    int vtile, hist_bins;
+    uint64_t vt_chunk;
 };
 
 constexpr int kBlock = 256;
@@ -563,17 +569,33 @@ __device__ __forceinline__ void direction_vanilla(const KParams &P, PathState &s
     s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
 }
 
-// Adds the square of the path's running sum for its current bin to m2.
-__device__ __forceinline__ void vanilla_flush_m2(const KParams &P, const PathState &s, int64_t pixel)
+__device__ __forceinline__ void compensated_lds_add(float *hi, float *lo, int i, float v)
+{
+    const float old = atomicAdd(&hi[i], v);
+    const float e = two_sum_err(old, v, old + v);
+    if (e != 0.f) atomicAdd(&lo[i], e);
+}
+
+// Adds the square of the path's running sum for its current bin to m2 (the
+// global image, or with PRIV the wave's LDS histogram hist[2 hist_bins + b]).
+template <bool PRIV>
+__device__ __forceinline__ void vanilla_flush_m2(const KParams &P, const PathState &s, int64_t pixel, float *hist)
 {
     if (s.vbin >= 0) {
-        const int64_t cell = P.resp_w ? pixel : (int64_t)s.vbin * P.npix + pixel;
-        unsafeAtomicAdd(P.m2 + cell, s.vpart * s.vpart);
+        if (PRIV) {
+            atomicAdd(&hist[2 * P.hist_bins + s.vbin], s.vpart * s.vpart);
+        } else {
+            const int64_t cell = P.resp_w ? pixel : (int64_t)s.vbin * P.npix + pixel;
+            unsafeAtomicAdd(P.m2 + cell, s.vpart * s.vpart);
+        }
     }
 }
 
-template <bool FLOOR, class ST>
-__device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathState &s, ST &st)
+// PRIV: every path of the wave belongs to one pixel, and its contributions go
+// to the wave's compensated LDS histogram hist[0 .. hist_bins) (hi),
+// hist[hist_bins .. 2 hist_bins) (lo) instead of global atomics.
+template <bool FLOOR, bool PRIV, class ST>
+__device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathState &s, ST &st, float *hist)
 {
     const Medium &m = P.med;
     const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
@@ -613,16 +635,20 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
         const float wsens = !in_range ? 0.f : (P.resp_w ? P.resp_w[bin] : 1.f);
         if (wsens > 0.f) {
             const float v = wsens * s.beta * s.em_scale * f_loc * fast_exp(-m.sigma_t * r_in) * ir * ir;
-            const int64_t cell = P.resp_w ? pixel : (int64_t)bin * P.npix + pixel;
-            add_compensated(P.hi, P.lo, cell, v, 0.f);
+            const int vb = P.resp_w ? 0 : bin;
+            if (PRIV) {
+                compensated_lds_add(hist, hist + P.hist_bins, vb, v);
+            } else {
+                const int64_t cell = P.resp_w ? pixel : (int64_t)bin * P.npix + pixel;
+                add_compensated(P.hi, P.lo, cell, v, 0.f);
+            }
             if (P.m2) {
                 // squares of per-path-per-bin sums: a path's length never
                 // decreases (a flight of d adds d to Le and shortens the
                 // distance to the emitter by at most d), so its contributions
                 // to one bin are consecutive and one running sum suffices
-                const int vb = P.resp_w ? 0 : bin;
                 if (vb != s.vbin) {
-                    vanilla_flush_m2(P, s, pixel);
+                    vanilla_flush_m2<PRIV>(P, s, pixel, hist);
                     s.vbin = vb;
                     s.vpart = v;
                 } else {
@@ -666,9 +692,12 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
 //    once at n_cells; the caller keeps ranges no longer than n_cells).  Each
 //    finished path adds its sum to the global image with one compensated
 //    atomic pair: suited to scenes with few paths per cell.
+//  - SRC_VTILE (vanilla): the wave owns pixel c0; slot j is path id
+//    c0 + j npix, and every contribution goes to the wave's compensated LDS
+//    histogram over the bins (hist), flushed by the caller once per wave.
 // ---------------------------------------------------------------------------
 enum { LANE_NEED = 0, LANE_FRESH = 1, LANE_ACTIVE = 2, LANE_DONE = 3 };
-enum { SRC_TILE = 0, SRC_IDS = 1 };
+enum { SRC_TILE = 0, SRC_IDS = 1, SRC_VTILE = 2 };
 
 // Set-up path queue of one wave in LDS, structure of arrays: field f of
 // entry i at q[f * 64 + i].
@@ -678,17 +707,11 @@ enum {
 };
 constexpr int kQueueFloats = Q_FIELDS * 64;
 
-__device__ __forceinline__ void compensated_lds_add(float *hi, float *lo, int i, float v)
-{
-    const float old = atomicAdd(&hi[i], v);
-    const float e = two_sum_err(old, v, old + v);
-    if (e != 0.f) atomicAdd(&lo[i], e);
-}
 
 template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, int SRC, bool FLOOR>
 __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end,
                                          float *img_hi, float *img_lo, float *acc_hi, float *acc_lo,
-                                         float *acc_m2, float *q, Stats<STATS> &st, double *gacc)
+                                         float *acc_m2, float *q, float *hist, Stats<STATS> &st, double *gacc)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t lanes_below = (1ull << lane) - 1ull;
@@ -744,6 +767,13 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
                         px = (int)(my_xy & 0xFFFFu);
                         py = (int)(my_xy >> 16);
                         pixj = (int64_t)py * P.width + px;
+                    } else if (SRC == SRC_VTILE) {
+                        valid = true;
+                        pj = (uint64_t)c0 + j * (uint64_t)P.npix;
+                        cj = c0;
+                        pixj = c0;
+                        py = (int)(c0 / P.width);
+                        px = (int)(c0 - (int64_t)py * P.width);
                     } else {
                         valid = true;
                         pj = j;
@@ -845,14 +875,14 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
                 else direction_darts<OUT, FLOOR>(P, s, r0, st);
             }
             bool alive;
-            if (MODE == 1) alive = fly_vanilla<FLOOR>(P, p, pixel, s, st);
+            if (MODE == 1) alive = fly_vanilla<FLOOR, SRC == SRC_VTILE>(P, p, pixel, s, st, hist);
             else alive = connect_and_fly<OUT, FLOOR>(P, p, s, st, grad_w, gacc);
             if (alive) {
                 state = LANE_ACTIVE;
             } else {
                 state = LANE_NEED;
                 if (s.acc == 0.f) st.inc(DARTS_ST_ZERO_PATHS);
-                if (MODE == 1 && P.m2) vanilla_flush_m2(P, s, pixel);
+                if (MODE == 1 && P.m2) vanilla_flush_m2<SRC == SRC_VTILE>(P, s, pixel, hist);
                 if (MODE == 0) {
                     if (OUT == OUT_PATHS) {
                         P.path_out[p - P.path_offset] = s.acc;
@@ -909,6 +939,16 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
         c0 = (int64_t)(P.n_tiles - 1 - tile) * 64;
         j_begin = chunk * P.chunk_reps * 64;
         j_end = have ? min((chunk + 1) * P.chunk_reps, P.max_reps) * 64 : j_begin;
+    } else if (SRC == SRC_VTILE) {
+        // pixel q's paths in the launch are p = q + i npix for i in [i_lo, i_hi)
+        const uint64_t npix = (uint64_t)P.npix;
+        const uint64_t qp = have ? wave % npix : 0, chunk = have ? wave / npix : 0;
+        const uint64_t off = P.path_offset, end = P.path_offset + P.n_paths;
+        const uint64_t i_lo = off > qp ? (off - qp + npix - 1) / npix : 0;
+        const uint64_t i_hi = end > qp ? (end - qp + npix - 1) / npix : 0;
+        j_begin = min(i_lo + chunk * P.vt_chunk, i_hi);
+        j_end = have ? min(j_begin + P.vt_chunk, i_hi) : j_begin;
+        c0 = (int64_t)qp;
     } else {
         const uint64_t end = P.path_offset + P.n_paths;
         j_begin = P.path_offset + (have ? wave : 0) * P.unit_paths;
@@ -918,13 +958,31 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
     acc_hi[threadIdx.x] = 0.f;
     acc_lo[threadIdx.x] = 0.f;
     acc_m2[threadIdx.x] = 0.f;
+    // vanilla pixel decomposition: the wave's histogram (hi, lo[, m2] over
+    // hist_bins bins) in dynamic LDS
+    extern __shared__ float vhist[];
+    const int n_hist = SRC == SRC_VTILE ? (P.m2 ? 3 : 2) * P.hist_bins : 0;
+    float *hist = vhist + wave_in_block * n_hist;
+    if (SRC == SRC_VTILE)
+        for (int b = lane; b < n_hist; b += 64) hist[b] = 0.f;
 
     Stats<STATS> st;
 #pragma unroll
     for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     double gacc[3] = {0.0, 0.0, 0.0};
     run_pool<MODE, OUT, STATS, SRC, FLOOR>(P, c0, j_begin, j_end, P.hi, P.lo, acc_hi + wbase, acc_lo + wbase,
-                                           acc_m2 + wbase, qmem + wave_in_block * kQueueFloats, st, gacc);
+                                           acc_m2 + wbase, qmem + wave_in_block * kQueueFloats, hist, st, gacc);
+
+    if (SRC == SRC_VTILE && have) {
+        // one compensated global atomic pair per bin the wave's paths reached
+        const int nb = P.hist_bins;
+        for (int b = lane; b < nb; b += 64) {
+            const float h = hist[b], l = hist[nb + b];
+            const int64_t cell = P.resp_w ? c0 : (int64_t)b * P.npix + c0;
+            if (h != 0.f || l != 0.f) add_compensated(P.hi, P.lo, cell, h, l);
+            if (P.m2 && hist[2 * nb + b] != 0.f) unsafeAtomicAdd(P.m2 + cell, hist[2 * nb + b]);
+        }
+    }
 
     if (SRC == SRC_TILE && MODE == 0 && OUT == OUT_IMAGE && have) {
         // The flush indices are formed again from the thread index here; the
@@ -1021,7 +1079,7 @@ __global__ __launch_bounds__(BLOCK, DARTS_BATCH_WAVES_PER_SIMD) void batch_kerne
             acc_lo[threadIdx.x] = 0.f;
         }
         run_pool<0, OUT_IMAGE, false, SRC, FLOOR>(P, c0, j_begin, j_end, img_hi, img_lo, acc_hi + wbase, acc_lo + wbase,
-                                                  nullptr, qmem + wave_in_block * kQueueFloats, st, nullptr);
+                                                  nullptr, qmem + wave_in_block * kQueueFloats, nullptr, st, nullptr);
         if (SRC == SRC_TILE) {
             const int64_t cell = c0 + lane;
             const float h = acc_hi[threadIdx.x], l = acc_lo[threadIdx.x];
@@ -1323,6 +1381,10 @@ std::atomic<int64_t> g_ids_max_reps{16};         // id ranges when no cell has m
 constexpr uint64_t kIdsUnit = 2048;   // most paths per wave in the id-range decomposition
 constexpr uint64_t kIdsWaves = 16384; // waves the id-range decomposition aims for
 std::atomic<int64_t> g_target_waves{1 << 16};   // measured: 4 chunks per tile balance the 2^28-path box frame best
+std::atomic<int> g_vanilla_privatised{1};      // vanilla renders histogram per pixel in LDS when it fits
+// most bins of a vanilla pixel histogram in LDS: hi, lo and m2 of 4 waves
+// (18 KiB) beside the 21 KiB of static LDS keep 4 blocks on a CU
+constexpr int kVTileMaxBins = 384;
 
 int make_params(const darts_scene *sc, const darts_params *pr, const darts_table *table, KParams &P,
                 bool per_path_only)
@@ -1445,6 +1507,25 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
         P.unit_paths = std::min<uint64_t>(nc, std::max<uint64_t>(64, std::min<uint64_t>(kIdsUnit, want)));
         P.n_waves = (pr->n_paths + P.unit_paths - 1) / P.unit_paths;
     }
+    // vanilla with many paths per pixel: waves own pixels and histogram their
+    // paths' contributions in LDS (flushed once per wave) instead of one
+    // compensated global atomic pair per contribution
+    P.vtile = 0;
+    P.hist_bins = 0;
+    P.vt_chunk = 0;
+    if (vanilla && g_vanilla_privatised.load(std::memory_order_relaxed)) {
+        const int nb = sc->response_dev ? 1 : sc->bins.n_bins;
+        const uint64_t ppp = pr->n_paths / (uint64_t)P.npix;   // paths per pixel (at least)
+        if (nb <= kVTileMaxBins && ppp >= 256) {
+            const int64_t target_waves = g_target_waves.load(std::memory_order_relaxed);
+            uint64_t chunks = (uint64_t)std::max<int64_t>(1, target_waves / P.npix);
+            chunks = std::max<uint64_t>(1, std::min<uint64_t>(chunks, ppp / 256));
+            P.vtile = 1;
+            P.hist_bins = nb;
+            P.vt_chunk = (ppp + 1 + chunks - 1) / chunks;
+            P.n_waves = (uint64_t)P.npix * ((ppp + 1 + P.vt_chunk - 1) / P.vt_chunk);
+        }
+    }
     if (P.n_waves / (kBlock / 64) > 0x7FFFFFFFull) return fail(DARTS_ERR_INVALID_ARG, "launch too large");
     P.hi = P.lo = P.m2 = nullptr;
     P.stats = nullptr;
@@ -1461,6 +1542,21 @@ int launch_render(const KParams &P, bool stats, hipStream_t stream)
     if (blocks == 0 || P.n_paths == 0) return ok();
     const dim3 grid((uint32_t)blocks), block(kBlock);
     // scenes without a floor run kernels compiled without its branches
+    if constexpr (MODE == 1) {
+        if (P.vtile) {
+            const size_t lds = (size_t)(kBlock / 64) * (P.m2 ? 3 : 2) * (size_t)P.hist_bins * sizeof(float);
+            if (P.floor) {
+                if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, true, SRC_VTILE>), grid, block, lds, stream, P);
+                else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, true, SRC_VTILE>), grid, block, lds, stream, P);
+            } else {
+                if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, false, SRC_VTILE>), grid, block, lds, stream, P);
+                else hipLaunchKernelGGL((render_kernel<MODE, OUT, false, false, SRC_VTILE>), grid, block, lds, stream, P);
+            }
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return fail(DARTS_ERR_DEVICE, "render launch failed: %s", hipGetErrorString(e));
+            return ok();
+        }
+    }
     if (P.unit_paths) {
         if (P.floor) {
             if (stats) hipLaunchKernelGGL((render_kernel<MODE, OUT, true, true, SRC_IDS>), grid, block, 0, stream, P);
@@ -2157,6 +2253,13 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
 int darts_set_ids_max_reps(int64_t reps)
 {
     g_ids_max_reps.store(reps, std::memory_order_relaxed);
+    return ok();
+}
+
+// Tuning knob: vanilla renders histogram per pixel in LDS when it fits.
+int darts_set_vanilla_privatised(int on)
+{
+    g_vanilla_privatised.store(on ? 1 : 0, std::memory_order_relaxed);
     return ok();
 }
 

@@ -116,6 +116,7 @@ def lib() -> C.CDLL:
         L.darts_debug_pointwise.argtypes = [C.c_int, vp, vp, i64, C.POINTER(_Medium), C.POINTER(_Table), vp]
         L.darts_set_target_waves.argtypes = [i64]
         L.darts_set_ids_max_reps.argtypes = [i64]
+        L.darts_set_vanilla_privatised.argtypes = [C.c_int]
         L.darts_response_bytes.argtypes = [C.c_int, C.POINTER(C.c_size_t)]
         L.darts_build_response.argtypes = [C.POINTER(C.c_float), C.c_int, vp, vp]
         pp = C.POINTER(C.c_void_p)
@@ -470,6 +471,12 @@ def set_ids_max_reps(n: int):
     """Tuning knob: renders whose cells hold at most n repetitions take
     consecutive path ids per wave instead of tiles of cells (-1: never)."""
     _check(lib().darts_set_ids_max_reps(int(n)))
+
+
+def set_vanilla_privatised(on: bool):
+    """Tuning knob: vanilla renders histogram per pixel in LDS when it fits
+    (default True); False: a global atomic pair per contribution."""
+    _check(lib().darts_set_vanilla_privatised(1 if on else 0))
 
 
 def set_target_waves(n: int):

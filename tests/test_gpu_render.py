@@ -328,6 +328,32 @@ def test_second_moments_match_oracle(D, oracle, wname, mode):
     assert tot <= 2e-4 and rel <= 5e-4, (tot, rel)
 
 
+@pytest.mark.parametrize("wname,offset,n", [("box_hg_small", 0, 1 << 16), ("box_hg_small", 37, 100003),
+                                           ("infinite_point", 5, 1 << 16), ("box_hg", 4097, 1 << 22)])
+def test_vanilla_pixel_histograms_agree(D, oracle, wname, offset, n):
+    """Vanilla with each wave owning one pixel and histogramming its paths in
+    LDS equals vanilla with a global atomic pair per contribution, on the
+    same path ids (ragged offsets and counts that are not multiples of the
+    pixel count included): images up to the order of the compensated
+    additions, second moments (plain FP32 sums of up to 65536 squares per
+    cell) to 2e-4 of the largest, and the same statistics."""
+    w = WORKLOADS[wname]()
+    sc, pr = w["scene"], dict(w["params"], path_offset=offset, n_paths=n)
+    out = {}
+    for priv in (True, False):
+        D.set_vanilla_privatised(priv)
+        try:
+            hi, lo, m2, st = D.render_transient(sc, pr, "vanilla", None, want_m2=True, want_stats=True)
+            torch.cuda.synchronize()
+        finally:
+            D.set_vanilla_privatised(True)
+        out[priv] = ((hi.double() + lo.double()).cpu().numpy(), m2.double().cpu().numpy(), D.stats_dict(st))
+    (a, ma, sa), (b, mb, sb) = out[True], out[False]
+    assert sa == sb
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
+    assert np.abs(ma - mb).max() <= 2e-4 * np.abs(mb).max()
+
+
 @pytest.mark.parametrize("wname,mode", [("box_hg", "darts"), ("box_hg", "uniform"), ("infinite_point", "darts"),
                                         ("box_hg_small", "eda_only")])
 def test_image_is_sum_of_path_values(D, oracle, wname, mode):

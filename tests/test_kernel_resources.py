@@ -44,8 +44,9 @@ def test_timed_kernel_has_no_scratch_and_fits_four_waves(kernels):
 
 def test_image_kernels_without_statistics_have_no_scratch(kernels):
     """Every image-output render kernel without statistics counters (DARTS
-    family and vanilla, with and without the floor, both decompositions)."""
+    family and vanilla, with and without the floor, the tile and id-range
+    decompositions, and vanilla's pixel decomposition)."""
     names = [n for n in kernels if re.search(r"render_kernelILi[01]ELi0ELb0E", n)]
-    assert len(names) == 8, names
+    assert len(names) == 10, names
     for n in names:
         assert kernels[n]["private_segment_fixed_size"] == 0, (n, kernels[n])
