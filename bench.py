@@ -39,42 +39,64 @@ FIT_SETTINGS = {"steps": 200, "mode": "da_only", "lr": 0.05, "lr_final": 0.01, "
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic floating-point operations per part of a vertex step, counted
-# from the algorithm: +, -, *, /, min/max and compares 1, fma 2, each exp, log,
-# sqrt, rsqrt, sin/cos 1 (integer RNG work is not counted).
+# Algorithmic work of the roofline: the per-unit figures of the hot path's
+# scope table, about 375 floating-point operations per vertex step (a
+# vertex that passed the early-exit test: connection test and connection,
+# medium-event draw, 8 RIS candidates with the FP64 normalisation, move,
+# direction sample) and about 60 per path (camera ray, medium entry, target
+# interval).
+FLOPS_PER_VERTEX_STEP = 375
+FLOPS_PER_PATH = 60
+
+# Cross-check: floating-point operations per part of a vertex step, counted
+# op by op from the algorithm as the kernel evaluates it.  Counted: FP32 and
+# FP64 add, subtract, multiply (1 each), fused multiply-add (2), and each
+# exp, log, sqrt, rsqrt, reciprocal, sin, cos (1).  Not counted: compares,
+# min/max, selects, conversions, integer and RNG work.
 FLOPS = {
-    "connect_test": 31,     # focal geometry, residual range, boundary clip (every step)
-    "connect_texp": 88,     # truncated-exponential S, t(S), p(t), phase, transmittance
-    "connect_uniform": 76,  # the same with S uniform
-    "flight_test": 4,       # medium-event probability and Bernoulli draw
-    "ris": 293,             # 8 candidates: distance, residual, validity, log DA fluence;
-                            # FP64 normalisation and selection; weight
-    "exp_distance": 9,      # plain exponential distance
-    "move": 20,             # advance, distance to emitter, early-exit test
-    "direction": 79,        # frame, phase pdf, MIS weight, boundary distance
-    "direction_eda": 15,    # gamma, table cell, EDA pdf, mixture pdf (EDA enabled)
-    "eda_branch": 15,       # inverse transform over the cos bins
-    "hg_branch": 30,        # HG inverse CDF
-    "hg_bin": 9,            # cos bin of a phase-sampled direction (EDA enabled)
+    "setup": 47,            # pixel jitter, camera ray, emitter and target interval, slab entry, C, early exit
+    "connect_test": 21,     # residual range, exit length d_m + |x + w d_m - x_e| (every step)
+    "connect_texp": 102,    # focal term, truncated-exponential S, t(S), p(t), control vertex, exit toward
+                            # the emitter, phase function, transmittance
+    "connect_uniform": 86,  # the same with S uniform
+    "flight_test": 4,       # medium-event probability
+    "ris": 249,             # 8 candidates (distance without cancellation, residual, validity, log DA
+                            # fluence), FP64 weights and pick, weight factor, b = w.(x_e - x)
+    "exp_distance": 8,      # plain exponential distance
+    "move": 18,             # advance, throughput, distance to the emitter, early-exit test
+    "direction": 69,        # uniforms, axis to the emitter, frame, phase pdf, MIS weight, boundary distance
+    "direction_eda": 13,    # gamma, table cell, EDA pdf, mixture pdf (EDA enabled)
+    "eda_branch": 7,        # cos inside the drawn bin and its sine (the bin search is compares only)
+    "hg_branch": 20,        # HG inverse CDF without cancellation
+    "hg_bin": 8,            # cos-bin of a phase-sampled direction (EDA enabled)
 }
 
 
-def algorithmic_flops(s: dict, mode: str) -> float:
-    """FLOPs of one launch from its statistics counters."""
+def algorithmic_flops(s: dict, paths: int) -> tuple:
+    """FLOPs of one DARTS launch from its statistics counters: the per-unit
+    figures times vertex steps and paths."""
     steps = s["vertices"] - s["early_exit"]             # vertices that passed the early-exit test
+    return float(FLOPS_PER_VERTEX_STEP * steps + FLOPS_PER_PATH * paths), steps
+
+
+def counted_flops(s: dict, mode: str) -> float:
+    """FLOPs of one launch from its statistics counters and the op-by-op part
+    counts (the cross-check of the per-unit figures)."""
+    steps = s["vertices"] - s["early_exit"]
     flights = steps - s["truncated"]
     draws = flights - s["medium_exit"]
     moves = draws - s["ris_all_invalid"]
     dirs = moves - (s["early_exit"] - s["setup_exit"])
     eda = s["eda_branch"]
-    f = steps * FLOPS["connect_test"] + flights * FLOPS["flight_test"] + moves * FLOPS["move"]
+    f = s["paths"] * FLOPS["setup"]
+    f += steps * FLOPS["connect_test"] + flights * FLOPS["flight_test"] + moves * FLOPS["move"]
     f += dirs * FLOPS["direction"]
     if mode == "darts":
         f += s["connections"] * FLOPS["connect_texp"] + draws * FLOPS["ris"]
         f += dirs * FLOPS["direction_eda"] + eda * FLOPS["eda_branch"] + (dirs - eda) * (FLOPS["hg_branch"] + FLOPS["hg_bin"])
     else:
         f += s["connections"] * FLOPS["connect_uniform"] + draws * FLOPS["exp_distance"] + dirs * FLOPS["hg_branch"]
-    return float(f), steps
+    return float(f)
 
 
 def parse():
@@ -183,11 +205,11 @@ def main():
         _, _, _, st = darts.render_transient(sc, pr, mode, table, h2, l2, want_stats=True)
         torch.cuda.synchronize()
         s = darts.stats_dict(st)
-        flops, steps = algorithmic_flops(s, mode)
-        return s, steps, flops
+        flops, steps = algorithmic_flops(s, n)
+        return s, steps, flops, counted_flops(s, mode)
 
     wall, kern_ms = timed("darts", a.steps, a.warmup)
-    stats, n_steps, flops = count_steps("darts")
+    stats, n_steps, flops, flops_counted = count_steps("darts")
     mean_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
     achieved = flops / mean_kern_s / 1e12
     value = a.steps * n / wall
@@ -217,7 +239,10 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
-            "flops_per_launch": flops, "flops_per_vertex_step": flops / n_steps,
+            "flops_per_launch": flops, "vertex_steps": n_steps, "paths": n,
+            "per_unit": {"vertex_step": FLOPS_PER_VERTEX_STEP, "path": FLOPS_PER_PATH},
+            "op_counted_flops_per_launch": flops_counted,
+            "op_counted_achieved": flops_counted / mean_kern_s / 1e12,
         },
         "stats": stats,
     }
@@ -226,10 +251,10 @@ def main():
 
     if not a.no_uniform:
         wall_u, kern_u = timed("uniform", max(2, a.steps // 2), 1)
-        st_u, n_steps_u, flops_u = count_steps("uniform")
+        st_u, n_steps_u, _, flops_u = count_steps("uniform")
         ku = sum(kern_u) / len(kern_u) / 1e3
         out["uniform"] = {"paths_per_s": max(2, a.steps // 2) * n / wall_u, "render_kernel_ms": ku * 1e3,
-                          "mean_steps_per_path": n_steps_u / n, "algorithmic_tflops": flops_u / ku / 1e12}
+                          "mean_steps_per_path": n_steps_u / n, "op_counted_tflops": flops_u / ku / 1e12}
         print(f"[bench] uniform {out['uniform']['paths_per_s']:.4g} paths/s", file=sys.stderr, flush=True)
 
     if not a.no_mse:

@@ -47,18 +47,25 @@ def test_traffic_follows_the_kernel_source(bench, tmp_path, monkeypatch):
 
 
 def test_flop_accounting(bench):
-    # a launch in which every vertex step moves on, no path is truncated and
-    # the direction counts follow from the step counts
-    s = {"vertices": 1000, "early_exit": 100, "setup_exit": 40, "truncated": 0, "medium_exit": 150,
-         "ris_all_invalid": 10, "connections": 60, "eda_branch": 200}
-    f_d, steps = bench.algorithmic_flops(s, "darts")
-    f_u, steps_u = bench.algorithmic_flops(s, "uniform")
-    assert steps == steps_u == 900
+    """The roofline's FLOPs are the per-unit figures (375 per vertex step, 60
+    per path) times the launch's counted units; the op-by-op part counts are
+    pinned here and, on a launch with the box workload's mix of events,
+    land within 10% of the per-unit figures."""
+    s = {"paths": 100, "vertices": 1000, "early_exit": 100, "setup_exit": 40, "truncated": 0,
+         "medium_exit": 100, "ris_all_invalid": 10, "connections": 270, "eda_branch": 120}
+    f, steps = bench.algorithmic_flops(s, 100)
+    assert steps == 900
+    assert f == 375 * 900 + 60 * 100
     F = bench.FLOPS
-    moves = 900 - 150 - 10
+    assert F == {"setup": 47, "connect_test": 21, "connect_texp": 102, "connect_uniform": 86, "flight_test": 4,
+                 "ris": 249, "exp_distance": 8, "move": 18, "direction": 69, "direction_eda": 13,
+                 "eda_branch": 7, "hg_branch": 20, "hg_bin": 8}
+    fc = bench.counted_flops(s, "darts")
+    fu = bench.counted_flops(s, "uniform")
+    moves = 900 - 100 - 10
     dirs = moves - (100 - 40)
     # what DARTS adds over uniform sampling on the same counts
-    extra = (60 * (F["connect_texp"] - F["connect_uniform"]) + 750 * (F["ris"] - F["exp_distance"]) +
-             dirs * F["direction_eda"] + 200 * F["eda_branch"] + (dirs - 200) * F["hg_bin"] - 200 * F["hg_branch"])
-    assert f_d - f_u == extra
-    assert 300 < f_d / steps < 600
+    extra = (270 * (F["connect_texp"] - F["connect_uniform"]) + 800 * (F["ris"] - F["exp_distance"]) +
+             dirs * F["direction_eda"] + 120 * F["eda_branch"] + (dirs - 120) * F["hg_bin"] - 120 * F["hg_branch"])
+    assert fc - fu == extra
+    assert abs(fc / f - 1) < 0.1, fc / f
