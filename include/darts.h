@@ -180,6 +180,12 @@ int darts_response_bytes(int n_bins, size_t *bytes);
 int darts_build_response(const float *w_host, int n_bins, float *response_dev, void *stream);
 
 /* Render: accumulate raw path contributions into the time-resolved image.
+ * Each path is the paper's estimator of the transient path integral
+ * (Eq. (1); per pixel and bin, the box sensor response of Eq. (4), or a
+ * general W): free flights by DA-RIS (Section IV, Eq. (9)-(15)), directions
+ * by EDA/phase one-sample MIS (Section V-A, Eq. (16)-(19)) and an elliptical
+ * control-vertex connection per vertex (Section V-B, Eq. (20)-(22)), or the
+ * strategies the flags select.
  *   Path id p = path_offset + i (i < n_paths) belongs to cell
  *   c = p mod (n_bins * height * width); its pixel is c mod (height*width) and,
  *   except in vanilla mode, its target interval is bin c / (height*width).
@@ -203,12 +209,16 @@ int darts_render_transient(const darts_scene *scene, const darts_params *params,
 
 /* Per-path estimates (DARTS family only), for parity checks and variance
  * studies: path_value_dev[i] = total contribution of path path_offset + i
- * (device float[n_paths], overwritten).  Same kernel as the render. */
+ * to the estimate of Eq. (1) in its cell (Sections IV-V, as for
+ * darts_render_transient; device float[n_paths], overwritten).  Same kernel
+ * as the render. */
 int darts_render_paths(const darts_scene *scene, const darts_params *params,
                        const darts_table *table, float *path_value_dev, void *stream);
 
-/* Gradient of L = sum_c grad_image[c] * I[c] (I the raw per-cell sums the
- * render call would add) with respect to (sigma_s, sigma_a, g), by replaying
+/* Differentiable rendering, which the paper names as future work (Section
+ * VII): gradient of L = sum_c grad_image[c] * I[c] (I the raw per-cell sums
+ * the render call would add) with respect to (sigma_s, sigma_a, g) of the
+ * medium of Eq. (9) and the phase function, by replaying
  * the same paths (same ids, same Philox counters; nothing is stored between
  * the calls) and weighting each contribution with the derivative of the log
  * of its path throughput (detached sampling).  grad_image_dev: device
@@ -217,6 +227,19 @@ int darts_render_paths(const darts_scene *scene, const darts_params *params,
 int darts_render_transient_backward(const darts_scene *scene, const darts_params *params,
                                     const darts_table *table, const float *grad_image_dev,
                                     double *grad_out_dev, void *stream);
+
+/* Forward mode of the same derivative (Section VII, as for the backward
+ * call): tangent_dev[k][c] += the sum, over the paths mapped to cell c, of
+ * each connection's contribution times the derivative of the log of its path
+ * throughput with respect to theta_k, theta = (sigma_s, sigma_a, g): per-cell
+ * images of dI_c/dtheta_k (I the raw per-cell sums the render call would
+ * add; detached sampling, the same paths), whose sums weighted by a
+ * grad_image are darts_render_transient_backward's gradient.  For
+ * Gauss-Newton or Fisher-information computations that need the per-cell
+ * Jacobian.  tangent_dev: device float[3][n_bins][height][width],
+ * accumulate-into with plain FP32 atomics.  DARTS family only. */
+int darts_render_transient_tangent(const darts_scene *scene, const darts_params *params,
+                                   const darts_table *table, float *tangent_dev, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batched persistent render: many independent scenes (media, tables,

@@ -84,6 +84,7 @@ struct KParams {
     float *path_out;
     const float *grad_image;
     double *grad_out;
+    float *tangent;             // OUT_TANGENT: [3][ncells] accumulate-into
     int floor;                  // the box's bottom face is an opaque Lambertian floor
     float floor_albedo;
     // id-range decomposition (few paths per cell): wave w takes path ids
@@ -111,7 +112,9 @@ constexpr int kBlock = 256;
 #define DARTS_BATCH_WAVES_PER_SIMD 4
 #endif
 
-enum { OUT_IMAGE = 0, OUT_PATHS = 1, OUT_GRAD = 2 };
+// OUT_TANGENT: per-cell images of the derivatives of the path contributions
+// (forward mode of the same detached-sampling derivative OUT_GRAD reduces).
+enum { OUT_IMAGE = 0, OUT_PATHS = 1, OUT_GRAD = 2, OUT_TANGENT = 3 };
 
 // Per-lane statistics counters; with ON = false every increment compiles away.
 template <bool ON>
@@ -426,7 +429,7 @@ __device__ __forceinline__ void direction_darts(const KParams &P, PathState &s, 
     const V3 wp = s.w;
     s.w = sample_direction(m, P.tb, P.alpha, (P.flags & DARTS_EDA_DIR) != 0, de * rcp(s.C), s.C, s.G_hi - s.Le,
                            wp, r0, weight, eb);
-    if (OUT == OUT_GRAD) s.dlog_g += dlog_hg_dg(dot(wp, s.w), m.g);
+    if (OUT == OUT_GRAD || OUT == OUT_TANGENT) s.dlog_g += dlog_hg_dg(dot(wp, s.w), m.g);
     st.inc(DARTS_ST_EDA_BRANCH, eb ? 1u : 0u);
     s.beta *= weight;
     s.dm = P.box ? box_exit(P.bx, s.x, s.w) : kInf;
@@ -477,12 +480,13 @@ __device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &
     const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
     {
         float dl[3];
-        const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD ? dl : nullptr, st);
+        const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD || OUT == OUT_TANGENT ? dl : nullptr, st);
         if (c != 0.f) {
             st.inc(DARTS_ST_CONNECTIONS);
             s.acc += c;
-            if (OUT == OUT_GRAD) {
-                const double cw = (double)c * (double)grad_w;
+            if (OUT == OUT_GRAD || OUT == OUT_TANGENT) {
+                // the tangent mode sums this path's c dlog/dtheta (weight 1)
+                const double cw = OUT == OUT_GRAD ? (double)c * (double)grad_w : (double)c;
                 gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
             }
         }
@@ -490,12 +494,12 @@ __device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &
     const bool to_floor = FLOOR && exits_floor(P.bx, s.x, s.w);
     if (to_floor) {
         float dl[3];
-        const float c = floor_connect(P, s, OUT == OUT_GRAD ? dl : nullptr, st);
+        const float c = floor_connect(P, s, OUT == OUT_GRAD || OUT == OUT_TANGENT ? dl : nullptr, st);
         if (c != 0.f) {
             st.inc(DARTS_ST_CONNECTIONS);
             s.acc += c;
-            if (OUT == OUT_GRAD) {
-                const double cw = (double)c * (double)grad_w;
+            if (OUT == OUT_GRAD || OUT == OUT_TANGENT) {
+                const double cw = OUT == OUT_GRAD ? (double)c * (double)grad_w : (double)c;
                 gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
             }
         }
@@ -884,7 +888,13 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
                 if (s.acc == 0.f) st.inc(DARTS_ST_ZERO_PATHS);
                 if (MODE == 1 && P.m2) vanilla_flush_m2<SRC == SRC_VTILE>(P, s, pixel, hist);
                 if (MODE == 0) {
-                    if (OUT == OUT_PATHS) {
+                    if (OUT == OUT_TANGENT) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            if (gacc[k] != 0.0) unsafeAtomicAdd(P.tangent + (int64_t)k * P.ncells + cell, (float)gacc[k]);
+                            gacc[k] = 0.0;
+                        }
+                    } else if (OUT == OUT_PATHS) {
                         P.path_out[p - P.path_offset] = s.acc;
                     } else if (OUT == OUT_IMAGE && s.acc != 0.f) {
                         if (SRC == SRC_TILE) {
@@ -912,7 +922,7 @@ typedef __attribute__((address_space(4))) const KParams CKParams;
 template <int OUT>
 constexpr int render_waves_per_simd()
 {
-    return OUT == OUT_GRAD ? 4 : DARTS_RENDER_WAVES_PER_SIMD;
+    return OUT == OUT_GRAD || OUT == OUT_TANGENT ? 4 : DARTS_RENDER_WAVES_PER_SIMD;
 }
 
 template <int MODE, int OUT, bool STATS, bool FLOOR, int SRC>
@@ -1108,11 +1118,15 @@ __global__ void zero2_kernel(float *a, float *b, int64_t n)
 
 // ---------------------------------------------------------------------------
 // Elliptical-DA table (Section V-A, Eq. (16)-(18)), FP64.
-// One block (one wave) per (C/S, S) cell; lane k integrates cos-bin k with
-// the fixed Gauss-Legendre rule; lane 0 normalises the row and writes the
-// float cumulative sums.
+// One wave per (C/S, S) cell.  The (cos-bin, u-node) pairs of the row's
+// quadrature are spread over the 64 lanes (kGLU = 4 u-nodes per cos-bin: 16
+// bins per pass of the wave); each lane integrates its pair over the kGLV
+// v-nodes, the u-nodes of a bin are summed across 4 neighbouring lanes, and
+// the row is normalised and turned into its float CDF by a wave-wide FP64
+// prefix sum.
 // ---------------------------------------------------------------------------
 constexpr int kGLU = 4, kGLV = 64;
+static_assert(64 % kGLU == 0, "a cos-bin's u-nodes must share one pass of the wave");
 
 struct TParams {
     double sigma_s, sigma_a, sigma_t, albedo, D;
@@ -1133,42 +1147,53 @@ __global__ __launch_bounds__(64) void table_kernel(TParams T)
 {
     extern __shared__ double row[];
     const int cell = blockIdx.x;
+    const int lane = threadIdx.x;
     const int i = cell / T.n_s, j = cell % T.n_s;
     const double kappa = (i + 0.5) / T.n_cs;
     const double S = (j + 0.5) * T.s_max / T.n_s;
     const double C = kappa * S;
     const double h = 2.0 / T.n_cos;
-    for (int k = threadIdx.x; k < T.n_cos; k += blockDim.x) {
-        const double ulo = -1.0 + k * h;
-        double acc = 0.0;
-        for (int a = 0; a < kGLU; ++a) {
-            const double u = ulo + 0.5 * h * (T.xu[a] + 1.0);
+    const int n_pairs = T.n_cos * kGLU;
+    for (int base = 0; base < n_pairs; base += 64) {
+        const int pidx = base + lane;
+        double v = 0.0;
+        if (pidx < n_pairs) {
+            const int k = pidx / kGLU, a = pidx % kGLU;
+            const double u = -1.0 + k * h + 0.5 * h * (T.xu[a] + 1.0);
             const double tM = (S * S - C * C) / (2.0 * S - 2.0 * C * u);   // Eq. (18)
             const double pM = -expm1(-T.sigma_t * tM);
             double inner = 0.0;
             for (int bq = 0; bq < kGLV; ++bq) {
-                const double v = 0.5 * (T.xv[bq] + 1.0);
-                const double t = -log1p(-v * pM) / T.sigma_t;
+                const double vq = 0.5 * (T.xv[bq] + 1.0);
+                const double t = -log1p(-vq * pM) / T.sigma_t;
                 const double r2 = fmax(t * t + C * C - 2.0 * t * C * u, 0.0);
                 inner += 0.5 * T.wv[bq] * da_phi64(T, r2, S - t);
             }
-            acc += 0.5 * h * T.wu[a] * T.albedo * pM * inner;
+            v = 0.5 * h * T.wu[a] * T.albedo * pM * inner;
         }
-        row[k] = acc;
+        // the kGLU u-nodes of a cos-bin sit on consecutive lanes
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        if (pidx < n_pairs && (lane & (kGLU - 1)) == 0) row[pidx / kGLU] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int k = 0; k < T.n_cos; ++k) tot += row[k];
-        const bool good = isfinite(tot) && tot > 0.0;
-        float *out = T.cdf + (size_t)cell * (T.n_cos + 1);
-        double run = 0.0;
-        out[0] = 0.f;
-        for (int k = 0; k < T.n_cos; ++k) {
-            run += good ? row[k] / tot : 1.0 / T.n_cos;
-            out[k + 1] = (float)run;
+    double tot = 0.0;
+    for (int k = lane; k < T.n_cos; k += 64) tot += row[k];
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    const bool good = isfinite(tot) && tot > 0.0;
+    float *out = T.cdf + (size_t)cell * (T.n_cos + 1);
+    if (lane == 0) out[0] = 0.f;
+    double carry = 0.0;
+    for (int base = 0; base < T.n_cos; base += 64) {
+        const int k = base + lane;
+        double x = k < T.n_cos ? (good ? row[k] / tot : 1.0 / T.n_cos) : 0.0;
+        for (int o = 1; o < 64; o <<= 1) {   // inclusive prefix sum across the wave
+            const double y = __shfl_up(x, o);
+            if (lane >= o) x += y;
         }
-        out[T.n_cos] = 1.f;
+        x += carry;
+        if (k < T.n_cos) out[k + 1] = k == T.n_cos - 1 ? 1.f : (float)x;
+        carry = __shfl(x, 63);
     }
 }
 
@@ -1532,6 +1557,7 @@ int make_params(const darts_scene *sc, const darts_params *pr, const darts_table
     P.path_out = nullptr;
     P.grad_image = nullptr;
     P.grad_out = nullptr;
+    P.tangent = nullptr;
     return DARTS_OK;
 }
 
@@ -1957,6 +1983,16 @@ int darts_render_transient_backward(const darts_scene *scene, const darts_params
     P.grad_image = grad_image_dev;
     P.grad_out = grad_out_dev;
     return launch_render<0, OUT_GRAD>(P, false, (hipStream_t)stream);
+}
+
+int darts_render_transient_tangent(const darts_scene *scene, const darts_params *params, const darts_table *table,
+                                   float *tangent_dev, void *stream)
+{
+    KParams P;
+    if (int rc = make_params(scene, params, table, P, true)) return rc;
+    if (!tangent_dev) return fail(DARTS_ERR_INVALID_ARG, "tangent_dev is null");
+    P.tangent = tangent_dev;
+    return launch_render<0, OUT_TANGENT>(P, false, (hipStream_t)stream);
 }
 
 int darts_batch_default_plan(darts_batch_plan *plan)

@@ -113,6 +113,8 @@ def lib() -> C.CDLL:
         L.darts_render_paths.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Table), vp, vp]
         L.darts_render_transient_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Table),
                                                       vp, vp, vp]
+        L.darts_render_transient_tangent.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.POINTER(_Table),
+                                                     vp, vp]
         L.darts_debug_pointwise.argtypes = [C.c_int, vp, vp, i64, C.POINTER(_Medium), C.POINTER(_Table), vp]
         L.darts_set_target_waves.argtypes = [i64]
         L.darts_set_ids_max_reps.argtypes = [i64]
@@ -322,6 +324,21 @@ def render_transient_backward(sc: dict, p: dict, mode, table: Table | None, grad
     _check(lib().darts_render_transient_backward(C.byref(h.c), C.byref(params(p, mode)), tb,
                                                  _ptr(gi), _ptr(grad_out), _stream(stream)))
     return grad_out
+
+
+def render_transient_tangent(sc: dict, p: dict, mode, table: Table | None, out=None, stream=None,
+                             device="cuda", response: Response | None = None) -> torch.Tensor:
+    """Per-cell derivative images of the raw sums, [3, *image_shape] for
+    (sigma_s, sigma_a, g) (darts_render_transient_tangent), accumulated into
+    `out` (zeros by default)."""
+    shape = (3,) + tuple(image_shape(sc, response))
+    if out is None:
+        out = torch.zeros(shape, dtype=torch.float32, device=device)
+    h = _SceneHolder(sc, response)
+    tb = C.byref(table.c_struct()) if table is not None else None
+    _check(lib().darts_render_transient_tangent(C.byref(h.c), C.byref(params(p, mode)), tb, _ptr(out),
+                                                _stream(stream)))
+    return out
 
 
 def debug_pointwise(fn: str, inputs: torch.Tensor, med: dict | None = None, table: Table | None = None,
