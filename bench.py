@@ -113,12 +113,11 @@ def parse():
     ap.add_argument("--no-fog", action="store_true", help="skip the fog-layer render and the Adam fit")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing on the differentiable box")
     ap.add_argument("--batched-reps", type=int, default=5, help="timed graph launches of the batch")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-converge", action="store_true",
-                    help="skip the measured (progressive-launch) time to MSE 1e-4 on the early time gate")
-    ap.add_argument("--converge-ref-log2", type=int, default=36,
-                    help="log2 of the reference's paths per arm for the measured time to MSE "
-                         "(36: about 20 s, reference MSE about 3e-6; 38: about 80 s)")
+                    help="skip the measured (progressive-launch) time to MSE 1e-4 on three time gates")
+    ap.add_argument("--converge-cap-seconds", type=float, default=4.0,
+                    help="most seconds of launches per arm and gate in the measured time to MSE")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device once (a kernel of known "
                          "traffic that calibrates the HBM byte counters of a profiler run)")
@@ -283,7 +282,7 @@ def main():
         out["batched"] = batched_bench(darts, torch, W, a.batched_reps)
         print(f"[bench] batched {out['batched']}", file=sys.stderr, flush=True)
     if not a.no_converge:
-        out["measured_time_to_mse"] = measured_convergence(darts, torch, np, W, ref_log2=a.converge_ref_log2)
+        out["measured_time_to_mse"] = measured_convergence(darts, torch, np, W, cap_seconds=a.converge_cap_seconds)
         print(f"[bench] measured time to MSE {out['measured_time_to_mse']}", file=sys.stderr, flush=True)
     if a.copy_bytes > 0:
         src = torch.empty(a.copy_bytes // 4, dtype=torch.float32, device=dev)
@@ -429,83 +428,87 @@ def time_gated(darts, torch, np, W, gates=GATES, width=0.15625, n_thr=1 << 26, k
     return rep
 
 
-def measured_convergence(darts, torch, np, W, gate=(3.0, 3.15625), ref_log2=38, chunk_log2=28,
-                         arms=(("darts_alpha4", "darts", 4.0), ("uniform", "uniform", 0.5)), target=1e-4):
-    """Time to MSE `target` measured, not extrapolated, on one time-gated
-    frame of the box workload: progressive launches, each doubling the path
-    count (N = 2^20, 2^21, ...; every launch adds as many new paths as the
-    frame already holds), MSE checked after each against a reference, wall
-    time (launches plus one table build) accumulated until the MSE reaches
-    the target; the crossing itself is placed between the last two doublings
-    with MSE ~ 1/N (`seconds_at_crossing`).  The reference is the inverse-variance combination, per
-    pixel, of 2^ref_log2 paths of each arm (seed 0x5EF, path ids disjoint
-    from the progressive runs), its own MSE stated; the MSE is normalised by
-    the reference's 0.95 quantile, as in time_gated."""
-    w = W.box_hg()
-    w["scene"]["bins"] = {"l_lo": gate[0], "l_hi": gate[0] + (gate[1] - gate[0]), "n_bins": 1}
-    sc, pr, dm = w["scene"], w["params"], w["dims"]
-    t0 = time.perf_counter()
-    table = darts.build_da_tables(sc["medium"], dm)
-    torch.cuda.synchronize()
-    t_table = time.perf_counter() - t0
-    shape = darts.image_shape(sc)
-    chunk = 1 << chunk_log2
-    n_chunks = 1 << (ref_log2 - chunk_log2)
-    means, vars_ = [], []
-    for arm, mode, alpha in arms:
-        s1 = torch.zeros(shape, dtype=torch.float64, device="cuda")
-        s2 = torch.zeros_like(s1)
-        hi = torch.zeros(shape, dtype=torch.float32, device="cuda")
-        lo = torch.zeros_like(hi)
-        for c in range(n_chunks):
-            hi.zero_(); lo.zero_()
-            pc = dict(pr, n_paths=chunk, path_offset=(1 << 45) + c * chunk, seed=0x5EF, alpha=alpha)
-            darts.render_transient(sc, pc, mode, table, hi, lo)
-            n = darts.paths_per_cell(sc, pc, mode).to("cuda")
-            x = (hi.double() + lo.double()) / n.clamp(min=1)
-            s1 += x
-            s2 += x * x
-        m = s1 / n_chunks
-        means.append(m)
-        vars_.append(torch.clamp(s2 / n_chunks - m * m, min=0) / (n_chunks - 1))   # variance of the mean
-    wts = [1.0 / torch.clamp(v, min=1e-300) for v in vars_]
-    ref = sum(wi * mi for wi, mi in zip(wts, means)) / sum(wts)
-    ref_var = 1.0 / sum(wts)
-    refn = ref.cpu().numpy()
-    q95 = float(np.quantile(refn, 0.95))
-    rep = {"gate": list(gate), "target": target, "reference_paths_per_arm": 1 << ref_log2, "q95": q95,
-           "reference_mse": float(ref_var.mean()) / q95 ** 2, "table_build_s": t_table}
-    for arm, mode, alpha in arms:
-        hi = torch.zeros(shape, dtype=torch.float32, device="cuda")
-        lo = torch.zeros_like(hi)
-        total, wall, n_log2, hist = 0, t_table, 20, []
-        while n_log2 <= 40:
-            add = (1 << 20) if total == 0 else total
-            pc = dict(pr, n_paths=add, path_offset=(1 << 44) + total, seed=0xC0, alpha=alpha)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            darts.render_transient(sc, pc, mode, table, hi, lo)
-            torch.cuda.synchronize()
-            wall += time.perf_counter() - t1
-            total += add
-            pall = dict(pr, n_paths=total, path_offset=1 << 44, seed=0xC0, alpha=alpha)
-            n = darts.paths_per_cell(sc, pall, mode).to("cuda")
-            est = (hi.double() + lo.double()) / n.clamp(min=1)
-            mse = float(((est - ref) ** 2).mean()) / q95 ** 2
-            hist.append((total, wall, mse))
-            if mse <= target:
-                break
-            n_log2 += 1
-        # crossing between the last two doublings, with MSE ~ 1/N and launch time ~ N
-        mse_last = hist[-1][2]
-        frac = min(1.0, mse_last / target)
-        rep[arm] = {"alpha": alpha, "paths": total, "seconds": wall, "mse": mse_last, "reached": mse_last <= target,
-                    "seconds_at_crossing": t_table + (wall - t_table) * frac, "paths_at_crossing": total * frac,
-                    "history": [{"paths": a, "seconds": b, "mse": c} for a, b, c in hist]}
-    if all(rep[a]["reached"] for a, _, _ in arms):
-        rep["uniform_over_darts_alpha4_time"] = (rep["uniform"]["seconds_at_crossing"] /
-                                                 rep["darts_alpha4"]["seconds_at_crossing"])
-    return rep
+MEASURED_ARMS = (("darts", "darts", 0.5), ("darts_alpha2", "darts", 2.0), ("darts_alpha4", "darts", 4.0),
+                 ("da_only", "da_only", 0.5), ("uniform", "uniform", 0.5), ("vanilla", "vanilla", 0.5))
+
+
+def measured_convergence(darts, torch, np, W, gates=(3.0, 6.0, 10.0), width=0.15625, q95_log2=32,
+                         arms=MEASURED_ARMS, target=1e-4, cap_seconds=4.0):
+    """Time to MSE `target` measured, not extrapolated, on time-gated frames
+    of the box workload (one gate [L0, L0 + width) per frame, the form of the
+    paper's comparison).  Each arm renders two independent replicas (seeds
+    0xC0 and 0xC1, disjoint path ids) by progressive launches, each doubling
+    the path count (N = 2^20, 2^21, ...; every launch adds as many new paths
+    as the frame already holds).  Both replicas are unbiased and independent,
+    so half the mean squared difference of their images is the MSE of one
+    replica at N paths; no reference image enters.  The MSE is normalised by
+    the 0.95 quantile of the frame (from 2^q95_log2 paths each of DARTS at
+    alpha = 4 and uniform sampling).  Wall time is that of one replica's
+    launches plus one table build, accumulated until the MSE reaches the
+    target (`reached`, and `seconds_at_crossing` placed between the last two
+    doublings with MSE ~ 1/N) or until the launches have taken `cap_seconds`
+    (then `extrapolated_seconds` continues MSE ~ 1/N from the last doubling).
+    `time_ratio_vs_uniform`: uniform sampling's time over the arm's (above 1:
+    the arm is faster), from the crossings or the extrapolations."""
+    out = {}
+    for L0 in gates:
+        w = W.box_hg()
+        w["scene"]["bins"] = {"l_lo": L0, "l_hi": L0 + width, "n_bins": 1}
+        sc, pr, dm = w["scene"], w["params"], w["dims"]
+        t0 = time.perf_counter()
+        table = darts.build_da_tables(sc["medium"], dm)
+        torch.cuda.synchronize()
+        t_table = time.perf_counter() - t0
+        shape = darts.image_shape(sc)
+        img = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        for mode, alpha in (("darts", 4.0), ("uniform", 0.5)):
+            pq = dict(pr, n_paths=1 << q95_log2, path_offset=1 << 45, seed=0x5EF, alpha=alpha)
+            hi, lo, _, _ = darts.render_transient(sc, pq, mode, table)
+            n = darts.paths_per_cell(sc, pq, mode).to("cuda")
+            img += (hi.double() + lo.double()) / n.clamp(min=1) / 2
+        q95 = float(np.quantile(img.cpu().numpy(), 0.95))
+        rep = {"gate": [L0, L0 + width], "target": target, "q95": q95, "q95_paths": 2 << q95_log2,
+               "table_build_s": t_table, "cap_seconds": cap_seconds}
+        for arm, mode, alpha in arms:
+            imgs = [[torch.zeros(shape, dtype=torch.float32, device="cuda") for _ in range(2)] for _ in range(2)]
+            total, wall, hist = 0, t_table, []
+            while True:
+                add = (1 << 20) if total == 0 else total
+                for rpl, seed in enumerate((0xC0, 0xC1)):
+                    pc = dict(pr, n_paths=add, path_offset=(1 << 44) + total, seed=seed, alpha=alpha)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    darts.render_transient(sc, pc, mode, table, imgs[rpl][0], imgs[rpl][1])
+                    torch.cuda.synchronize()
+                    if rpl == 0:
+                        wall += time.perf_counter() - t1
+                total += add
+                pall = dict(pr, n_paths=total, path_offset=1 << 44, alpha=alpha)
+                n = darts.paths_per_cell(sc, pall, mode).to("cuda").clamp(min=1)
+                a = (imgs[0][0].double() + imgs[0][1].double()) / n
+                b = (imgs[1][0].double() + imgs[1][1].double()) / n
+                mse = float(((a - b) ** 2).mean()) / 2 / q95 ** 2
+                hist.append((total, wall, mse))
+                if mse <= target or wall - t_table >= cap_seconds or total >= (1 << 40):
+                    break
+            mse_last = hist[-1][2]
+            reached = mse_last <= target
+            frac = mse_last / target   # MSE ~ 1/N and launch time ~ N
+            r = {"alpha": alpha, "paths": total, "seconds": wall, "mse": mse_last, "reached": reached,
+                 "history": [{"paths": x, "seconds": y, "mse": z} for x, y, z in hist]}
+            if reached:
+                r["seconds_at_crossing"] = t_table + (wall - t_table) * min(1.0, frac)
+                r["paths_at_crossing"] = total * min(1.0, frac)
+            else:
+                r["extrapolated_seconds"] = t_table + (wall - t_table) * frac
+            rep[arm] = r
+        tu = rep["uniform"].get("seconds_at_crossing", rep["uniform"].get("extrapolated_seconds"))
+        for arm, _, _ in arms:
+            ta = rep[arm].get("seconds_at_crossing", rep[arm].get("extrapolated_seconds"))
+            if tu and ta:
+                rep[arm]["time_ratio_vs_uniform"] = tu / ta
+        out[f"L0={L0:g}"] = rep
+    return out
 
 
 def response_bench(darts, torch, np, W, w, n_thr=1 << 26, n_var=1 << 26, k=64, target=1e-4):
@@ -586,6 +589,11 @@ def fog_bench(darts, torch, W, reps=2):
     fw = W.fog_slab_fit()
     fit = inverse.fit_medium(fw, fw["target_medium"], fw["init_medium"], **FIT_SETTINGS)
     tm, im = fw["target_medium"], fw["init_medium"]
+    # what the fit's target image determines: Gauss-Newton geometry of the L2
+    # fit from forward-mode derivative images (the target of 2^27 paths the
+    # fit uses; Jacobians from 2^31 paths each, uniform sampling for the
+    # lightest-tailed estimate)
+    info = inverse.fit_information(fw, tm, "uniform", target_paths=1 << 27, jac_paths=1 << 31)
     return {
         "render": {"paths": n, "cells": 256 * 256 * 1024, "render_ms": ms, "paths_per_s": n / ms * 1e3},
         "fit": {"target": {"sigma_s": tm["sigma_s"], "g": tm["g"]}, "init": {"sigma_s": im["sigma_s"], "g": im["g"]},
@@ -595,6 +603,7 @@ def fog_bench(darts, torch, W, reps=2):
                 "steps": fit["steps"], "seconds": fit["seconds"], "ms_per_step": fit["seconds"] / fit["steps"] * 1e3,
                 "paths_per_render": fit["paths_per_render"], "mode": fit["mode"],
                 "image": "16x16 x 128 bins over [0,40)"},
+        "fit_information": info,
     }
 
 
@@ -678,39 +687,84 @@ def batched_bench(darts, torch, W, reps):
         torch.cuda.synchronize()
         seq.append(e0.elapsed_time(e1))
     seq_ms = min(seq)
+    # the batch's work: the same paths rendered one medium at a time with the
+    # statistics counters (vertex steps), priced at the per-unit figures
+    steps = 0
+    for sc, p, mode, t in items:
+        _, _, _, st = darts.render_transient(sc, p, mode, t, want_stats=True)
+        s_ = darts.stats_dict(st)
+        steps += s_["vertices"] - s_["early_exit"]
+    torch.cuda.synchronize()
+    flops = FLOPS_PER_VERTEX_STEP * steps + FLOPS_PER_PATH * n_paths
     return {"media": len(ws), "paths": n_paths, "plan": plan, "autotune_s": t_tune, "tuned_launch_ms": tuned_ms,
             "graph_launch_ms": graph_ms, "paths_per_s": n_paths / graph_ms * 1e3,
+            "vertex_steps": steps, "mean_steps_per_path": steps / n_paths,
+            "algorithmic_tflops": flops / graph_ms / 1e9, "vertex_steps_per_s": steps / graph_ms * 1e3,
             "separate_calls_ms": seq_ms, "speedup_vs_separate_calls": seq_ms / graph_ms,
             "table_build_s": t_tables,
             "workload": "256 box media, sigma_s~U[0.5,20], albedo~U[0.8,0.999], g~U[-0.3,0.9], 32x32 x 128 bins "
                         "over [0,40), budgets log-uniform in [2^12,2^18], 64x64x32 tables"}
 
 
-def cpu_baseline(w, seconds):
-    """The oracle as it stands on the host cores: DARTS on the same box
-    workload, doubling the sample until about `seconds` of work."""
-    from oracle import ref
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_rate(ref, w, mode, cdf, threads, seconds):
+    """Paths/s of the oracle on workload w, doubling the sample from 2^12
+    until about `seconds` of work."""
     sc, pr, dm = w["scene"], w["params"], w["dims"]
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    _, cdf = ref.build_table(sc["medium"], dm, n_threads=threads)
-    n = 1 << 16
+    n = 1 << 12
     while True:
         p = dict(pr, n_paths=n)
         t0 = time.perf_counter()
-        ref.render(sc, p, "darts", cdf, dm, n_threads=threads)
+        ref.render(sc, p, mode, cdf, dm, n_threads=threads)
         dt = time.perf_counter() - t0
         if dt >= seconds or n >= (1 << 26):
-            break
-        n = n * 2 if dt * 2.5 < seconds else int(n * seconds / max(dt, 1e-3))
+            return n, dt
+        n = n * 2 if dt * 2.5 < seconds else max(n + 1, int(n * seconds / max(dt, 1e-3)))
+
+
+def cpu_baseline(w, seconds):
+    """The oracle as it stands on the host cores: DARTS on the same box
+    workload (`value`, about `seconds` of work on all threads, plus a quarter
+    of that work on one thread), and the planned grid: DARTS, uniform and
+    vanilla on the box workload and on the infinite-medium workload, each on
+    all threads and on one thread (about seconds/16 each)."""
+    from oracle import ref
+    from paper_2402_03106_amd import workloads as W
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    _, cdf = ref.build_table(sc["medium"], dm, n_threads=threads)
+    n, dt = _oracle_rate(ref, w, "darts", cdf, threads, seconds)
     # one thread on about a quarter of that work: the per-core rate
     n1 = max(1 << 12, int(n / max(threads, 1) / 4))
     t0 = time.perf_counter()
     ref.render(sc, dict(pr, n_paths=n1), "darts", cdf, dm, n_threads=1)
     dt1 = time.perf_counter() - t0
+    grid = {}
+    for wname, wk in (("box_hg", w), ("infinite_point", W.infinite_point())):
+        _, cdf_k = ref.build_table(wk["scene"]["medium"], wk["dims"], n_threads=threads)
+        for mode in ("darts", "uniform", "vanilla"):
+            e = {}
+            for label, th in (("all_threads", threads), ("one_thread", 1)):
+                nk, dk = _oracle_rate(ref, wk, mode, cdf_k if mode == "darts" else None, th, seconds / 16)
+                e[label] = {"paths_per_s": nk / dk, "paths": nk, "seconds": dk}
+            grid[f"{wname}/{mode}"] = e
     return {"value": n / dt, "unit": "paths/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{n} DARTS paths of the box workload (ids 0..{n - 1}), FP64, {dt:.1f} s",
             "single_thread_value": n1 / dt1,
-            "single_thread_sample": f"{n1} paths (ids 0..{n1 - 1}) on one thread, {dt1:.1f} s"}
+            "single_thread_sample": f"{n1} paths (ids 0..{n1 - 1}) on one thread, {dt1:.1f} s",
+            "grid": grid}
 
 
 if __name__ == "__main__":
