@@ -35,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "transient paths/s and time-to-MSE 1e-4, DARTS vs uniform sampling, 1×MI355X"
-FIT_SETTINGS = {"steps": 200, "mode": "da_only", "lr": 0.05, "lr_final": 0.01, "n_paths": 1 << 24}
+FIT_SETTINGS = {"steps": 200, "mode": "da_only", "lr": 0.05, "lr_final": 0.01, "n_paths": 1 << 26}
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
 HBM_PEAK_GBS = 8000.0
 
@@ -113,6 +113,8 @@ def parse():
     ap.add_argument("--no-fog", action="store_true", help="skip the fog-layer render and the Adam fit")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing on the differentiable box")
     ap.add_argument("--batched-reps", type=int, default=5, help="timed graph launches of the batch")
+    ap.add_argument("--batched-scale", type=int, default=1,
+                    help="multiply every medium's path budget of the batched sweep (the default line uses 1)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-converge", action="store_true",
                     help="skip the measured (progressive-launch) time to MSE 1e-4 on three time gates")
@@ -279,7 +281,7 @@ def main():
         out["adjoint"] = adjoint_bench(darts, torch, W)
         print(f"[bench] adjoint {out['adjoint']}", file=sys.stderr, flush=True)
     if not a.no_batched:
-        out["batched"] = batched_bench(darts, torch, W, a.batched_reps)
+        out["batched"] = batched_bench(darts, torch, W, a.batched_reps, a.batched_scale)
         print(f"[bench] batched {out['batched']}", file=sys.stderr, flush=True)
     if not a.no_converge:
         out["measured_time_to_mse"] = measured_convergence(darts, torch, np, W, cap_seconds=a.converge_cap_seconds)
@@ -648,12 +650,15 @@ def adjoint_bench(darts, torch, W, reps=3):
             "cells": int(n.numel()), "grad": [float(x) for x in g.cpu()]}
 
 
-def batched_bench(darts, torch, W, reps):
+def batched_bench(darts, torch, W, reps, scale=1):
     """The many-media sweep: 256 box media with uneven budgets in one
     persistent launch (plan chosen by the autotuner), replayed as a captured
     graph (clear + launch), against one render call per medium on the same
-    paths.  Tables are built once, outside the timed region."""
+    paths.  Tables are built once, outside the timed region.  `scale`
+    multiplies every medium's budget (how the launch's tail weighs)."""
     ws = W.batched()
+    for w in ws:
+        w["params"]["n_paths"] = int(w["params"]["n_paths"]) * int(scale)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tables = [darts.build_da_tables(w["scene"]["medium"], w["dims"]) for w in ws]
@@ -696,14 +701,15 @@ def batched_bench(darts, torch, W, reps):
         steps += s_["vertices"] - s_["early_exit"]
     torch.cuda.synchronize()
     flops = FLOPS_PER_VERTEX_STEP * steps + FLOPS_PER_PATH * n_paths
-    return {"media": len(ws), "paths": n_paths, "plan": plan, "autotune_s": t_tune, "tuned_launch_ms": tuned_ms,
+    return {"media": len(ws), "budget_scale": int(scale), "paths": n_paths, "plan": plan, "autotune_s": t_tune, "tuned_launch_ms": tuned_ms,
             "graph_launch_ms": graph_ms, "paths_per_s": n_paths / graph_ms * 1e3,
             "vertex_steps": steps, "mean_steps_per_path": steps / n_paths,
             "algorithmic_tflops": flops / graph_ms / 1e9, "vertex_steps_per_s": steps / graph_ms * 1e3,
             "separate_calls_ms": seq_ms, "speedup_vs_separate_calls": seq_ms / graph_ms,
             "table_build_s": t_tables,
             "workload": "256 box media, sigma_s~U[0.5,20], albedo~U[0.8,0.999], g~U[-0.3,0.9], 32x32 x 128 bins "
-                        "over [0,40), budgets log-uniform in [2^12,2^18], 64x64x32 tables"}
+                        f"over [0,40), budgets log-uniform in [2^12,2^18]{'' if scale == 1 else f' x {scale}'}, "
+                        "64x64x32 tables"}
 
 
 def cpu_model() -> str:

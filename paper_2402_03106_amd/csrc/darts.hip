@@ -1374,6 +1374,7 @@ Medium make_medium(const darts_medium &m)
     o.ln2_over_sigma_t = (float)(0.69314718055994530942 / (m.sigma_s + m.sigma_a));
     o.inv4D_log2e = (float)(1.4426950408889634074 / (4.0 * D));
     o.sigma_a_log2e = (float)(1.4426950408889634074 * m.sigma_a);
+    o.four_D_sigma_a = (float)(4.0 * D * m.sigma_a);
     o.hg = hg_consts(o.g);
     return o;
 }
@@ -1385,7 +1386,7 @@ bool same_medium(const darts_medium &a, const darts_medium &b)
 
 int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &tb)
 {
-    tb = Table{nullptr, 1, 1, 1, 0.f, 1.f, 1.f, 2.f};
+    tb = Table{nullptr, 1, 1, 1, 1, 0.f, 1.f, 1.f, 2.f};
     if (!needed) return DARTS_OK;
     if (!t || !t->cdf_dev) return fail(DARTS_ERR_INVALID_ARG, "EDA direction sampling needs a built table");
     if (int rc = check_dims(&t->dims)) return rc;
@@ -1395,6 +1396,8 @@ int fill_table(const darts_table *t, const darts_scene *sc, bool needed, Table &
     tb.n_cs = t->dims.n_cs;
     tb.n_s = t->dims.n_s;
     tb.n_cos = t->dims.n_cos;
+    tb.cos_pow2 = 1;
+    while (tb.cos_pow2 <= tb.n_cos / 2) tb.cos_pow2 *= 2;
     tb.ns_over_smax = (float)t->dims.n_s / t->dims.s_max;
     tb.fn_cs = (float)tb.n_cs;
     tb.fn_cos = (float)tb.n_cos;

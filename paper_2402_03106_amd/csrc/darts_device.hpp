@@ -42,8 +42,9 @@ __device__ __forceinline__ V3 fma3(V3 x, V3 w, float t) { return V3{fmaf(w.x, t,
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
 // with a Weyl-sequence key schedule.  Counter layout of this library:
-// (path id low, path id high, vertex index or 0xFFFFFFFF for camera set-up,
-// stream), key = seed.
+// (path id low, path id high, vertex index k, stream), key = seed; stream 0
+// of vertex 0 is the camera set-up, stream 0 of vertex k >= 1 the direction
+// sample, stream 1 of vertex k the connection and free flight.
 // ---------------------------------------------------------------------------
 struct U4 { uint32_t x, y, z, w; };
 
@@ -266,6 +267,7 @@ struct Medium {
     float inv4D;      // 1 / (4 D), D = 1 / (3 (sigma_a + sigma_s (1 - g)))  (Eq. (9))
     float ln2_over_sigma_t;
     float inv4D_log2e, sigma_a_log2e;   // the exponent of Eq. (9) in base 2
+    float four_D_sigma_a;               // 4 D sigma_a = sigma_a_log2e / inv4D_log2e
     HG hg;
 };
 
@@ -308,10 +310,11 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
                                              float epc, uint32_t row, uint32_t eps, float u_sel,
                                              float &d_out, float &factor, uint32_t *choice = nullptr)
 {
-    // Phi_i = (4 pi D s_i)^{-3/2} exp(E_i),  E_i = -r_i^2 / (4 D s_i) - sigma_a s_i:
-    // the weights s_i^{-3/2} 2^{(E_i - E_max) log2 e} share one rsq per
-    // candidate and cannot underflow for the candidate with the largest
-    // exponent.  The exponents are formed in base 2 (E_i log2 e).
+    // Phi_i = (4 pi D s_i)^{-3/2} exp(E_i),  E_i = -r_i^2 / (4 D s_i) - sigma_a s_i
+    // = -(r_i^2 + 4 D sigma_a s_i^2) / (4 D s_i): with F_i = (r_i^2 + 4 D
+    // sigma_a s_i^2) / s_i the weights s_i^{-3/2} 2^{(F_min - F_i) log2 e / (4 D)}
+    // share one rsq per candidate (1/s_i = rsq^2, s_i^{-3/2} = rsq^3) and
+    // cannot underflow for the candidate with the smallest F.
     //
     // Candidate uniforms: the radical inverse of 8 row + i is the radical
     // inverse of 8 row plus that of i (the low three bits of 8 row are zero,
@@ -330,8 +333,8 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
     //    of non-negative terms with 1 - u exact, rounded once.
     const uint32_t base = __builtin_bitreverse32(8u * row) + eps;
     const float pc24 = pc * 0x1p-24f, em24 = epc * 0x1p-24f;
-    float dc[8], q[8], E[8];
-    float emax = -kInf;
+    float dc[8], q[8], F[8];
+    float fmin = kInf;
     const float two_b = 2.f * b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -344,20 +347,22 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
         const float di = -L * m.ln2_over_sigma_t;
         const float si = R_hi - di;
         const float r2 = fmaf(di, di - two_b, C2);
-        const bool valid = (si > 0.f) && (r2 < si * si);   // inside the residual-time ellipsoid
-        const float rq = rsq(si);
-        const float e = -fmaf(r2 * m.inv4D_log2e, rq * rq, m.sigma_a_log2e * si);
+        const float si2 = si * si;
+        const bool valid = (si > 0.f) && (r2 < si2);   // inside the residual-time ellipsoid
+        const float rq = rsq(si), rq2 = rq * rq;
+        const float f = fmaf(si2, m.four_D_sigma_a, r2) * rq2;
         dc[i] = di;
-        q[i] = valid ? rq * rq * rq : 0.f;
-        E[i] = valid ? e : -kInf;
-        emax = fmaxf(emax, E[i]);
+        q[i] = valid ? rq2 * rq : 0.f;
+        F[i] = valid ? f : kInf;
+        fmin = fminf(fmin, F[i]);
         if (choice) *choice = (i == 0 ? 0u : *choice) | (valid ? 1u << (8 + i) : 0u);
     }
-    if (!(emax > -kInf)) return false;
+    if (!(fmin < kInf)) return false;
+    const float cmin = m.inv4D_log2e * fmin;
     float wv[8];
     double wsum = 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { wv[i] = q[i] * exp2_hw(E[i] - emax); wsum += (double)wv[i]; }
+    for (int i = 0; i < 8; ++i) { wv[i] = q[i] * exp2_hw(fmaf(-m.inv4D_log2e, F[i], cmin)); wsum += (double)wv[i]; }
     const double target = (double)u_sel * wsum;
     double cum = 0.0;
     float dsel = dc[7], wsel = wv[7];
@@ -393,10 +398,11 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
 // ---------------------------------------------------------------------------
 // A built direction table as the kernels read it: the float constants are
 // formed once on the host (fn_cs = n_cs, fn_cos = n_cos, cos_step =
-// 2 / n_cos, ns_over_smax = n_s / s_max); offsets fit 32 bits.
+// 2 / n_cos, ns_over_smax = n_s / s_max, cos_pow2); offsets fit 32 bits.
 struct Table {
     const float *cdf;
     int n_cs, n_s, n_cos;
+    int cos_pow2;   // the largest power of two <= n_cos
     float ns_over_smax, fn_cs, fn_cos, cos_step;
 };
 
@@ -423,15 +429,20 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
     float mu, s, c_lo = 0.f, c_hi = 0.f;
     int k = 0;
     if (eda_branch) {
-        // largest k with cdf[k] <= u1 (cdf[0] = 0 <= u1 < 1 = cdf[n_cos])
-        int lo = 0, hi = tb.n_cos;
-        c_lo = 0.f; c_hi = 1.f;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            const float v = row[mid];
-            if (v <= u1) { lo = mid; c_lo = v; } else { hi = mid; c_hi = v; }
-        }
+        // largest k < n_cos with cdf[k] <= u1 (cdf[0] = 0 <= u1 < 1 =
+        // cdf[n_cos], nondecreasing) by a binary search whose probes depend
+        // on n_cos alone: with P the largest power of two <= n_cos, one probe
+        // at n_cos - P, then steps P/2, ..., 1 (lo + step <= n_cos - 1), so
+        // every lane makes the same number of probes and the loop stays
+        // uniform across the wave.
+        int lo = 0;
+        const int first = tb.n_cos - tb.cos_pow2;
+        if (first > 0 && row[first] <= u1) lo = first;
+        for (int step = tb.cos_pow2 >> 1; step > 0; step >>= 1)
+            lo = row[lo + step] <= u1 ? lo + step : lo;
         k = lo;
+        c_lo = row[k];
+        c_hi = row[k + 1];
         mu = fmaf((float)k + u3, tb.cos_step, -1.f);
         s = hw_sqrt(fmaxf((1.f - mu) * (1.f + mu), 0.f));
         axis = a;

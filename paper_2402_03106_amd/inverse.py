@@ -123,14 +123,19 @@ def fit_medium(w: dict, target_medium: dict, init_medium: dict, steps: int = 200
     per-cell estimates [n_bins, H, W]), starting from `init_medium`.  The
     learning rate decays from `lr` to `lr_final` on a cosine schedule; the
     estimate is the mean of the last `average_last` iterates (the single
-    iterates carry the noise of the stochastic gradient).  Returns the
-    trajectory and the estimate.
+    iterates carry the noise of the stochastic gradient), taken in the
+    coordinates Adam works in, log sigma_s (1 - g) and atanh(g / 0.99), and
+    mapped back, so that the estimate's sigma_s (1 - g) is the geometric mean
+    of the iterates' (averaging sigma_s and g separately would bias it where
+    g is near 1 and sigma_s = sigma_s (1 - g) / (1 - g) swings between
+    iterates).  Returns the trajectory and the estimate.
 
     With `relative` the loss is sum_c (I_c - T_c)^2 / (T_c^2 + e^2) with e =
     rel_floor * max T: every cell counts by its relative error, so the dim
     early (single-scattering) and late cells, which separate sigma_s from g,
-    weigh as much as the bright diffuse ones (a plain L2 loss only sees the
-    reduced scattering coefficient sigma_s (1 - g))."""
+    weigh as much as the bright diffuse ones (to first order a plain L2 loss
+    on the fog layer's view changes only with sigma_s (1 - g): see
+    fit_information)."""
     sc, dm, pr = w["scene"], w["dims"], w["params"]
     sigma_a = float(target_medium["sigma_a"])
     if target_image is None:
@@ -150,6 +155,7 @@ def fit_medium(w: dict, target_medium: dict, init_medium: dict, steps: int = 200
     hist = []
     t0 = time.perf_counter()
     for it in range(steps):
+        coords = (float(log_s), float(atanh_g))
         theta = _theta(log_s, atanh_g, sigma_a)
         with torch.no_grad():
             I1 = darts.transient_image(theta.detach(), sc, dict(pr, n_paths=n_paths, seed=seed + 2 * it + 1), mode, dm)
@@ -161,10 +167,12 @@ def fit_medium(w: dict, target_medium: dict, init_medium: dict, steps: int = 200
         opt.step()
         sched.step()
         th = theta.detach()
-        hist.append({"step": it, "loss": float((wgt * r * r).sum()), "sigma_s": float(th[0]), "g": float(th[2])})
+        hist.append({"step": it, "loss": float((wgt * r * r).sum()), "sigma_s": float(th[0]), "g": float(th[2]),
+                     "log_reduced": coords[0], "atanh_g": coords[1]})
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tail = hist[-max(1, min(average_last, len(hist))):]
-    return {"sigma_s": sum(h["sigma_s"] for h in tail) / len(tail), "sigma_a": sigma_a,
-            "g": sum(h["g"] for h in tail) / len(tail), "history": hist, "seconds": elapsed, "steps": steps,
-            "paths_per_render": n_paths, "mode": mode}
+    reduced = math.exp(sum(h["log_reduced"] for h in tail) / len(tail))
+    g = 0.99 * math.tanh(sum(h["atanh_g"] for h in tail) / len(tail))
+    return {"sigma_s": reduced / (1.0 - g), "sigma_a": sigma_a, "g": g, "reduced_sigma_s": reduced,
+            "history": hist, "seconds": elapsed, "steps": steps, "paths_per_render": n_paths, "mode": mode}
