@@ -13,6 +13,10 @@ ARCH = os.environ.get("DARTS_OFFLOAD_ARCH", "gfx950")
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
+    # contract a * b + c into an fma only within one source expression, so a
+    # path's arithmetic is the same in every kernel that inlines it (the
+    # render, batch and adjoint kernels give the same per-path values)
+    "-ffp-contract=on",
     # keep hand-written and compiler-made code off the packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -469,46 +469,66 @@ __device__ float floor_connect(const KParams &P, const PathState &s, float *dlog
            ir * ir;
 }
 
-// Connection at vertex k and free flight from it (DARTS family, stream 1 of
-// vertex k): medium-event Bernoulli (Eq. (12)), DA-RIS or exponential
-// distance, then the early-exit test at the new vertex.  Returns false when
-// the path has ended.
+// What the free flight from vertex k needs once its medium event has been
+// drawn: the stream-1 words of vertex k that DA-RIS reads (Sobol row, offset,
+// selection uniform) and pc = 1 - e^{-sigma_t d_m}, epc = e^{-sigma_t d_m}.
+struct Pending {
+    uint32_t y, z, w;
+    float pc, epc;
+};
+
+// Connection at vertex k and the medium-event Bernoulli (Eq. (12)) from r1,
+// stream 1 of vertex k (DARTS family).  Returns false when the path has
+// ended (truncation, a flight that leaves the medium, or the early-exit test
+// after a floor vertex); otherwise a medium event is pending and `pd` holds
+// what the flight needs.  A flight that reaches the floor is a surface event
+// (floor scenes): the walk goes on from the floor point, whose direction is
+// drawn from stream 0 of the new vertex, and the connection and the event
+// are drawn again there.
+//
+// Callers draw streams 0 and 1 of a vertex next to each other: the two
+// counters differ only in their last word, which enters the first products
+// in the second round, so four of the forty 32x32 -> 64-bit products of the
+// pair are common to both and computed once.
 template <int OUT, bool FLOOR, class ST>
-__device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &st, float grad_w, double *gacc)
+__device__ bool connect_and_event(const KParams &P, uint64_t p, PathState &s, ST &st, float grad_w, double *gacc,
+                                  Pending &pd, U4 r1)
 {
     const Medium &m = P.med;
-    const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
-    {
-        float dl[3];
-        const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD || OUT == OUT_TANGENT ? dl : nullptr, st);
-        if (c != 0.f) {
-            st.inc(DARTS_ST_CONNECTIONS);
-            s.acc += c;
-            if (OUT == OUT_GRAD || OUT == OUT_TANGENT) {
-                // the tangent mode sums this path's c dlog/dtheta (weight 1)
-                const double cw = OUT == OUT_GRAD ? (double)c * (double)grad_w : (double)c;
-                gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
+    while (true) {
+        {
+            float dl[3];
+            const float c = connect(P, s, u01(r1.x), OUT == OUT_GRAD || OUT == OUT_TANGENT ? dl : nullptr, st);
+            if (c != 0.f) {
+                st.inc(DARTS_ST_CONNECTIONS);
+                s.acc += c;
+                if (OUT == OUT_GRAD || OUT == OUT_TANGENT) {
+                    // the tangent mode sums this path's c dlog/dtheta (weight 1)
+                    const double cw = OUT == OUT_GRAD ? (double)c * (double)grad_w : (double)c;
+                    gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
+                }
             }
         }
-    }
-    const bool to_floor = FLOOR && exits_floor(P.bx, s.x, s.w);
-    if (to_floor) {
-        float dl[3];
-        const float c = floor_connect(P, s, OUT == OUT_GRAD || OUT == OUT_TANGENT ? dl : nullptr, st);
-        if (c != 0.f) {
-            st.inc(DARTS_ST_CONNECTIONS);
-            s.acc += c;
-            if (OUT == OUT_GRAD || OUT == OUT_TANGENT) {
-                const double cw = OUT == OUT_GRAD ? (double)c * (double)grad_w : (double)c;
-                gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
+        const bool to_floor = FLOOR && exits_floor(P.bx, s.x, s.w);
+        if (to_floor) {
+            float dl[3];
+            const float c = floor_connect(P, s, OUT == OUT_GRAD || OUT == OUT_TANGENT ? dl : nullptr, st);
+            if (c != 0.f) {
+                st.inc(DARTS_ST_CONNECTIONS);
+                s.acc += c;
+                if (OUT == OUT_GRAD || OUT == OUT_TANGENT) {
+                    const double cw = OUT == OUT_GRAD ? (double)c * (double)grad_w : (double)c;
+                    gacc[0] += cw * dl[0]; gacc[1] += cw * dl[1]; gacc[2] += cw * dl[2];
+                }
             }
         }
-    }
-    if (s.k == P.max_bounces - 1) { st.inc(DARTS_ST_TRUNCATED); return false; }
-    float epc = 0.f;
-    const float pc = P.box ? one_minus_exp_neg(m.sigma_t * s.dm, epc) : 1.f;
-    const float u5 = u01(r1.y);
-    if (!(u5 < pc)) {
+        if (s.k == P.max_bounces - 1) { st.inc(DARTS_ST_TRUNCATED); return false; }
+        float epc = 0.f;
+        const float pc = P.box ? one_minus_exp_neg(m.sigma_t * s.dm, epc) : 1.f;
+        if (u01(r1.y) < pc) {
+            pd = Pending{r1.y, r1.z, r1.w, pc, epc};
+            return true;
+        }
         if (!to_floor) { st.inc(DARTS_ST_MEDIUM_EXIT); return false; }
         // surface event: probability e^{-sigma_t d_m}, equal to the
         // transmittance, so the throughput is unchanged
@@ -522,18 +542,29 @@ __device__ bool connect_and_fly(const KParams &P, uint64_t p, PathState &s, ST &
         s.C = length(s.xe - s.x);
         st.inc(DARTS_ST_VERTICES);
         if (s.G_hi - s.Le <= s.C) { st.inc(DARTS_ST_EARLY_EXIT); return false; }
-        return true;
+        const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 0u, P.key0, P.key1);
+        r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
+        direction_darts<OUT, FLOOR>(P, s, r0, st);
     }
+}
+
+// Free flight from vertex k given its pending medium event: DA-RIS distance
+// (Section IV-C) or the plain exponential, the move to vertex k + 1 and its
+// early-exit test.  Returns false when the path has ended.
+template <class ST>
+__device__ bool fly(const KParams &P, PathState &s, ST &st, const Pending &pd)
+{
+    const Medium &m = P.med;
     float d, factor;
     if (P.flags & DARTS_RIS_DIST) {
         const V3 de = s.xe - s.x;
-        if (!ris_distance(m, s.C * s.C, dot(s.w, de), s.G_hi - s.Le, pc, epc, r1.y & 31u, r1.z, u01(r1.w), d,
+        if (!ris_distance(m, s.C * s.C, dot(s.w, de), s.G_hi - s.Le, pd.pc, pd.epc, pd.y & 31u, pd.z, u01(pd.w), d,
                           factor)) {
             st.inc(DARTS_ST_RIS_ALL_INVALID);
             return false;
         }
     } else {
-        d = texp_sample(u5, m.ln2_over_sigma_t, 1.f, 0.f);   // plain exponential, given u5 < pc
+        d = texp_sample(u01(pd.y), m.ln2_over_sigma_t, 1.f, 0.f);   // plain exponential, given u < pc
         factor = m.albedo;
     }
     s.x = fma3(s.x, s.w, d);
@@ -674,18 +705,25 @@ __device__ bool fly_vanilla(const KParams &P, uint64_t p, int64_t pixel, PathSta
 // ---------------------------------------------------------------------------
 // Path pool.  A wave works through a range [j_begin, j_end) of path slots.
 // New paths are set up in bulk: when lanes need a path and the wave's queue
-// is empty, all 64 lanes set up the next 64 slots at once (camera ray, entry
-// into the medium, target interval, early-exit test) and the paths that
+// is empty, all 64 lanes set up the next 64 slots at once and the paths that
 // survive set-up are written, compacted, to the wave's queue in LDS.  A lane
 // whose path has ended takes the next queued path at the top of the next
 // iteration (ballot + popcount on the wave-uniform queue head), so set-up
 // runs with full lanes once per 64 paths instead of for the few lanes that
 // happen to need a path, and no lane waits for others before it refills.
-// One loop iteration is then: stream-0 Philox of the current vertex and
-// direction sampling (paths past their first vertex); stream-1 Philox ->
-// connection and free flight.
 //
-// Two slot sources:
+// DARTS family: the bulk set-up also makes vertex 0's connection and draws
+// its medium event, and a queued path waits for its first free flight.  One
+// loop iteration is then: the free flight from vertex k (DA-RIS) and the
+// move to vertex k + 1; stream-0 Philox and direction sampling at k + 1;
+// stream-1 Philox, connection and medium-event draw at k + 1.  A path that
+// leaves the medium ends at the end of an iteration and its lane takes a new
+// path, queued ready for its flight, at the top of the next one: no lane sits
+// out the RIS flight of an iteration because its path left the medium there.
+// Vanilla: set-up only; one iteration is the direction at vertex k (k >= 1),
+// the shadow connection and the free flight.
+//
+// Slot sources:
 //  - SRC_TILE: slot j is repetition j / 64 of cell c0 + (j mod 64) of a tile
 //    of 64 consecutive cells; a bulk set-up covers one repetition of the
 //    whole tile, lane l taking cell c0 + l.  Per-cell sums go to compensated
@@ -704,28 +742,33 @@ enum { LANE_NEED = 0, LANE_FRESH = 1, LANE_ACTIVE = 2, LANE_DONE = 3 };
 enum { SRC_TILE = 0, SRC_IDS = 1, SRC_VTILE = 2 };
 
 // Set-up path queue of one wave in LDS, structure of arrays: field f of
-// entry i at q[f * 64 + i].
+// entry i at q[f * 64 + i].  The DARTS family adds the state after vertex
+// 0's connection and medium event (throughput, vertex index, sum so far,
+// the pending flight; and the derivative bookkeeping for the gradient
+// outputs).
 enum {
     Q_X = 0, Q_W = 3, Q_LE = 6, Q_DM, Q_C, Q_GLO, Q_GHI, Q_EMS, Q_EM, Q_PLO, Q_PHI, Q_CLO, Q_CHI, Q_PIX,
-    Q_FIELDS
+    Q_BASE_FIELDS,
+    Q_BETA = Q_BASE_FIELDS, Q_K, Q_ACC, Q_RY, Q_RZ, Q_RW, Q_PC, Q_EPC,
+    Q_DARTS_FIELDS,
+    Q_LMED = Q_DARTS_FIELDS, Q_DLG, Q_NSURF,
+    Q_GRAD_FIELDS
 };
-constexpr int kQueueFloats = Q_FIELDS * 64;
-
-
-template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, int SRC, bool FLOOR>
-__device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end,
-                                         float *img_hi, float *img_lo, float *acc_hi, float *acc_lo,
-                                         float *acc_m2, float *q, float *hist, Stats<STATS> &st, double *gacc)
+template <int MODE, int OUT>
+constexpr int queue_floats()
 {
-    const int lane = threadIdx.x & 63;
-    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    return 64 * (MODE == 1 ? Q_BASE_FIELDS : OUT == OUT_GRAD || OUT == OUT_TANGENT ? Q_GRAD_FIELDS : Q_DARTS_FIELDS);
+}
 
-    // SRC_TILE: lane l describes tile cell c0 + l (time bin, pixel,
-    // repetition bounds), packed in two registers: my_bf = bin | flags << 29
-    // (bit 29: the cell exists, bit 30: cell < r0, bit 31: cell < r1),
-    // my_xy = px | py << 16.  A bulk set-up of repetition m gives lane l a
-    // path of its own cell.
-    uint32_t my_bf = 0, my_xy = 0;
+// Tile-cell description of lane l (SRC_TILE), packed in two registers:
+// bf = bin | flags << 29 (bit 29: the cell exists, bit 30: cell < r0, bit
+// 31: cell < r1), xy = px | py << 16.
+template <int SRC>
+__device__ __forceinline__ void tile_cell(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end, int lane,
+                                          uint32_t &bf, uint32_t &xy)
+{
+    bf = 0;
+    xy = 0;
     if (SRC == SRC_TILE) {
         const int64_t my_cell = c0 + lane;
         if (j_begin < j_end && my_cell < P.ncells) {
@@ -733,20 +776,105 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
             const int64_t pix = my_cell - b * P.npix;
             const uint32_t y = (uint32_t)(pix / P.width);
             const uint32_t x = (uint32_t)(pix - (int64_t)y * P.width);
-            my_bf = (uint32_t)b | (1u << 29) | ((uint64_t)my_cell < P.r0 ? 1u << 30 : 0u) |
-                    ((uint64_t)my_cell < P.r1 ? 1u << 31 : 0u);
-            my_xy = x | (y << 16);
+            bf = (uint32_t)b | (1u << 29) | ((uint64_t)my_cell < P.r0 ? 1u << 30 : 0u) |
+                 ((uint64_t)my_cell < P.r1 ? 1u << 31 : 0u);
+            xy = x | (y << 16);
         }
     }
+}
+
+// Path id, cell, pixel and (bin, px, py) of slot j; false for an empty slot
+// of a ragged range.
+template <int SRC>
+__device__ __forceinline__ bool pool_slot(const KParams &P, int64_t c0, uint64_t j, uint64_t j_begin, int lane,
+                                          uint32_t my_bf, uint32_t my_xy, uint64_t &pj, int64_t &cj, int64_t &pixj,
+                                          int &bin, int &px, int &py)
+{
+    if (SRC == SRC_TILE) {
+        const uint64_t m = P.q0 + (uint64_t)((my_bf >> 30) & 1u) + (j >> 6);
+        const uint64_t m_hi = P.q1 + (uint64_t)(my_bf >> 31);
+        cj = c0 + lane;
+        pj = (uint64_t)cj + m * (uint64_t)P.ncells;
+        bin = (int)(my_bf & ((1u << 29) - 1u));
+        px = (int)(my_xy & 0xFFFFu);
+        py = (int)(my_xy >> 16);
+        pixj = (int64_t)py * P.width + px;
+        return ((my_bf >> 29) & 1u) && m < m_hi;
+    } else if (SRC == SRC_VTILE) {
+        pj = (uint64_t)c0 + j * (uint64_t)P.npix;
+        cj = c0;
+        pixj = c0;
+        py = (int)(c0 / P.width);
+        px = (int)(c0 - (int64_t)py * P.width);
+        bin = 0;
+        return true;
+    } else {
+        pj = j;
+        cj = c0 + (int64_t)(j - j_begin);
+        if (cj >= P.ncells) cj -= P.ncells;
+        if (P.ncells <= 0xFFFFFFFFll) {
+            const uint32_t c32 = (uint32_t)cj, np = (uint32_t)P.npix;
+            const uint32_t b = c32 / np, pix = c32 - b * np;
+            const uint32_t y = pix / (uint32_t)P.width;
+            bin = (int)b;
+            py = (int)y;
+            px = (int)(pix - y * (uint32_t)P.width);
+            pixj = pix;
+        } else {
+            const int64_t b = cj / P.npix;
+            pixj = cj - b * P.npix;
+            bin = (int)b;
+            py = (int)(pixj / P.width);
+            px = (int)(pixj - (int64_t)py * P.width);
+        }
+        return true;
+    }
+}
+
+// A finished path of the DARTS family: its sum into its cell (LDS slot or
+// global compensated pair), its square into the second moments, or its value
+// into the per-path output; the tangent images receive the path's derivative
+// sums.
+template <int OUT, int SRC, class ST>
+__device__ __forceinline__ void finish_path(const KParams &P, const PathState &s, uint64_t p, int64_t cell, int slot,
+                                            float *img_hi, float *img_lo, float *acc_hi, float *acc_lo, float *acc_m2,
+                                            ST &st, double *gacc)
+{
+    if (s.acc == 0.f) st.inc(DARTS_ST_ZERO_PATHS);
+    if (OUT == OUT_TANGENT) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (gacc[k] != 0.0) unsafeAtomicAdd(P.tangent + (int64_t)k * P.ncells + cell, (float)gacc[k]);
+            gacc[k] = 0.0;
+        }
+    } else if (OUT == OUT_PATHS) {
+        P.path_out[p - P.path_offset] = s.acc;
+    } else if (OUT == OUT_IMAGE && s.acc != 0.f) {
+        if (SRC == SRC_TILE) {
+            compensated_lds_add(acc_hi, acc_lo, slot, s.acc);
+            if (P.m2) atomicAdd(&acc_m2[slot], s.acc * s.acc);
+        } else {
+            add_compensated(img_hi, img_lo, cell, s.acc, 0.f);
+            if (P.m2) unsafeAtomicAdd(P.m2 + cell, s.acc * s.acc);
+        }
+    }
+}
+
+template <bool STATS, int SRC, bool FLOOR>
+__device__ __forceinline__ void run_pool_vanilla(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end,
+                                                 float *img_hi, float *img_lo, float *q, float *hist, Stats<STATS> &st)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    uint32_t my_bf, my_xy;
+    tile_cell<SRC>(P, c0, j_begin, j_end, lane, my_bf, my_xy);
 
     PathState s;
     uint64_t next = j_begin;   // next slot to set up (wave-uniform)
     uint32_t qh = 0, qn = 0;   // queue head and length (wave-uniform)
     int state = j_begin < j_end ? LANE_NEED : LANE_DONE;
     uint64_t p = 0;
-    int slot = 0;
-    int64_t pixel = 0, cell = 0;
-    float grad_w = 0.f;
+    int64_t pixel = 0;
 
     while (true) {
         const uint64_t need = __ballot(state == LANE_NEED);
@@ -760,52 +888,10 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
                 int64_t cj = 0, pixj = 0;
                 if (j < j_end) {
                     int bin = 0, px = 0, py = 0;
-                    bool valid = false;
-                    if (SRC == SRC_TILE) {
-                        const uint64_t m = P.q0 + (uint64_t)((my_bf >> 30) & 1u) + (j >> 6);
-                        const uint64_t m_hi = P.q1 + (uint64_t)(my_bf >> 31);
-                        valid = ((my_bf >> 29) & 1u) && m < m_hi;   // else an empty slot of a ragged range
-                        cj = c0 + lane;
-                        pj = (uint64_t)cj + m * (uint64_t)P.ncells;
-                        bin = (int)(my_bf & ((1u << 29) - 1u));
-                        px = (int)(my_xy & 0xFFFFu);
-                        py = (int)(my_xy >> 16);
-                        pixj = (int64_t)py * P.width + px;
-                    } else if (SRC == SRC_VTILE) {
-                        valid = true;
-                        pj = (uint64_t)c0 + j * (uint64_t)P.npix;
-                        cj = c0;
-                        pixj = c0;
-                        py = (int)(c0 / P.width);
-                        px = (int)(c0 - (int64_t)py * P.width);
-                    } else {
-                        valid = true;
-                        pj = j;
-                        cj = c0 + (int64_t)(j - j_begin);
-                        if (cj >= P.ncells) cj -= P.ncells;
-                        if (P.ncells <= 0xFFFFFFFFll) {
-                            const uint32_t c32 = (uint32_t)cj, np = (uint32_t)P.npix;
-                            const uint32_t b = c32 / np, pix = c32 - b * np;
-                            const uint32_t y = pix / (uint32_t)P.width;
-                            bin = (int)b;
-                            py = (int)y;
-                            px = (int)(pix - y * (uint32_t)P.width);
-                            pixj = pix;
-                        } else {
-                            const int64_t b = cj / P.npix;
-                            pixj = cj - b * P.npix;
-                            bin = (int)b;
-                            py = (int)(pixj / P.width);
-                            px = (int)(pixj - (int64_t)py * P.width);
-                        }
-                    }
-                    if (valid) {
+                    if (pool_slot<SRC>(P, c0, j, j_begin, lane, my_bf, my_xy, pj, cj, pixj, bin, px, py)) {
                         const U4 r0 = philox((uint32_t)pj, (uint32_t)(pj >> 32), 0u, 0u, P.key0, P.key1);
-                        ok = setup_path(P, r0, bin, px, py, t, st, MODE == 1);
-                        if (!ok) {
-                            st.inc(DARTS_ST_ZERO_PATHS);
-                            if (MODE == 0 && OUT == OUT_PATHS) P.path_out[pj - P.path_offset] = 0.f;
-                        }
+                        ok = setup_path(P, r0, bin, px, py, t, st, true);
+                        if (!ok) st.inc(DARTS_ST_ZERO_PATHS);
                     }
                 }
                 const uint64_t okb = __ballot(ok);
@@ -822,8 +908,6 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
                     q[Q_EM * 64 + i] = __int_as_float(t.em);
                     q[Q_PLO * 64 + i] = __uint_as_float((uint32_t)pj);
                     q[Q_PHI * 64 + i] = __uint_as_float((uint32_t)(pj >> 32));
-                    q[Q_CLO * 64 + i] = __uint_as_float((uint32_t)cj);
-                    q[Q_CHI * 64 + i] = __uint_as_float((uint32_t)((uint64_t)cj >> 32));
                     q[Q_PIX * 64 + i] = __uint_as_float((uint32_t)pixj);
                 }
                 qh = 0;
@@ -855,11 +939,7 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
                     s.vpart = 0.f;
                     p = (uint64_t)__float_as_uint(q[Q_PLO * 64 + i]) |
                         ((uint64_t)__float_as_uint(q[Q_PHI * 64 + i]) << 32);
-                    cell = (int64_t)((uint64_t)__float_as_uint(q[Q_CLO * 64 + i]) |
-                                     ((uint64_t)__float_as_uint(q[Q_CHI * 64 + i]) << 32));
                     pixel = (int64_t)__float_as_uint(q[Q_PIX * 64 + i]);
-                    slot = (int)(cell - c0);
-                    if (OUT == OUT_GRAD) grad_w = P.grad_image[cell];
                     state = LANE_FRESH;
                 }
                 const uint32_t took = (uint32_t)__popcll(need);
@@ -870,45 +950,191 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
         }
         if (__ballot(state != LANE_DONE) == 0) break;
         if (state == LANE_FRESH || state == LANE_ACTIVE) {
-            // the emitter position is looked up again in every iteration
-            // rather than carried across it (scalar loads for one emitter)
             s.xe = emitter_pos(P, s.em);
             if (state == LANE_ACTIVE) {
                 const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 0u, P.key0, P.key1);
-                if (MODE == 1) direction_vanilla<FLOOR>(P, s, r0);
-                else direction_darts<OUT, FLOOR>(P, s, r0, st);
+                direction_vanilla<FLOOR>(P, s, r0);
             }
-            bool alive;
-            if (MODE == 1) alive = fly_vanilla<FLOOR, SRC == SRC_VTILE>(P, p, pixel, s, st, hist);
-            else alive = connect_and_fly<OUT, FLOOR>(P, p, s, st, grad_w, gacc);
-            if (alive) {
+            if (fly_vanilla<FLOOR, SRC == SRC_VTILE>(P, p, pixel, s, st, hist)) {
                 state = LANE_ACTIVE;
             } else {
                 state = LANE_NEED;
                 if (s.acc == 0.f) st.inc(DARTS_ST_ZERO_PATHS);
-                if (MODE == 1 && P.m2) vanilla_flush_m2<SRC == SRC_VTILE>(P, s, pixel, hist);
-                if (MODE == 0) {
-                    if (OUT == OUT_TANGENT) {
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            if (gacc[k] != 0.0) unsafeAtomicAdd(P.tangent + (int64_t)k * P.ncells + cell, (float)gacc[k]);
-                            gacc[k] = 0.0;
-                        }
-                    } else if (OUT == OUT_PATHS) {
-                        P.path_out[p - P.path_offset] = s.acc;
-                    } else if (OUT == OUT_IMAGE && s.acc != 0.f) {
-                        if (SRC == SRC_TILE) {
-                            compensated_lds_add(acc_hi, acc_lo, slot, s.acc);
-                            if (P.m2) atomicAdd(&acc_m2[slot], s.acc * s.acc);
-                        } else {
-                            add_compensated(img_hi, img_lo, cell, s.acc, 0.f);
-                            if (P.m2) unsafeAtomicAdd(P.m2 + cell, s.acc * s.acc);
-                        }
-                    }
-                }
+                if (P.m2) vanilla_flush_m2<SRC == SRC_VTILE>(P, s, pixel, hist);
             }
         }
     }
+}
+
+template <int OUT, bool STATS, int SRC, bool FLOOR>
+__device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end,
+                                               float *img_hi, float *img_lo, float *acc_hi, float *acc_lo,
+                                               float *acc_m2, float *q, Stats<STATS> &st, double *gacc)
+{
+    constexpr bool kGrad = OUT == OUT_GRAD || OUT == OUT_TANGENT;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    uint32_t my_bf, my_xy;
+    tile_cell<SRC>(P, c0, j_begin, j_end, lane, my_bf, my_xy);
+
+    PathState s;
+    Pending pd;
+    uint64_t next = j_begin;   // next slot to set up (wave-uniform)
+    uint32_t qh = 0, qn = 0;   // queue head and length (wave-uniform)
+    int state = j_begin < j_end ? LANE_NEED : LANE_DONE;
+    uint64_t p = 0;
+    int slot = 0;
+    int64_t cell = 0;
+    float grad_w = 0.f;
+
+    while (true) {
+        const uint64_t need = __ballot(state == LANE_NEED);
+        if (need) {
+            if (qh == qn && next < j_end) {
+                // bulk set-up of slots next .. next + 63, one per lane: camera
+                // ray (stream 0 of vertex 0), then vertex 0's connection and
+                // medium event (stream 1 of vertex 0)
+                const uint64_t j = next + (uint64_t)lane;
+                bool ok = false;
+                PathState t;
+                Pending tpd;
+                uint64_t pj = 0;
+                int64_t cj = 0, pixj = 0;
+                if (j < j_end) {
+                    int bin = 0, px = 0, py = 0;
+                    if (pool_slot<SRC>(P, c0, j, j_begin, lane, my_bf, my_xy, pj, cj, pixj, bin, px, py)) {
+                        const U4 r0 = philox((uint32_t)pj, (uint32_t)(pj >> 32), 0u, 0u, P.key0, P.key1);
+                        const U4 r1 = philox((uint32_t)pj, (uint32_t)(pj >> 32), 0u, 1u, P.key0, P.key1);
+                        if (setup_path(P, r0, bin, px, py, t, st, false)) {
+                            double g0[3] = {0.0, 0.0, 0.0};
+                            const float gw = OUT == OUT_GRAD ? P.grad_image[cj] : 0.f;
+                            ok = connect_and_event<OUT, FLOOR>(P, pj, t, st, gw, g0, tpd, r1);
+                            if (OUT == OUT_GRAD) { gacc[0] += g0[0]; gacc[1] += g0[1]; gacc[2] += g0[2]; }
+                            if (!ok) {
+                                finish_path<OUT, SRC>(P, t, pj, cj, (int)(cj - c0), img_hi, img_lo, acc_hi, acc_lo,
+                                                      acc_m2, st, g0);
+                            } else if (OUT == OUT_TANGENT) {
+                                // vertex 0's derivative sums go to the tangent images now
+#pragma unroll
+                                for (int k = 0; k < 3; ++k)
+                                    if (g0[k] != 0.0) unsafeAtomicAdd(P.tangent + (int64_t)k * P.ncells + cj, (float)g0[k]);
+                            }
+                        } else {
+                            st.inc(DARTS_ST_ZERO_PATHS);
+                            if (OUT == OUT_PATHS) P.path_out[pj - P.path_offset] = 0.f;
+                        }
+                    }
+                }
+                const uint64_t okb = __ballot(ok);
+                if (ok) {
+                    const int i = __popcll(okb & lanes_below);
+                    q[(Q_X + 0) * 64 + i] = t.x.x; q[(Q_X + 1) * 64 + i] = t.x.y; q[(Q_X + 2) * 64 + i] = t.x.z;
+                    q[(Q_W + 0) * 64 + i] = t.w.x; q[(Q_W + 1) * 64 + i] = t.w.y; q[(Q_W + 2) * 64 + i] = t.w.z;
+                    q[Q_LE * 64 + i] = t.Le;
+                    q[Q_DM * 64 + i] = t.dm;
+                    q[Q_C * 64 + i] = t.C;
+                    q[Q_GLO * 64 + i] = t.G_lo;
+                    q[Q_GHI * 64 + i] = t.G_hi;
+                    q[Q_EMS * 64 + i] = t.em_scale;
+                    q[Q_EM * 64 + i] = __int_as_float(t.em);
+                    q[Q_PLO * 64 + i] = __uint_as_float((uint32_t)pj);
+                    q[Q_PHI * 64 + i] = __uint_as_float((uint32_t)(pj >> 32));
+                    q[Q_CLO * 64 + i] = __uint_as_float((uint32_t)cj);
+                    q[Q_CHI * 64 + i] = __uint_as_float((uint32_t)((uint64_t)cj >> 32));
+                    q[Q_BETA * 64 + i] = t.beta;
+                    q[Q_K * 64 + i] = __int_as_float(t.k);
+                    q[Q_ACC * 64 + i] = t.acc;
+                    q[Q_RY * 64 + i] = __uint_as_float(tpd.y);
+                    q[Q_RZ * 64 + i] = __uint_as_float(tpd.z);
+                    q[Q_RW * 64 + i] = __uint_as_float(tpd.w);
+                    q[Q_PC * 64 + i] = tpd.pc;
+                    q[Q_EPC * 64 + i] = tpd.epc;
+                    if (kGrad) {
+                        q[Q_LMED * 64 + i] = t.L_med;
+                        q[Q_DLG * 64 + i] = t.dlog_g;
+                        q[Q_NSURF * 64 + i] = __int_as_float(t.n_surf);
+                    }
+                }
+                qh = 0;
+                qn = (uint32_t)__popcll(okb);
+                next += 64;
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (qh < qn) {
+                const uint32_t rank = (uint32_t)__popcll(need & lanes_below);
+                if (state == LANE_NEED && rank < qn - qh) {
+                    const int i = (int)(qh + rank);
+                    s.x = V3{q[(Q_X + 0) * 64 + i], q[(Q_X + 1) * 64 + i], q[(Q_X + 2) * 64 + i]};
+                    s.w = V3{q[(Q_W + 0) * 64 + i], q[(Q_W + 1) * 64 + i], q[(Q_W + 2) * 64 + i]};
+                    s.Le = q[Q_LE * 64 + i];
+                    s.dm = q[Q_DM * 64 + i];
+                    s.C = q[Q_C * 64 + i];
+                    s.G_lo = q[Q_GLO * 64 + i];
+                    s.G_hi = q[Q_GHI * 64 + i];
+                    s.em_scale = q[Q_EMS * 64 + i];
+                    s.em = __float_as_int(q[Q_EM * 64 + i]);
+                    s.beta = q[Q_BETA * 64 + i];
+                    s.k = __float_as_int(q[Q_K * 64 + i]);
+                    s.acc = q[Q_ACC * 64 + i];
+                    s.on_floor = false;
+                    if (kGrad) {
+                        s.L_med = q[Q_LMED * 64 + i];
+                        s.dlog_g = q[Q_DLG * 64 + i];
+                        s.n_surf = __float_as_int(q[Q_NSURF * 64 + i]);
+                    } else {
+                        s.L_med = 0.f;
+                        s.dlog_g = 0.f;
+                        s.n_surf = 0;
+                    }
+                    pd.y = __float_as_uint(q[Q_RY * 64 + i]);
+                    pd.z = __float_as_uint(q[Q_RZ * 64 + i]);
+                    pd.w = __float_as_uint(q[Q_RW * 64 + i]);
+                    pd.pc = q[Q_PC * 64 + i];
+                    pd.epc = q[Q_EPC * 64 + i];
+                    p = (uint64_t)__float_as_uint(q[Q_PLO * 64 + i]) |
+                        ((uint64_t)__float_as_uint(q[Q_PHI * 64 + i]) << 32);
+                    cell = (int64_t)((uint64_t)__float_as_uint(q[Q_CLO * 64 + i]) |
+                                     ((uint64_t)__float_as_uint(q[Q_CHI * 64 + i]) << 32));
+                    slot = (int)(cell - c0);
+                    if (OUT == OUT_GRAD) grad_w = P.grad_image[cell];
+                    state = LANE_ACTIVE;
+                }
+                const uint32_t took = (uint32_t)__popcll(need);
+                qh += took < qn - qh ? took : qn - qh;
+            } else if (next >= j_end && state == LANE_NEED) {
+                state = LANE_DONE;
+            }
+        }
+        if (__ballot(state != LANE_DONE) == 0) break;
+        if (state == LANE_ACTIVE) {
+            // the emitter position is looked up again in every iteration
+            // rather than carried across it (scalar loads for one emitter)
+            s.xe = emitter_pos(P, s.em);
+            bool alive = fly(P, s, st, pd);
+            if (alive) {
+                const U4 r0 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 0u, P.key0, P.key1);
+                const U4 r1 = philox((uint32_t)p, (uint32_t)(p >> 32), (uint32_t)s.k, 1u, P.key0, P.key1);
+                direction_darts<OUT, FLOOR>(P, s, r0, st);
+                alive = connect_and_event<OUT, FLOOR>(P, p, s, st, grad_w, gacc, pd, r1);
+            }
+            if (!alive) {
+                state = LANE_NEED;
+                finish_path<OUT, SRC>(P, s, p, cell, slot, img_hi, img_lo, acc_hi, acc_lo, acc_m2, st, gacc);
+            }
+        }
+    }
+}
+
+template <int MODE /*0 DARTS family, 1 vanilla*/, int OUT, bool STATS, int SRC, bool FLOOR>
+__device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t j_begin, uint64_t j_end,
+                                         float *img_hi, float *img_lo, float *acc_hi, float *acc_lo,
+                                         float *acc_m2, float *q, float *hist, Stats<STATS> &st, double *gacc)
+{
+    if constexpr (MODE == 1)
+        run_pool_vanilla<STATS, SRC, FLOOR>(P, c0, j_begin, j_end, img_hi, img_lo, q, hist, st);
+    else
+        run_pool_darts<OUT, STATS, SRC, FLOOR>(P, c0, j_begin, j_end, img_hi, img_lo, acc_hi, acc_lo, acc_m2, q, st,
+                                               gacc);
 }
 
 // Single-scene render kernel: each wave owns a tile of 64 consecutive cells
@@ -932,7 +1158,7 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
     (void)P_arg;
     const KParams &P = *(const KParams *)(CKParams *)__builtin_amdgcn_kernarg_segment_ptr();
     __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
-    __shared__ float qmem[(kBlock / 64) * kQueueFloats];
+    __shared__ float qmem[(kBlock / 64) * queue_floats<MODE, OUT>()];
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
     // the wave's index within the block is the same on all of its lanes: read
@@ -981,7 +1207,7 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
     for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     double gacc[3] = {0.0, 0.0, 0.0};
     run_pool<MODE, OUT, STATS, SRC, FLOOR>(P, c0, j_begin, j_end, P.hi, P.lo, acc_hi + wbase, acc_lo + wbase,
-                                           acc_m2 + wbase, qmem + wave_in_block * kQueueFloats, hist, st, gacc);
+                                           acc_m2 + wbase, qmem + wave_in_block * queue_floats<MODE, OUT>(), hist, st, gacc);
 
     if (SRC == SRC_VTILE && have) {
         // one compensated global atomic pair per bin the wave's paths reached
@@ -1063,7 +1289,7 @@ template <int SRC, int BLOCK, bool FLOOR>
 __global__ __launch_bounds__(BLOCK, DARTS_BATCH_WAVES_PER_SIMD) void batch_kernel(BParams B)
 {
     __shared__ float acc_hi[BLOCK], acc_lo[BLOCK];
-    __shared__ float qmem[(BLOCK / 64) * kQueueFloats];
+    __shared__ float qmem[(BLOCK / 64) * queue_floats<0, OUT_IMAGE>()];
     const int lane = threadIdx.x & 63;
     const int wbase = threadIdx.x & ~63;
     const uint32_t wave_in_block = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1089,7 +1315,7 @@ __global__ __launch_bounds__(BLOCK, DARTS_BATCH_WAVES_PER_SIMD) void batch_kerne
             acc_lo[threadIdx.x] = 0.f;
         }
         run_pool<0, OUT_IMAGE, false, SRC, FLOOR>(P, c0, j_begin, j_end, img_hi, img_lo, acc_hi + wbase, acc_lo + wbase,
-                                                  nullptr, qmem + wave_in_block * kQueueFloats, nullptr, st, nullptr);
+                                                  nullptr, qmem + wave_in_block * queue_floats<0, OUT_IMAGE>(), nullptr, st, nullptr);
         if (SRC == SRC_TILE) {
             const int64_t cell = c0 + lane;
             const float h = acc_hi[threadIdx.x], l = acc_lo[threadIdx.x];
