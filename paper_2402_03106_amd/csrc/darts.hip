@@ -100,11 +100,15 @@ struct KParams {
 
 constexpr int kBlock = 256;
 // Minimum resident waves per SIMD the render kernel is compiled for (caps its
-// VGPR budget at 512 / waves).  At 4 the path loop keeps its 96 VGPRs without
-// spilling; measured on the box frame, 4 to 8 resident waves time within a
-// few per cent of each other (the loop is bound by VALU issue, not latency).
+// VGPR budget at 512 / waves, allocated in granules of 8: 96 at 5 waves).  At
+// 5 the DARTS path loop keeps its 95 VGPRs without spilling, and five
+// 256-thread blocks of 31 KiB of LDS share a CU's 160 KiB; measured on the
+// box frame, 5 resident waves run 6% faster than 4 and 3 run 26% slower (the
+// loop needs several waves per SIMD to hide the latency of its table reads,
+// LDS queue and FP64 chains).  Floor scenes keep 4 (their tile kernel would
+// spill at 5).
 #ifndef DARTS_RENDER_WAVES_PER_SIMD
-#define DARTS_RENDER_WAVES_PER_SIMD 4
+#define DARTS_RENDER_WAVES_PER_SIMD 5
 #endif
 // The batched kernel keeps more registers (it runs the whole pool per work
 // unit from parameters in constant memory) and is faster at 4.
@@ -759,6 +763,20 @@ constexpr int queue_floats()
 {
     return 64 * (MODE == 1 ? Q_BASE_FIELDS : OUT == OUT_GRAD || OUT == OUT_TANGENT ? Q_GRAD_FIELDS : Q_DARTS_FIELDS);
 }
+// LDS per wave of the pool: the queue, and for the DARTS family the tile's
+// cell descriptions (two words per lane)
+template <int MODE, int OUT>
+constexpr int pool_floats()
+{
+    return queue_floats<MODE, OUT>() + (MODE == 1 ? 0 : 2 * 64);
+}
+
+// Number of set bits of the wave mask below this lane (one mbcnt pair, no
+// per-lane mask kept in registers).
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
 
 // Tile-cell description of lane l (SRC_TILE), packed in two registers:
 // bf = bin | flags << 29 (bit 29: the cell exists, bit 30: cell < r0, bit
@@ -972,10 +990,16 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
                                                float *acc_m2, float *q, Stats<STATS> &st, double *gacc)
 {
     constexpr bool kGrad = OUT == OUT_GRAD || OUT == OUT_TANGENT;
-    const int lane = threadIdx.x & 63;
-    const uint64_t lanes_below = (1ull << lane) - 1ull;
-    uint32_t my_bf, my_xy;
-    tile_cell<SRC>(P, c0, j_begin, j_end, lane, my_bf, my_xy);
+    // SRC_TILE: the tile's cell descriptions wait in LDS between bulk
+    // set-ups (two words per lane after the queue) rather than in registers
+    uint32_t *tdesc = (uint32_t *)(q + queue_floats<0, OUT>());
+    if (SRC == SRC_TILE) {
+        const int lane = threadIdx.x & 63;
+        uint32_t bf, xy;
+        tile_cell<SRC>(P, c0, j_begin, j_end, lane, bf, xy);
+        tdesc[lane] = bf;
+        tdesc[64 + lane] = xy;
+    }
 
     PathState s;
     Pending pd;
@@ -983,8 +1007,8 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
     uint32_t qh = 0, qn = 0;   // queue head and length (wave-uniform)
     int state = j_begin < j_end ? LANE_NEED : LANE_DONE;
     uint64_t p = 0;
-    int slot = 0;
-    int64_t cell = 0;
+    int slot = 0;          // SRC_TILE: the path's cell is c0 + slot
+    int64_t cell_ids = 0;  // other sources: the path's cell
     float grad_w = 0.f;
 
     while (true) {
@@ -994,6 +1018,7 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
                 // bulk set-up of slots next .. next + 63, one per lane: camera
                 // ray (stream 0 of vertex 0), then vertex 0's connection and
                 // medium event (stream 1 of vertex 0)
+                const int lane = threadIdx.x & 63;
                 const uint64_t j = next + (uint64_t)lane;
                 bool ok = false;
                 PathState t;
@@ -1002,6 +1027,8 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
                 int64_t cj = 0, pixj = 0;
                 if (j < j_end) {
                     int bin = 0, px = 0, py = 0;
+                    const uint32_t my_bf = SRC == SRC_TILE ? tdesc[lane] : 0u;
+                    const uint32_t my_xy = SRC == SRC_TILE ? tdesc[64 + lane] : 0u;
                     if (pool_slot<SRC>(P, c0, j, j_begin, lane, my_bf, my_xy, pj, cj, pixj, bin, px, py)) {
                         const U4 r0 = philox((uint32_t)pj, (uint32_t)(pj >> 32), 0u, 0u, P.key0, P.key1);
                         const U4 r1 = philox((uint32_t)pj, (uint32_t)(pj >> 32), 0u, 1u, P.key0, P.key1);
@@ -1027,7 +1054,7 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
                 }
                 const uint64_t okb = __ballot(ok);
                 if (ok) {
-                    const int i = __popcll(okb & lanes_below);
+                    const int i = (int)lane_rank(okb);
                     q[(Q_X + 0) * 64 + i] = t.x.x; q[(Q_X + 1) * 64 + i] = t.x.y; q[(Q_X + 2) * 64 + i] = t.x.z;
                     q[(Q_W + 0) * 64 + i] = t.w.x; q[(Q_W + 1) * 64 + i] = t.w.y; q[(Q_W + 2) * 64 + i] = t.w.z;
                     q[Q_LE * 64 + i] = t.Le;
@@ -1040,7 +1067,7 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
                     q[Q_PLO * 64 + i] = __uint_as_float((uint32_t)pj);
                     q[Q_PHI * 64 + i] = __uint_as_float((uint32_t)(pj >> 32));
                     q[Q_CLO * 64 + i] = __uint_as_float((uint32_t)cj);
-                    q[Q_CHI * 64 + i] = __uint_as_float((uint32_t)((uint64_t)cj >> 32));
+                    if (SRC != SRC_TILE) q[Q_CHI * 64 + i] = __uint_as_float((uint32_t)((uint64_t)cj >> 32));
                     q[Q_BETA * 64 + i] = t.beta;
                     q[Q_K * 64 + i] = __int_as_float(t.k);
                     q[Q_ACC * 64 + i] = t.acc;
@@ -1061,7 +1088,7 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
                 __builtin_amdgcn_wave_barrier();
             }
             if (qh < qn) {
-                const uint32_t rank = (uint32_t)__popcll(need & lanes_below);
+                const uint32_t rank = lane_rank(need);
                 if (state == LANE_NEED && rank < qn - qh) {
                     const int i = (int)(qh + rank);
                     s.x = V3{q[(Q_X + 0) * 64 + i], q[(Q_X + 1) * 64 + i], q[(Q_X + 2) * 64 + i]};
@@ -1093,10 +1120,14 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
                     pd.epc = q[Q_EPC * 64 + i];
                     p = (uint64_t)__float_as_uint(q[Q_PLO * 64 + i]) |
                         ((uint64_t)__float_as_uint(q[Q_PHI * 64 + i]) << 32);
-                    cell = (int64_t)((uint64_t)__float_as_uint(q[Q_CLO * 64 + i]) |
-                                     ((uint64_t)__float_as_uint(q[Q_CHI * 64 + i]) << 32));
-                    slot = (int)(cell - c0);
-                    if (OUT == OUT_GRAD) grad_w = P.grad_image[cell];
+                    if (SRC == SRC_TILE) {
+                        slot = (int)(__float_as_uint(q[Q_CLO * 64 + i]) - (uint32_t)c0);
+                        if (OUT == OUT_GRAD) grad_w = P.grad_image[c0 + slot];
+                    } else {
+                        cell_ids = (int64_t)((uint64_t)__float_as_uint(q[Q_CLO * 64 + i]) |
+                                             ((uint64_t)__float_as_uint(q[Q_CHI * 64 + i]) << 32));
+                        if (OUT == OUT_GRAD) grad_w = P.grad_image[cell_ids];
+                    }
                     state = LANE_ACTIVE;
                 }
                 const uint32_t took = (uint32_t)__popcll(need);
@@ -1119,7 +1150,8 @@ __device__ __forceinline__ void run_pool_darts(const KParams &P, int64_t c0, uin
             }
             if (!alive) {
                 state = LANE_NEED;
-                finish_path<OUT, SRC>(P, s, p, cell, slot, img_hi, img_lo, acc_hi, acc_lo, acc_m2, st, gacc);
+                finish_path<OUT, SRC>(P, s, p, SRC == SRC_TILE ? c0 + slot : cell_ids, slot, img_hi, img_lo, acc_hi,
+                                      acc_lo, acc_m2, st, gacc);
             }
         }
     }
@@ -1143,28 +1175,29 @@ __device__ __forceinline__ void run_pool(const KParams &P, int64_t c0, uint64_t 
 // compensated global atomic pair per cell.
 typedef __attribute__((address_space(4))) const KParams CKParams;
 
-// The adjoint keeps three FP64 accumulators per lane; it is compiled for 4
-// waves per SIMD like the image kernels.
-template <int OUT>
+// The adjoint and the derivative images keep three FP64 accumulators per
+// lane and are compiled for 4 waves per SIMD, as are the floor scenes.
+template <int OUT, bool FLOOR>
 constexpr int render_waves_per_simd()
 {
-    return OUT == OUT_GRAD || OUT == OUT_TANGENT ? 4 : DARTS_RENDER_WAVES_PER_SIMD;
+    return OUT == OUT_GRAD || OUT == OUT_TANGENT || FLOOR ? 4 : DARTS_RENDER_WAVES_PER_SIMD;
 }
 
 template <int MODE, int OUT, bool STATS, bool FLOOR, int SRC>
-__global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_kernel(KParams P_arg)
+__global__ __launch_bounds__(kBlock, (render_waves_per_simd<OUT, FLOOR>())) void render_kernel(KParams P_arg)
 {
     // the parameter block, read in place in the kernel-argument segment
     (void)P_arg;
     const KParams &P = *(const KParams *)(CKParams *)__builtin_amdgcn_kernarg_segment_ptr();
     __shared__ float acc_hi[kBlock], acc_lo[kBlock], acc_m2[kBlock];
-    __shared__ float qmem[(kBlock / 64) * queue_floats<MODE, OUT>()];
+    __shared__ float qmem[(kBlock / 64) * pool_floats<MODE, OUT>()];
     const int lane = threadIdx.x & 63;
-    const int wbase = threadIdx.x & ~63;
     // the wave's index within the block is the same on all of its lanes: read
-    // it as a scalar so that the wave's cell and path ranges live in scalar
-    // registers rather than occupying vector registers for the whole loop
+    // it as a scalar so that the wave's cell and path ranges (and its LDS
+    // offsets) live in scalar registers rather than occupying vector
+    // registers for the whole loop
     const uint32_t wave_in_block = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wbase = (int)wave_in_block * 64;
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + wave_in_block;
     const bool have = wave < P.n_waves;
     int64_t c0;
@@ -1207,7 +1240,7 @@ __global__ __launch_bounds__(kBlock, render_waves_per_simd<OUT>()) void render_k
     for (int i = 0; i < DARTS_ST_COUNT; ++i) st.v[i] = 0;
     double gacc[3] = {0.0, 0.0, 0.0};
     run_pool<MODE, OUT, STATS, SRC, FLOOR>(P, c0, j_begin, j_end, P.hi, P.lo, acc_hi + wbase, acc_lo + wbase,
-                                           acc_m2 + wbase, qmem + wave_in_block * queue_floats<MODE, OUT>(), hist, st, gacc);
+                                           acc_m2 + wbase, qmem + wave_in_block * pool_floats<MODE, OUT>(), hist, st, gacc);
 
     if (SRC == SRC_VTILE && have) {
         // one compensated global atomic pair per bin the wave's paths reached
@@ -1289,10 +1322,10 @@ template <int SRC, int BLOCK, bool FLOOR>
 __global__ __launch_bounds__(BLOCK, DARTS_BATCH_WAVES_PER_SIMD) void batch_kernel(BParams B)
 {
     __shared__ float acc_hi[BLOCK], acc_lo[BLOCK];
-    __shared__ float qmem[(BLOCK / 64) * queue_floats<0, OUT_IMAGE>()];
+    __shared__ float qmem[(BLOCK / 64) * pool_floats<0, OUT_IMAGE>()];
     const int lane = threadIdx.x & 63;
-    const int wbase = threadIdx.x & ~63;
     const uint32_t wave_in_block = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wbase = (int)wave_in_block * 64;
     Stats<false> st;
     while (true) {
         uint32_t u = 0;
@@ -1315,7 +1348,7 @@ __global__ __launch_bounds__(BLOCK, DARTS_BATCH_WAVES_PER_SIMD) void batch_kerne
             acc_lo[threadIdx.x] = 0.f;
         }
         run_pool<0, OUT_IMAGE, false, SRC, FLOOR>(P, c0, j_begin, j_end, img_hi, img_lo, acc_hi + wbase, acc_lo + wbase,
-                                                  nullptr, qmem + wave_in_block * queue_floats<0, OUT_IMAGE>(), nullptr, st, nullptr);
+                                                  nullptr, qmem + wave_in_block * pool_floats<0, OUT_IMAGE>(), nullptr, st, nullptr);
         if (SRC == SRC_TILE) {
             const int64_t cell = c0 + lane;
             const float h = acc_hi[threadIdx.x], l = acc_lo[threadIdx.x];

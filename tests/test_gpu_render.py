@@ -520,3 +520,30 @@ def test_tile_and_id_range_decompositions_agree(D, oracle, wname, mode, n):
     assert np.abs(a - b).max() <= 1e-6 * scale
     assert np.abs(ma - mb).max() <= 1e-5 * max(np.abs(ma).max(), 1e-30)
     assert sa == sb
+
+
+@pytest.mark.parametrize("wname,mode,alpha,n", [("box_hg_small", "darts", 0.5, 1 << 16),
+                                                ("infinite_point", "darts", 0.5, 1 << 16),
+                                                ("fog_slab_fit", "darts", 4.0, 1 << 18),
+                                                ("fog_slab_fit", "da_only", 0.5, 1 << 18)])
+def test_path_values_are_bit_identical_across_decompositions(D, wname, mode, alpha, n):
+    """A path's value is a function of its id alone: the tile and the
+    id-range decompositions (different kernels' code around the same path
+    arithmetic, different lanes and orders) give bit-identical per-path
+    values, the floor scene's surface events included.  The library is built
+    with multiply-add contraction only inside one source expression, so no
+    kernel rounds a path differently."""
+    w = getattr(W, wname)()
+    sc, dm = w["scene"], w["dims"]
+    pr = dict(w["params"], n_paths=n, path_offset=4321, alpha=alpha)
+    table = D.build_da_tables(sc["medium"], dm)
+    vals = {}
+    try:
+        for name, reps in [("tiles", -1), ("ids", 1 << 40)]:
+            D.set_ids_max_reps(reps)
+            vals[name] = D.render_paths(sc, pr, mode, table).cpu().numpy()
+    finally:
+        D.set_ids_max_reps(16)
+    a, b = vals["tiles"], vals["ids"]
+    assert np.count_nonzero(a) > n // 50
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))

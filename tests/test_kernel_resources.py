@@ -2,8 +2,9 @@
 gfx950 assembly the build's own compiler flags produce (CPU only: hipcc
 cross-compiles).  The frame's HBM traffic stays near its algorithmic bytes
 only while the DARTS image kernel keeps all path state in registers and LDS:
-no scratch (spill) memory, at most 128 VGPRs and 40 KiB of LDS per 256-thread
-block so that 4 waves (4 blocks of a CU's 160 KiB) fit on a SIMD."""
+no scratch (spill) memory, and it runs at 5 resident waves per SIMD only
+with at most 96 VGPRs (512 per SIMD lane, in granules of 8) and 32 KiB of LDS
+per 256-thread block (5 blocks of a CU's 160 KiB)."""
 import os
 import re
 import shutil
@@ -35,11 +36,11 @@ def kernels(tmp_path_factory):
     return res
 
 
-def test_timed_kernel_has_no_scratch_and_fits_four_waves(kernels):
+def test_timed_kernel_has_no_scratch_and_fits_five_waves(kernels):
     k = kernels[TIMED]
     assert k["private_segment_fixed_size"] == 0, k
-    assert k["next_free_vgpr"] <= 128, k
-    assert k["group_segment_fixed_size"] <= 40 * 1024, k
+    assert k["next_free_vgpr"] <= 96, k
+    assert k["group_segment_fixed_size"] <= 32 * 1024, k
 
 
 def test_image_kernels_without_statistics_have_no_scratch(kernels):
