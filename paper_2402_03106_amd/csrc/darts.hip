@@ -103,10 +103,11 @@ constexpr int kBlock = 256;
 // VGPR budget at 512 / waves, allocated in granules of 8: 96 at 5 waves).  At
 // 5 the DARTS path loop keeps its 95 VGPRs without spilling, and five
 // 256-thread blocks of 31 KiB of LDS share a CU's 160 KiB; measured on the
-// box frame, 5 resident waves run 6% faster than 4 and 3 run 26% slower (the
-// loop needs several waves per SIMD to hide the latency of its table reads,
-// LDS queue and FP64 chains).  Floor scenes keep 4 (their tile kernel would
-// spill at 5).
+// box frame, 5 resident waves run 8% faster than 4, and 3 ran 26% slower
+// than 4 with the previous pool (the loop needs several waves per SIMD to
+// hide the latency of its table reads, LDS queue and FP64 chains).  Floor
+// scenes keep 4: their tile kernel would spill at 5, and the fog layer's
+// id-range kernel times the same at 4 and 5.
 #ifndef DARTS_RENDER_WAVES_PER_SIMD
 #define DARTS_RENDER_WAVES_PER_SIMD 5
 #endif
