@@ -127,11 +127,18 @@ def parse():
 
 
 def kernel_source_hash() -> str:
+    """First 16 hex digits of the sha256 of the kernel sources with their
+    comments and whitespace removed (an edited comment leaves the kernel, and
+    its counter record, as they were)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ["paper_2402_03106_amd/csrc/darts.hip", "paper_2402_03106_amd/csrc/darts_device.hpp"]:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                 # line comments
+        h.update(re.sub(r"\s+", "", text).encode())
     return h.hexdigest()[:16]
 
 

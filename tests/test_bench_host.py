@@ -39,8 +39,11 @@ def test_traffic_follows_the_kernel_source(bench, tmp_path, monkeypatch):
     rec = tmp_path / "profiles" / "render_kernel_box_hg_traffic.json"
     rec.write_text(json.dumps({"kernel_source_hash": bench.kernel_source_hash(), "bytes_per_launch": 1234}))
     assert bench.measured_traffic() == 1234
-    with open(src / "darts.hip", "a") as f:   # any change to the kernel source voids the record
-        f.write("\n")
+    with open(src / "darts.hip", "a") as f:   # an edited comment leaves the record valid
+        f.write("\n// a comment\n")
+    assert bench.measured_traffic() == 1234
+    with open(src / "darts.hip", "a") as f:   # any change to the code voids it
+        f.write("static int extra_symbol = 1;\n")
     assert bench.measured_traffic() is None
     rec.unlink()
     assert bench.measured_traffic() is None
