@@ -511,7 +511,8 @@ def measured_convergence(darts, torch, np, W, gates=(3.0, 6.0, 10.0), width=0.15
             else:
                 r["extrapolated_seconds"] = t_table + (wall - t_table) * frac
             rep[arm] = r
-        tu = rep["uniform"].get("seconds_at_crossing", rep["uniform"].get("extrapolated_seconds"))
+        tu = rep["uniform"].get("seconds_at_crossing", rep["uniform"].get("extrapolated_seconds")) \
+            if "uniform" in rep else None
         for arm, _, _ in arms:
             ta = rep[arm].get("seconds_at_crossing", rep[arm].get("extrapolated_seconds"))
             if tu and ta:
