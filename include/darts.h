@@ -211,7 +211,10 @@ int darts_render_transient(const darts_scene *scene, const darts_params *params,
  * studies: path_value_dev[i] = total contribution of path path_offset + i
  * to the estimate of Eq. (1) in its cell (Sections IV-V, as for
  * darts_render_transient; device float[n_paths], overwritten).  Same kernel
- * as the render. */
+ * as the render.  A path's value is a function of its id, the seed and the
+ * scene: it is bit-identical whatever work decomposition, knob setting or
+ * kernel (single render, batch, adjoint replay) traces it; images differ
+ * between such launches only in the order of their additions. */
 int darts_render_paths(const darts_scene *scene, const darts_params *params,
                        const darts_table *table, float *path_value_dev, void *stream);
 
