@@ -310,11 +310,22 @@ int ref_ris_step_detail(const ref_medium *m, int n_ris, const double x[3], const
     /* medium-event probability p_m (Eq. (12)); candidates follow the
      * truncated exponential on [0, d_m) (Eq. (13)-(14)). */
     double pc = isinf(d_m) ? 1.0 : -expm1(-st * d_m);
-    double dc[8], lphi[8];
+    double dc[8], lphi[8], us[8];
     int valid[8], any = 0;
     double lmax = -INFINITY;
+    /* The candidates' uniforms, taken in increasing order: the selection
+     * below walks the running weight sum in that order (any fixed order
+     * gives the same categorical choice in distribution; this one is the
+     * order of increasing distance). */
+    for (int i = 0; i < n_ris; ++i) us[i] = ref_sobol_u(row, (uint32_t)i, eps_bits);
+    for (int i = 1; i < n_ris; ++i) {
+        double v = us[i];
+        int j = i - 1;
+        while (j >= 0 && us[j] > v) { us[j + 1] = us[j]; --j; }
+        us[j + 1] = v;
+    }
     for (int i = 0; i < n_ris; ++i) {
-        double ui = ref_sobol_u(row, (uint32_t)i, eps_bits);
+        double ui = us[i];
         dc[i] = -log1p(-pc * ui) / st;
         double si = R_hi - dc[i];                 /* upper residual time     */
         double p[3];

@@ -158,7 +158,8 @@ int ref_ris_step(const ref_medium *m, int n_ris, const double x[3], const double
 
 /* The same step with how close its discrete decisions sat to their
  * boundaries, for parity tests of an implementation in lower precision:
- * mask of valid candidates, selected candidate (-1: none), the smallest
+ * mask of valid candidates and selected candidate (-1: none), both indexed
+ * in the order of increasing candidate uniform, the smallest
  * |s_i| or |s_i - r_i| over R_hi (validity), and the smallest distance of a
  * running weight sum from u_sel times the total, over the total (pick). */
 typedef struct { unsigned mask; int sel; double valid_margin, pick_margin; } ref_ris_detail;

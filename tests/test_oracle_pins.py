@@ -683,18 +683,25 @@ def test_darts_vs_uniform_infinite_medium(oracle):
 def test_late_time_diffusion_band(oracle):
     """DA is an approximation of the transport equation (Section IV-B): the
     multiple-scattering transient approaches it at late times.  Sanity band,
-    not parity: total fluence over [6, 10) within 15% of the DA fluence."""
-    w = W.with_(W.infinite_point(), n_paths=1 << 20)
+    not parity: total fluence over [6, 10) within 15% of the DA fluence.
+    With the emitter inside the medium every estimator's variance is
+    unbounded, so the band is checked on a robust estimate: the median over
+    eight disjoint batches of 2^17 paths (median of means)."""
+    w = W.with_(W.infinite_point(), n_paths=1 << 17)
     sc = w["scene"]
     m = sc["medium"]
     D = 1.0 / (3 * (m["sigma_a"] + m["sigma_s"] * (1 - m["g"])))
     phi = lambda s: (4 * PI * D * s) ** -1.5 * math.exp(-1.0 / (4 * D * s) - m["sigma_a"] * s)
     da = integrate.quad(phi, 6.0, 10.0)[0]
     _, cdf = oracle.build_table(m, w["dims"])
-    img, m2, _ = oracle.render(sc, w["params"], "darts", cdf, w["dims"])
-    mean, _ = oracle.estimate(sc, w["params"], "darts", img, m2)
-    ratio = mean.ravel()[38:].sum() / da
-    assert 0.95 < ratio < 1.15, ratio
+    ratios = []
+    for b in range(8):
+        p = dict(w["params"], path_offset=b << 17)
+        img, m2, _ = oracle.render(sc, p, "darts", cdf, w["dims"])
+        mean, _ = oracle.estimate(sc, p, "darts", img, m2)
+        ratios.append(mean.ravel()[38:].sum() / da)
+    ratio = float(np.median(ratios))
+    assert 0.95 < ratio < 1.15, ratios
 
 
 def test_diffusion_coefficient_from_transport(oracle):
@@ -758,7 +765,10 @@ def test_absorption_scaling(oracle, mode):
         assert np.max(np.abs(z)) < 4.0, (wl["name"], np.round(z, 1))
         assert abs(a[ok].sum() - b[ok].sum()) < 4 * math.sqrt((sa[ok] ** 2).sum() + (sb[ok] ** 2).sum())
         (a, sa), (b, sb) = res["shifted_bad"], res["direct_bad"]
-        assert abs(a[ok].sum() / b[ok].sum() - 1) > 0.1, (wl["name"], a[ok].sum() / b[ok].sum())
+        # the planted mistake moves the two sums apart by more than 5 standard
+        # errors (the correct pair agrees within 4)
+        z_bad = abs(a[ok].sum() - b[ok].sum()) / math.sqrt((sa[ok] ** 2).sum() + (sb[ok] ** 2).sum())
+        assert z_bad > 5.0, (wl["name"], z_bad, a[ok].sum() / b[ok].sum())
 
 
 def test_box_sensor_modes_agree(oracle):
