@@ -290,7 +290,7 @@ __device__ bool setup_path(const KParams &P, U4 r, int bin, int px, int py, Path
 struct Conn {
     V3 x, w, xe;      // vertex, ray direction, emitter
     float C;          // |xe - x|
-    float S_lo, S_hi; // length-sum range
+    float lo, hi;     // length-sum range [C + lo, C + hi), as offsets above C
     float scale;      // throughput times emitter intensity / selection probability
     float u;          // uniform for S
     float dm;         // distance along the ray to the medium boundary
@@ -331,19 +331,20 @@ __device__ __forceinline__ float exit_length(V3 x, V3 w, V3 xe, float C, float d
     return S_exit;
 }
 
-// Range of the length sum; false if no control vertex can close the path.
-__device__ __forceinline__ bool connect_range(const KParams &P, const PathState &s, float &S_lo, float &S_hi)
+// Range of the length sum as offsets above C, [C + lo, C + hi); false if no
+// control vertex can close the path.  Kept relative to C so that, when the
+// boundary clips the range to a few ulps of C (a ray aimed almost at an
+// emitter outside the medium), its width is the cancellation-free excess
+// itself rather than (C + excess) - C, whose rounding would move the
+// contribution (proportional to the width) by percents.
+__device__ __forceinline__ bool connect_range(const KParams &P, const PathState &s, float &lo, float &hi)
 {
     if (!(s.C > 0.f)) return false;
-    const float R_lo = s.G_lo - s.Le, R_hi = s.G_hi - s.Le;
-    float S_exit = kInf;
-    if (P.box) {
-        float excess;
-        S_exit = exit_length(s.x, s.w, s.xe, s.C, s.dm, excess);
-    }
-    S_lo = fmaxf(R_lo, s.C);
-    S_hi = fminf(R_hi, S_exit);
-    return S_lo < S_hi;
+    float excess = kInf;
+    if (P.box) exit_length(s.x, s.w, s.xe, s.C, s.dm, excess);
+    lo = fmaxf(s.G_lo - s.Le - s.C, 0.f);
+    hi = fminf(s.G_hi - s.Le - s.C, excess);
+    return lo < hi;
 }
 
 // Contribution of one connection; mu_c and the in-medium lengths t, r_in
@@ -353,18 +354,19 @@ __device__ __forceinline__ float connect_eval(const KParams &P, const Conn &q, f
     const Medium &m = P.med;
     const float C = q.C;
     const float cm = focal_cm(q.x, q.w, q.xe, C);
-    const float W = q.S_hi - q.S_lo;
+    const float W = q.hi - q.lo;
     const bool texp = (P.flags & DARTS_ELL_TEXP) != 0;
-    float S, mass = 0.f;
+    float sc, mass = 0.f;   // S - C
     if (texp) {
         float emass;
         mass = one_minus_exp_neg(m.sigma_t * W, emass);
-        S = q.S_lo + texp_sample(q.u, m.ln2_over_sigma_t, mass, emass);
+        sc = q.lo + texp_sample(q.u, m.ln2_over_sigma_t, mass, emass);
     } else {
-        S = fmaf(q.u, W, q.S_lo);
+        sc = fmaf(q.u, W, q.lo);
     }
+    const float S = C + sc;
     float den, t, r;
-    ellipse(S, C, cm, den, t, r);
+    ellipse(S, C, sc, cm, den, t, r);
     mu_c = 0.f;
     t_out = 0.f;
     r_in_out = 0.f;
@@ -389,7 +391,7 @@ __device__ __forceinline__ float connect_eval(const KParams &P, const Conn &q, f
     const float scale = q.scale * f * ir * rcp(den);
     if (texp) {
         // e^{-sigma_t (t + r_in)} / p(S) = (mass / sigma_t) e^{-sigma_t (S_lo - (r - r_in))}
-        return scale * m.albedo * mass * fast_exp(-m.sigma_t * (q.S_lo - (r - r_in)));
+        return scale * m.albedo * mass * fast_exp(-m.sigma_t * ((C + q.lo) - (r - r_in)));
     }
     return scale * m.sigma_s * W * fast_exp(-m.sigma_t * (t + r_in));
 }
@@ -400,7 +402,7 @@ template <class ST>
 __device__ float connect(const KParams &P, const PathState &s, float u4, float *dlog, ST &st)
 {
     Conn q;
-    if (!connect_range(P, s, q.S_lo, q.S_hi)) return 0.f;
+    if (!connect_range(P, s, q.lo, q.hi)) return 0.f;
     st.inc(DARTS_ST_SAMPLES);   // a full path sample, its length inside the target bin
     q.x = s.x; q.w = s.w; q.xe = s.xe; q.C = s.C; q.scale = s.beta * s.em_scale; q.u = u4; q.dm = s.dm;
     float mu_c, t, r_in;
@@ -1531,7 +1533,7 @@ __global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
     case DARTS_PW_ELLIPSE: {
         float den, t, r;
         const float S = a[0], C = a[1], mu = a[2];
-        ellipse(S, C, C * (1.f - mu), den, t, r);
+        ellipse(S, C, S - C, C * (1.f - mu), den, t, r);
         o[0] = t; o[1] = r; o[2] = a[3] * den / r;
         break;
     }

@@ -281,14 +281,14 @@ __device__ __forceinline__ float da_log_phi_rel(const Medium &m, float r2, float
 
 // ---------------------------------------------------------------------------
 // Elliptical connection geometry (Eq. (18), (21), (22)).  For a length sum S,
-// focal distance C and cm = C (1 - mu) >= 0 (mu the cosine of the direction
-// to the focal axis):  den = S - C mu, t the polar distance, r = S - t the
-// distance from the control vertex to the emitter, written so that nothing
-// cancels when S ~ C or mu ~ 1.
+// focal distance C, the excess sc = S - C (passed as the caller formed it,
+// not recomputed from S, which may have rounded it away) and cm = C (1 - mu) >= 0 (mu the cosine of
+// the direction to the focal axis):  den = S - C mu, t the polar distance,
+// r = S - t the distance from the control vertex to the emitter, written so
+// that nothing cancels when S ~ C or mu ~ 1.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void ellipse(float S, float C, float cm, float &den, float &t, float &r)
+__device__ __forceinline__ void ellipse(float S, float C, float sc, float cm, float &den, float &t, float &r)
 {
-    const float sc = S - C;
     den = sc + cm;
     const float ih = 0.5f * rcp(den);
     t = sc * (S + C) * ih;
@@ -302,11 +302,12 @@ __device__ __forceinline__ void ellipse(float S, float C, float cm, float &den, 
 // outside the residual-time ellipsoid); the normalisation and the selection
 // run in FP64.  On success returns the distance and the factor
 // albedo * mean(w) / w_selected that multiplies the path throughput.
-// b = dot(w, x_e - x), C2 = |x_e - x|^2, epc = 1 - pc = e^{-sigma_t d_m}.
+// b_dot = dot(w, x_e - x), C2 = |x_e - x|^2, epc = 1 - pc = e^{-sigma_t d_m}.
 // ---------------------------------------------------------------------------
 // choice (diagnostics only; null in the kernels): selected candidate in bits
-// 0-7, mask of the valid candidates in bits 8-15.
-__device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b, float R_hi, float pc,
+// 0-7, mask of the valid candidates in bits 8-15, candidates indexed in
+// increasing order of their uniform.
+__device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b_dot, float R_hi, float pc,
                                              float epc, uint32_t row, uint32_t eps, float u_sel,
                                              float &d_out, float &factor, uint32_t *choice = nullptr)
 {
@@ -316,34 +317,42 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b,
     // share one rsq per candidate (1/s_i = rsq^2, s_i^{-3/2} = rsq^3) and
     // cannot underflow for the candidate with the smallest F.
     //
-    // Candidate uniforms: the radical inverse of 8 row + i is the radical
-    // inverse of 8 row plus that of i (the low three bits of 8 row are zero,
-    // so the bit-reversed parts do not overlap), which leaves one add per
-    // candidate on top of the row's offset.
-    constexpr uint32_t kRev3[8] = {0x00000000u, 0x80000000u, 0x40000000u, 0xC0000000u,
-                                   0x20000000u, 0xA0000000u, 0x60000000u, 0xE0000000u};
+    // Candidate uniforms: row `row` of the 32 x 8 Sobol table (the radical
+    // inverses of 8 row .. 8 row + 7) plus the offset eps, on 32-bit fixed
+    // point.  The radical inverse of 8 row + i is that of 8 row (bits 0-28)
+    // plus that of i (the top three bits), so each candidate keeps the low
+    // 29 bits of base = bitrev(8 row) + eps and has (top3(base) + bitrev3(i))
+    // mod 8 as its top three: one candidate per eighth of [0,1).  Taken in
+    // increasing order (the order of the selection below), the candidate in
+    // eighth s has the 24-bit integer k = s 2^21 + b of u = k 2^-24, with
+    // b = (base mod 2^29) >> 8: one exact float add per candidate.
     //
-    // Candidate distance d = -ln(1 - pc u) / sigma_t (Eq. (14)) from the
-    // 24-bit integer k of u = k 2^-24, without cancellation:
-    //  - where v = fl(1 - pc u) >= 1/2, one fma gives v and a second its
-    //    rounding error e = (1 - v) - pc u (1 - v is exact there), and
-    //    ln(1 - pc u) = ln(v + e) = ln v + e (error below 2^-24 of the result,
-    //    also for pc u -> 0, where ln v alone would lose the low bits);
-    //  - otherwise u > 1/2 and 1 - pc u = (1 - u) + u e^{-sigma_t d_m}, a sum
-    //    of non-negative terms with 1 - u exact, rounded once.
+    // Candidate distance d = -ln(1 - pc u) / sigma_t (Eq. (14)) without
+    // cancellation:
+    //  - eighths 0-3 (u < 1/2, so pc u < 1/2): v = fl(1 - pc u) >= 1/2 from
+    //    one fma, its rounding error e = (1 - v) - pc u from a second (1 - v
+    //    is exact there), and ln(1 - pc u) = ln(v + e) = ln v + e (error
+    //    below 2^-24 of the result, also for pc u -> 0, where ln v alone
+    //    would lose the low bits);
+    //  - eighths 4-7 (u >= 1/2): 1 - pc u = (1 - u) + u e^{-sigma_t d_m}, a
+    //    sum of non-negative terms with 1 - u exact, rounded once.
     const uint32_t base = __builtin_bitreverse32(8u * row) + eps;
+    const float b = (float)((base & 0x1FFFFFFFu) >> 8);
     const float pc24 = pc * 0x1p-24f, em24 = epc * 0x1p-24f;
     float dc[8], q[8], F[8];
     float fmin = kInf;
-    const float two_b = 2.f * b;
+    const float two_b = 2.f * b_dot;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const float k = (float)((base + kRev3[i]) >> 8);
-        const float va = fmaf(-pc24, k, 1.f);
-        const float ea = fmaf(-pc24, k, 1.f - va);
-        const float vb = fmaf(k, em24, fmaf(k, -0x1p-24f, 1.f));
-        const bool near = va >= 0.5f;
-        const float L = fmaf(near ? ea : 0.f, kLog2e, log2_hw(near ? va : vb));   // log2(1 - pc u)
+        const float k = b + (float)(i << 21);
+        float L;   // log2(1 - pc u)
+        if (i < 4) {
+            const float va = fmaf(-pc24, k, 1.f);
+            const float ea = fmaf(-pc24, k, 1.f - va);
+            L = fmaf(ea, kLog2e, log2_hw(va));
+        } else {
+            L = log2_hw(fmaf(k, em24, fmaf(k, -0x1p-24f, 1.f)));
+        }
         const float di = -L * m.ln2_over_sigma_t;
         const float si = R_hi - di;
         const float r2 = fmaf(di, di - two_b, C2);
