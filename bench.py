@@ -55,13 +55,13 @@ FLOPS_PER_PATH = 60
 # min/max, selects, conversions, integer and RNG work.
 FLOPS = {
     "setup": 47,            # pixel jitter, camera ray, emitter and target interval, slab entry, C, early exit
-    "connect_test": 21,     # residual range, exit length d_m + |x + w d_m - x_e| (every step)
-    "connect_texp": 102,    # focal term, truncated-exponential S, t(S), p(t), control vertex, exit toward
+    "connect_test": 23,     # residual range above C, exit length d_m + |x + w d_m - x_e| (every step)
+    "connect_texp": 103,    # focal term, truncated-exponential S, t(S), p(t), control vertex, exit toward
                             # the emitter, phase function, transmittance
     "connect_uniform": 86,  # the same with S uniform
     "flight_test": 4,       # medium-event probability
-    "ris": 249,             # 8 candidates (distance without cancellation, residual, validity, log DA
-                            # fluence), FP64 weights and pick, weight factor, b = w.(x_e - x)
+    "ris": 222,             # 8 candidates (distance without cancellation, residual, validity, DA
+                            # fluence exponent), FP64 weights and pick, weight factor, b = w.(x_e - x)
     "exp_distance": 8,      # plain exponential distance
     "move": 18,             # advance, throughput, distance to the emitter, early-exit test
     "direction": 69,        # uniforms, axis to the emitter, frame, phase pdf, MIS weight, boundary distance

@@ -60,8 +60,8 @@ def test_flop_accounting(bench):
     assert steps == 900
     assert f == 375 * 900 + 60 * 100
     F = bench.FLOPS
-    assert F == {"setup": 47, "connect_test": 21, "connect_texp": 102, "connect_uniform": 86, "flight_test": 4,
-                 "ris": 249, "exp_distance": 8, "move": 18, "direction": 69, "direction_eda": 13,
+    assert F == {"setup": 47, "connect_test": 23, "connect_texp": 103, "connect_uniform": 86, "flight_test": 4,
+                 "ris": 222, "exp_distance": 8, "move": 18, "direction": 69, "direction_eda": 13,
                  "eda_branch": 7, "hg_branch": 20, "hg_bin": 8}
     fc = bench.counted_flops(s, "darts")
     fu = bench.counted_flops(s, "uniform")
