@@ -337,7 +337,10 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b_
     //  - eighths 4-7 (u >= 1/2): 1 - pc u = (1 - u) + u e^{-sigma_t d_m}, a
     //    sum of non-negative terms with 1 - u exact, rounded once.
     const uint32_t base = __builtin_bitreverse32(8u * row) + eps;
-    const float b = (float)((base & 0x1FFFFFFFu) >> 8);
+    float b = (float)((base & 0x1FFFFFFFu) >> 8);
+    // b < 2^21 is hidden from the compiler, which would otherwise rewrite
+    // each exact add b + s 2^21 as an integer or plus a conversion
+    asm volatile("" : "+v"(b));
     const float pc24 = pc * 0x1p-24f, em24 = epc * 0x1p-24f;
     float dc[8], q[8], F[8];
     float fmin = kInf;
@@ -368,18 +371,23 @@ __device__ __forceinline__ bool ris_distance(const Medium &m, float C2, float b_
     }
     if (!(fmin < kInf)) return false;
     const float cmin = m.inv4D_log2e * fmin;
+    // running sums of the weights in FP64; the first term starts them (the
+    // weights are >= +0, so this equals 0 + w_0)
     float wv[8];
-    double wsum = 0.0;
+    double cs[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { wv[i] = q[i] * exp2_hw(fmaf(-m.inv4D_log2e, F[i], cmin)); wsum += (double)wv[i]; }
+    for (int i = 0; i < 8; ++i) {
+        wv[i] = q[i] * exp2_hw(fmaf(-m.inv4D_log2e, F[i], cmin));
+        cs[i] = i == 0 ? (double)wv[0] : cs[i - 1] + (double)wv[i];
+    }
+    const double wsum = cs[7];
     const double target = (double)u_sel * wsum;
-    double cum = 0.0;
     float dsel = dc[7], wsel = wv[7];
     uint32_t isel = 7;
     bool found = false;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        cum += (double)wv[i];
+        const double cum = cs[i];
         const bool take = !found && (cum > target);
         dsel = take ? dc[i] : dsel;
         wsel = take ? wv[i] : wsel;
