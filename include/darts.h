@@ -364,7 +364,10 @@ enum {
     DARTS_PW_RIS,         /* in: x[3], w[3], xe[3], R_hi, d_m, row (bits), eps (bits),
                                  u_sel                   out: ok, d, factor, selected
                                                          candidate (-1 if none), mask
-                                                         of valid candidates (medium)  */
+                                                         of valid candidates; both
+                                                         index the candidates in
+                                                         increasing order of their
+                                                         uniform (medium)              */
     DARTS_PW_DIRECTION,   /* in: x[3], xe[3], w_prev[3], S, u[4], use_eda, alpha
                                                          out: w[3], weight, eda_branch,
                                                          table row i n_s + j, cos-bin
