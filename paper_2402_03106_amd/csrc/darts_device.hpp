@@ -460,8 +460,16 @@ __device__ __forceinline__ V3 sample_direction(const Medium &m, const Table &tb,
         k = lo;
         c_lo = row[k];
         c_hi = row[k + 1];
-        mu = fmaf((float)k + u3, tb.cos_step, -1.f);
-        s = hw_sqrt(fmaxf((1.f - mu) * (1.f + mu), 0.f));
+        // cos(theta) = -1 + (k + u3) 2/n_cos; sin(theta) from 1 + cos and
+        // 1 - cos = (n_cos - k - u3) 2/n_cos, formed without going through
+        // cos itself: its FP32 rounding near +-1 (steps of 2^-24) quantises
+        // the angle to the emitter, and at 1 - cos ~ 1e-7 a connection whose
+        // control vertex lands ~1e-4 from the emitter changed by up to 14%
+        const float kf = (float)k;
+        mu = fmaf(kf + u3, tb.cos_step, -1.f);
+        const float opmu = (kf + u3) * tb.cos_step;
+        const float omu = ((tb.fn_cos - kf) - u3) * tb.cos_step;
+        s = hw_sqrt(omu * opmu);
         axis = a;
     } else {
         hg_sample(m.hg, u1, mu, s);

@@ -369,6 +369,65 @@ def test_direction_sampling(D, oracle, n_cos):
     assert all(mg <= 1e-5 for mg in flips), flips
 
 
+def test_direction_near_the_emitter_axis(D, oracle):
+    """EDA directions in the table's last cos-bin, within 4e-9..2e-4 of
+    cos(theta) = 1 about the axis to the emitter (alpha = 0, so every
+    direction comes from the table; u3 = 1 - m 2^-24).  Such rays put the
+    connection's control vertex next to the emitter, where the contribution
+    goes as the inverse squared distance, so the angle matters, not just the
+    vector: |w - a|^2 = 2 (1 - cos theta) from the GPU's FP32 direction
+    (evaluated in FP64) must equal the oracle's to what FP32 rounding of the
+    components of w and a allows (each within 2^-24 of its value, so |w - a|
+    within about 1.04e-7: a relative bar of 4.2e-7 / |w - a|, twice that
+    bound, plus 1e-5).  A cos(theta) rounded to FP32 before sin(theta) is
+    formed moves in steps of 2^-24 and fails this by orders of magnitude."""
+    L = oracle.lib()
+    w = W.box_hg_small()
+    med, dims = w["scene"]["medium"], w["dims"]
+    n_cos = dims["n_cos"]
+    table = D.build_da_tables(med, dims)
+    _, cdf = oracle.build_table(med, dims)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(23)
+    rows = []
+    xe = np.array([0, 0, 1.5])
+    for _ in range(2000):
+        x = rng.uniform(-1, 1, 3)
+        wp = rng.normal(size=3)
+        wp /= np.linalg.norm(wp)
+        Cd = np.linalg.norm(xe - x)
+        S = Cd * (1 + 10 ** rng.uniform(-3, 1))
+        m = int(2 ** rng.uniform(0, 16))
+        u = [0, 0xFFFFFF00, int(rng.integers(0, 2 ** 32)), ((1 << 24) - m) << 8]
+        rows.append([*x, *xe, *wp, S, *[ubits(v) for v in u], 1.0, 0.0])
+    out, inp, ib = run(D, "direction", rows, med, table)
+    mm, dd = C.byref(oracle.medium(med)), C.byref(oracle.dims(dims))
+    cp = np.ascontiguousarray(cdf).ctypes.data_as(C.POINTER(C.c_float))
+    v3 = lambda a: (C.c_double * 3)(*a)
+    rel, bar, n_last = [], [], 0
+    for o, r, rb in zip(out, inp, ib):
+        u = [L.ref_u01(int(v)) for v in rb[10:14]]
+        x, xe_, S = r[0:3], r[3:6], r[9]
+        wp = r[6:9] / np.linalg.norm(r[6:9])
+        wo, wt, eb, k = (C.c_double * 3)(), C.c_double(), C.c_int(), C.c_int()
+        L.ref_sample_direction(mm, dd, cp, 0.0, 1, v3(x), v3(xe_), v3(wp), S, (C.c_double * 4)(*u), wo,
+                               C.byref(wt), C.byref(eb), C.byref(k), 0)
+        assert eb.value == 1 and int(o[4]) == 1
+        if k.value != n_cos - 1 or int(o[6]) != k.value:
+            continue
+        n_last += 1
+        a = (xe_ - x) / np.linalg.norm(xe_ - x)
+        d_o = float(np.sum((np.array(wo[:]) - a) ** 2))
+        d_g = float(np.sum((o[0:3] - a) ** 2))
+        rel.append(abs(d_g - d_o) / d_o)
+        bar.append(4.2e-7 / math.sqrt(d_o) + 1e-5)
+    rel, bar = np.array(rel), np.array(bar)
+    print(f"near-axis EDA directions: {n_last} in the last cos-bin, max relative error of |w - a|^2 "
+          f"{rel.max():.2e}, max error / bar {np.max(rel / bar):.3f}")
+    assert n_last >= 1000
+    assert np.all(rel <= bar)
+
+
 TABLE_CASES = [("box_hg_small", None), ("infinite_point", None), ("box_hg", None),
                ("box_hg", {"n_cs": 16, "n_s": 16, "n_cos": 256, "s_max": 40.0}),
                ("box_hg", {"n_cs": 8, "n_s": 8, "n_cos": 1024, "s_max": 40.0}),

@@ -185,6 +185,30 @@ def test_connection_range_a_few_ulps_above_C(D, oracle):
     assert g.max() <= 1.01 * o.max()
 
 
+@pytest.mark.parametrize("alpha,pid", [(4.0, 3298543548479), (0.5, 3298548220315)])
+def test_table_direction_almost_at_the_emitter(D, oracle, alpha, pid):
+    """Regression: in the infinite medium (seed 0x51) these DARTS paths draw a
+    table direction within 1e-7 of cos(theta) = 1 about the axis to the
+    emitter; the connection's control vertex then lands 1.5e-4 (resp. 1e-3)
+    from the emitter and the path is worth 1e4-1e5 times the mean.  With
+    cos(theta) rounded to FP32 before sin(theta) was formed, the angle moved
+    in steps of 2^-24 and the paths came out 14% (resp. 10%) below the
+    oracle.  The path and the 2^16 around it agree with the oracle path by
+    path."""
+    w = W.infinite_point()
+    k = 2345
+    w = W.with_(w, n_paths=1 << 16, path_offset=pid - k, seed=0x51, alpha=alpha)
+    table, cdf = tables(D, oracle, w)
+    sc, pr, dm = w["scene"], w["params"], w["dims"]
+    g = D.render_paths(sc, pr, "darts", table).cpu().numpy().astype(np.float64)
+    o, _ = oracle.render_paths(sc, pr, "darts", cdf, dm)
+    print(f"path {pid}: gpu {g[k]:.7g} oracle {o[k]:.7g} ({g[k] / o[k]:.5f}); "
+          f"{g[k] / max(o.mean(), 1e-300):.3g} x the chunk's mean")
+    assert abs(g[k] - o[k]) <= 1e-3 * abs(o[k])
+    close = np.abs(g - o) <= 1e-3 * np.abs(o) + 1e-30
+    assert close.mean() >= 0.99
+
+
 @pytest.mark.parametrize("alpha", [0.0, 2.0, 4.0])
 def test_per_path_parity_alpha(D, oracle, alpha):
     """The EDA preference alpha of Eq. (19) away from 0.5: at 0 every
