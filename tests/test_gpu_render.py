@@ -92,6 +92,7 @@ def test_per_path_parity(D, oracle, wname, mode, n):
 TAIL_CASES = [("box_hg", "darts", 0.5, None), ("box_hg", "darts", 4.0, None), ("box_hg", "da_only", 0.5, None),
               ("box_hg", "uniform", 0.5, None), ("box_hg", "darts", 4.0, (3.0, 3.15625)),
               ("box_hg", "darts", 0.5, (10.0, 10.15625)), ("infinite_point", "darts", 0.5, None),
+              ("infinite_point", "darts", 4.0, None),
               ("infinite_point", "uniform", 0.5, None), ("box_point", "darts", 0.5, None),
               ("fog_slab_small", "darts", 0.5, None), ("fog_slab_small", "da_only", 0.5, None),
               ("box_floor_point", "darts", 4.0, None), ("box_hg", "darts", 4.0, "response"),
