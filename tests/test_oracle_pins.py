@@ -491,6 +491,36 @@ def _lookup_rows(oracle, dims, cdf, cases, mutation=0):
     return out
 
 
+def test_table_direction_angle_near_the_axis(oracle):
+    """Inside cos-bin k the EDA sampler takes cos(theta) = -1 + (k + u) 2/n_cos
+    (cos uniform in the bin, Section V-A) about the unit axis to the emitter;
+    in the last bin, at u = 1 - m 2^-24, the closed form is 1 - cos(theta) =
+    m 2^-24 2/n_cos.  The sampled unit vector w must carry that angle
+    through |w - a|^2 / 2 = 1 - cos(theta) to 1e-7 relative, down to
+    1 - cos(theta) = 4e-9 (a cos(theta) rounded to FP32, a frame about another
+    axis than the direction to the emitter, or a bin other than the last,
+    fails)."""
+    L = oracle.lib()
+    med = MEDIA[1]
+    dims = {"n_cs": 4, "n_s": 3, "n_cos": 32, "s_max": 6.0}
+    _, cdf = oracle.build_table(med, dims)
+    m, dd = C.byref(oracle.medium(med)), C.byref(oracle.dims(dims))
+    cp = np.ascontiguousarray(cdf, np.float32).ctypes.data_as(C.POINTER(C.c_float))
+    x, xe = np.array([0.1, -0.2, 0.3]), np.array([0.7, 0.4, 1.9])
+    a = (xe - x) / np.linalg.norm(xe - x)
+    S = 1.5 * np.linalg.norm(xe - x)
+    for mm in [1, 7, 100, 4096, 65536]:
+        u = [0.0, 1.0 - 2.0 ** -24, 0.37, 1.0 - mm * 2.0 ** -24]
+        wo, wt, eb, kb = _vec([0, 0, 0]), C.c_double(), C.c_int(), C.c_int()
+        L.ref_sample_direction(m, dd, cp, 0.0, 1, _vec(x), _vec(xe), _vec([1, 0, 0]), S, (C.c_double * 4)(*u), wo,
+                               C.byref(wt), C.byref(eb), C.byref(kb), 0)
+        assert eb.value == 1 and kb.value == dims["n_cos"] - 1
+        w = np.array(wo[:])
+        want = mm * 2.0 ** -24 * 2.0 / dims["n_cos"]
+        assert abs(np.dot(w, w) - 1) < 1e-15
+        assert abs(np.sum((w - a) ** 2) / 2 - want) <= 1e-7 * want, (mm, np.sum((w - a) ** 2) / 2, want)
+
+
 def test_direction_lookup_lands_in_its_row(oracle):
     """The sampler reads row (floor(n_cs C/S), floor(n_s S/s_max)), clamped
     to the table: (C/S, S) just inside either edge of every cell (and S
