@@ -96,7 +96,9 @@ TAIL_CASES = [("box_hg", "darts", 0.5, None), ("box_hg", "darts", 4.0, None), ("
               ("infinite_point", "uniform", 0.5, None), ("box_point", "darts", 0.5, None),
               ("fog_slab_small", "darts", 0.5, None), ("fog_slab_small", "da_only", 0.5, None),
               ("box_floor_point", "darts", 4.0, None), ("box_hg", "darts", 4.0, "response"),
-              ("box_hg", "uniform", 0.5, "response")]
+              ("box_hg", "uniform", 0.5, "response"), ("fog_slab_small", "darts", 4.0, "response"),
+              ("box_floor_point", "darts", 0.5, "response"), ("infinite_point", "eda_only", 4.0, None),
+              ("box_hg", "darts", 2.0, (6.0, 6.15625))]
 
 
 def _tail_id(c):
