@@ -379,6 +379,20 @@ enum {
     DARTS_PW_EXIT_LENGTH, /* in: x[3], w[3], xe[3], d_m  out: S_exit, S_exit - C as formed
                                                          (largest length sum of a
                                                          connection, Section V-B)      */
+    DARTS_PW_CONNECT,     /* in: x[3], w[3] (unit), xe[3], R_lo, R_hi, d_m, u, texp, box
+                                                         out: contribution, t, r_in,
+                                                         mu_c, reached, range offsets
+                                                         lo, hi above C: one elliptical
+                                                         connection (Section V-B, Eq.
+                                                         (20)-(22)) of a path of
+                                                         throughput 1 at x to an
+                                                         emitter of intensity 1, S
+                                                         truncated-exponential if texp
+                                                         != 0 (else uniform), in the
+                                                         box [-1,1]^3 if box != 0
+                                                         (d_m its distance along w;
+                                                         else an infinite medium)
+                                                         (medium)                      */
     DARTS_PW_COUNT
 };
 int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n,

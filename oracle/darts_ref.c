@@ -726,6 +726,41 @@ static double connect_elliptical(const ref_scene *sc, const ref_params *pr, cons
     return ps->beta * ps->J * m->sigma_s * ref_hg_pdf(dot3(ps->w, wc), m->g) * trans * Ie / (r * r * pt);
 }
 
+/* One connection through the same code, for tests: a scene holding the
+ * medium, the geometry and one emitter of power 4 pi (intensity 1) at xe, a
+ * path of throughput 1 and emitter weight 1 at x heading along w with length
+ * 0 so far and target interval [R_lo, R_hi). */
+double ref_connect(const ref_medium *m, const ref_geometry *g, const double x[3], const double w[3],
+                   const double xe[3], double R_lo, double R_hi, double dm, double u, int texp,
+                   double *t, double *r_in, double *mu_c, int *reached)
+{
+    ref_emitter em;
+    for (int i = 0; i < 3; ++i) em.pos[i] = xe[i];
+    em.start = 0.0;
+    em.power = 4.0 * PI;
+    ref_scene sc;
+    memset(&sc, 0, sizeof sc);
+    sc.medium = *m;
+    sc.geom = *g;
+    sc.emitters = &em;
+    sc.n_emitters = 1;
+    ref_params pr;
+    memset(&pr, 0, sizeof pr);
+    pr.flags = texp ? REF_ELL_TEXP : REF_ELL_UNIFORM;
+    path_state ps;
+    memset(&ps, 0, sizeof ps);
+    for (int i = 0; i < 3; ++i) { ps.x[i] = x[i]; ps.w[i] = w[i]; }
+    ps.beta = 1.0;
+    ps.Le = 0.0;
+    ps.G_lo = R_lo;
+    ps.G_hi = R_hi;
+    ps.em = &em;
+    ps.J = 1.0;
+    ps.dm0 = dm;
+    ps.alive = 1;
+    return connect_elliptical(&sc, &pr, &ps, dm, u, t, r_in, mu_c, reached);
+}
+
 /* Direction leaving the Lambertian floor: cosine-weighted about +z
  * (cos theta = sqrt(u1), phi = 2 pi u2); the BRDF-to-pdf ratio is the albedo. */
 static void floor_direction(double u1, double u2, double w[3])

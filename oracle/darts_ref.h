@@ -147,6 +147,19 @@ int    ref_box_entry(const ref_geometry *g, const double x[3], const double w[3]
                      double *t_in, double *t_out);
 double ref_sobol_u(uint32_t row, uint32_t col, uint32_t eps_bits);
 
+/* One elliptical connection (Section V-B, case I, Eq. (20)-(22)) for tests:
+ * the ray (x, w unit) from a vertex with residual range [R_lo, R_hi) (target
+ * interval minus the length so far) and distance d_m to the boundary along w
+ * (INFINITY with geometry kind 0), an emitter of intensity 1 at xe, a path
+ * throughput of 1, the uniform u for S, texp != 0 for the truncated
+ * exponential S (else uniform).  Returns the contribution (0 when the
+ * length-sum range is empty: *reached = 0) and, as the path tracer does,
+ * the control vertex's polar distance *t, the in-medium length *r_in from it
+ * to the emitter and the phase-function cosine *mu_c. */
+double ref_connect(const ref_medium *m, const ref_geometry *g, const double x[3], const double w[3],
+                   const double xe[3], double R_lo, double R_hi, double dm, double u, int texp,
+                   double *t, double *r_in, double *mu_c, int *reached);
+
 /* One RIS free-flight step (Section IV-C) for a medium event, for tests:
  * inputs x, w (unit), xe, R_hi, d_m; raw uniforms row bits, eps bits, u_sel.
  * Returns 1 and fills d, factor (sigma_s exp(-sigma_t d)/(p_c p(d)) estimate)

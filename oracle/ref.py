@@ -123,6 +123,9 @@ def lib():
         L.ref_da_log_phi.argtypes = [C.POINTER(_Medium), d, d]
         L.ref_box_exit.restype = d
         L.ref_box_exit.argtypes = [C.POINTER(_Geometry), pd, pd]
+        L.ref_connect.restype = d
+        L.ref_connect.argtypes = [C.POINTER(_Medium), C.POINTER(_Geometry), pd, pd, pd, d, d, d, d, C.c_int,
+                                  pd, pd, pd, C.POINTER(C.c_int)]
         L.ref_box_entry.restype = C.c_int
         L.ref_box_entry.argtypes = [C.POINTER(_Geometry), pd, pd, pd, pd]
         L.ref_sobol_u.restype = d

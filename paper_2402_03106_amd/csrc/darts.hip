@@ -1586,6 +1586,34 @@ __global__ __launch_bounds__(kBlock) void pointwise_kernel(PWParams Q)
         o[1] = excess;
         break;
     }
+    case DARTS_PW_CONNECT: {
+        KParams P{};
+        P.med = Q.med;
+        P.box = a[14] != 0.f ? 1 : 0;
+        P.bx = Box{{-1.f, -1.f, -1.f}, {1.f, 1.f, 1.f}};
+        P.flags = a[13] != 0.f ? DARTS_ELL_TEXP : DARTS_ELL_UNIFORM;
+        PathState s{};
+        s.x = V3{a[0], a[1], a[2]};
+        s.w = V3{a[3], a[4], a[5]};
+        s.xe = V3{a[6], a[7], a[8]};
+        s.C = length(s.xe - s.x);
+        s.G_lo = a[9];
+        s.G_hi = a[10];
+        s.Le = 0.f;
+        s.dm = P.box ? a[11] : kInf;
+        s.beta = 1.f;
+        s.em_scale = 1.f;
+        Stats<false> st;
+        float lo = 0.f, hi = 0.f;
+        const bool reached = connect_range(P, s, lo, hi);
+        o[0] = connect(P, s, a[12], nullptr, st);
+        Conn q;
+        q.x = s.x; q.w = s.w; q.xe = s.xe; q.C = s.C; q.lo = lo; q.hi = hi; q.scale = 1.f; q.u = a[12]; q.dm = s.dm;
+        float mu_c = 0.f, t = 0.f, r_in = 0.f;
+        if (reached) connect_eval(P, q, mu_c, t, r_in);
+        o[1] = t; o[2] = r_in; o[3] = mu_c; o[4] = reached ? 1.f : 0.f; o[5] = lo; o[6] = hi;
+        break;
+    }
     case DARTS_PW_MATH: {
         const float x = a[0];
         o[0] = rcp(x); o[1] = rsq(x); o[2] = log2_hw(x); o[3] = exp2_hw(x);
@@ -2533,7 +2561,8 @@ int darts_debug_pointwise(int fn, const float *in_dev, float *out_dev, int64_t n
     Q.in = in_dev;
     Q.out = out_dev;
     Q.med = Medium{};
-    const bool need_med = fn == DARTS_PW_DA_LOGPHI || fn == DARTS_PW_RIS || fn == DARTS_PW_DIRECTION;
+    const bool need_med = fn == DARTS_PW_DA_LOGPHI || fn == DARTS_PW_RIS || fn == DARTS_PW_DIRECTION ||
+                          fn == DARTS_PW_CONNECT;
     if (need_med) {
         if (int rc = check_medium(medium)) return rc;
         Q.med = make_medium(*medium);

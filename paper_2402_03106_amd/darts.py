@@ -37,7 +37,7 @@ ST_COUNT = 16
 PW_IN, PW_OUT = 16, 8
 PW = {name: i for i, name in enumerate(
     ["philox", "hg_pdf", "hg_sample", "da_logphi", "texp", "ellipse", "sobol", "onb", "box_exit",
-     "ris", "direction", "math", "exit_length"])}
+     "ris", "direction", "math", "exit_length", "connect"])}
 
 
 class DartsError(RuntimeError):

@@ -369,6 +369,96 @@ def test_direction_sampling(D, oracle, n_cos):
     assert all(mg <= 1e-5 for mg in flips), flips
 
 
+def test_connection_matches_oracle(D, oracle):
+    """One elliptical connection (Section V-B, Eq. (20)-(22)): range test,
+    sampled length sum, control vertex, phase function, transmittance and
+    Jacobian together, against the oracle on the same float inputs, with
+    truncated-exponential and uniform S, in the box and in an infinite
+    medium.  General rays: whether the length-sum range is empty agrees
+    except within 1e-5 (relative) of its ends, and the contribution agrees to
+    2e-5 plus what FP32 rounding of the range's ends allows: an end set by
+    R_lo or R_hi carries the rounding of C (a few 1e-7 C), i.e. 8e-7 C / W
+    of a range of width W.  Rays aimed within 1e-4..1e-2 rad of an emitter
+    beyond the boundary, with the range [C, S_exit) clipped by it to a few
+    ulps of C and up: the contribution is proportional to S_exit - C, known
+    to FP32 rounding of the direction to the emitter, so the bar adds
+    1e-6 / theta (theta the angle, about 4 eps on |w - a| twice); a width
+    formed as (C + (S_exit - C)) - C would carry half an ulp of C and miss
+    it."""
+    L = oracle.lib()
+    med = W.box_hg()["scene"]["medium"]
+    mm = C.byref(oracle.medium(med))
+    box = oracle.geometry({"kind": 1, "lo": (-1, -1, -1), "hi": (1, 1, 1)})
+    inf = oracle.geometry({"kind": 0})
+    rng = np.random.default_rng(31)
+    rows, kind = [], []
+
+    def exit_dist(x, w):
+        t = np.where(w > 0, (1 - x) / np.where(w > 0, w, 1), np.where(w < 0, (-1 - x) / np.where(w < 0, w, 1), np.inf))
+        return float(t.min())
+
+    for _ in range(3000):
+        in_box = rng.uniform() < 0.7
+        x = rng.uniform(-0.95, 0.95, 3)
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        if in_box:
+            d = rng.normal(size=3)
+            xe = d / np.linalg.norm(d) * rng.uniform(1.8, 3.0)
+        else:
+            xe = rng.uniform(-1, 1, 3)
+        Cd = np.linalg.norm(xe - x)
+        R_lo = Cd * (1 + rng.uniform(-0.3, 0.5))
+        R_hi = R_lo + 10 ** rng.uniform(-3, 0.5)
+        dm = exit_dist(x, w) if in_box else np.inf
+        rows.append([*x, *w, *xe, R_lo, R_hi, dm, rng.uniform(), float(rng.uniform() < 0.5), float(in_box)])
+        kind.append(0)
+    for theta in [1e-4, 3e-4, 1e-3, 3e-3, 1e-2]:
+        for _ in range(200):
+            x = rng.uniform(-0.9, 0.9, 3)
+            d = rng.normal(size=3)
+            xe = d / np.linalg.norm(d) * rng.uniform(1.8, 3.0)
+            a = (xe - x) / np.linalg.norm(xe - x)
+            n = np.cross(a, rng.normal(size=3))
+            w = a * math.cos(theta) + n / np.linalg.norm(n) * math.sin(theta)
+            Cd = np.linalg.norm(xe - x)
+            rows.append([*x, *w, *xe, Cd * 0.9, Cd * 1.5, exit_dist(x, w), rng.uniform(), float(rng.uniform() < 0.5), 1.0])
+            kind.append(1)
+    rows = [[F32(v) for v in r] for r in rows]
+    kind = np.array(kind)
+    out, inp, _ = run(D, "connect", rows, med)
+    v3 = lambda a: (C.c_double * 3)(*a)
+    n_cmp, flips, worst = 0, [], []
+    for o, r, k in zip(out, inp, kind):
+        x, w32, xe = r[0:3], r[3:6], r[6:9]
+        w = w32 / np.linalg.norm(w32)
+        R_lo, R_hi, dm, u, texp, in_box = r[9], r[10], r[11], r[12], int(r[13]), r[14] != 0
+        t, rin, mu, re = C.c_double(), C.c_double(), C.c_double(), C.c_int()
+        c = L.ref_connect(mm, C.byref(box if in_box else inf), v3(x), v3(w), v3(xe), R_lo, R_hi,
+                          dm if in_box else np.inf, u, texp, C.byref(t), C.byref(rin), C.byref(mu), C.byref(re))
+        Cd = float(np.linalg.norm(xe - x))
+        s_exit = L.ref_exit_length(v3(x), v3(w), v3(xe), dm) if in_box else np.inf
+        lo_end, hi_end = max(R_lo, Cd), min(R_hi, s_exit)
+        if int(o[4]) != re.value:
+            flips.append(abs(hi_end - lo_end) / Cd)
+            continue
+        if not re.value:
+            assert o[0] == 0.0
+            continue
+        width = hi_end - lo_end
+        r_set = R_lo > Cd or R_hi < s_exit          # an end of the range set by R_lo or R_hi
+        theta = float(np.linalg.norm(w - (xe - x) / Cd))
+        bar = 2e-5 + (8e-7 * Cd / width if r_set else 0.0) + 1e-6 / theta
+        err = abs(o[0] - c) / c
+        worst.append(err / bar)
+        n_cmp += 1
+        assert err <= bar, (k, r, o[0], c, err, bar)
+    print(f"connections: {n_cmp} compared (max error / bar {max(worst):.3f}), {len(flips)} range flips "
+          f"(margins {sorted(flips)[-3:]})")
+    assert n_cmp >= 2000 and np.sum(kind == 1) >= 1000
+    assert len(flips) <= 5 and all(f <= 1e-5 for f in flips)
+
+
 def test_direction_near_the_emitter_axis(D, oracle):
     """EDA directions in the table's last cos-bin, within 4e-9..2e-4 of
     cos(theta) = 1 about the axis to the emitter (alpha = 0, so every
