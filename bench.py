@@ -129,10 +129,13 @@ def parse():
 def kernel_source_hash() -> str:
     """First 16 hex digits of the sha256 of the kernel sources with their
     comments and whitespace removed (an edited comment leaves the kernel, and
-    its counter record, as they were)."""
+    its counter record, as they were), and of the compiler flags they are
+    built with."""
     import hashlib
     import re
+    from paper_2402_03106_amd import build as B
     h = hashlib.sha256()
+    h.update(" ".join(B.HIPCC_FLAGS).encode())
     for f in ["paper_2402_03106_amd/csrc/darts.hip", "paper_2402_03106_amd/csrc/darts_device.hpp"]:
         with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
             text = fh.read()

@@ -19,6 +19,10 @@ HIPCC_FLAGS = [
     "-ffp-contract=on",
     # keep hand-written and compiler-made code off the packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the machine scheduler's maximum-ILP strategy: the path loops are bound
+    # by VALU issue at their register budget, and this order issues them
+    # about 1% faster (same registers, no scratch in the image kernels)
+    "-mllvm", "-amdgpu-sched-strategy=max-ilp",
 ]
 
 
